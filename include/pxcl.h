@@ -1,0 +1,287 @@
+/*
+ * pxcl.h -- per-event pixel clustering on MI355X behind a non-blocking
+ * acquire / produce boundary.
+ *
+ * The boundary follows the offload pattern of "Bringing heterogeneity to the CMS
+ * software framework" (arXiv:2004.04334):
+ *
+ *  - Sec. 2 (External Worker): a module's work is split into acquire(), which only
+ *    reads its inputs and launches the offloaded work, and produce(), which runs
+ *    after completion.  The continuation is released by a reference-counted holder
+ *    that non-framework threads may signal and that can carry an error.
+ *    -> pxcl_acquire() enqueues all device work and returns without blocking;
+ *       pxcl_done_cb fires exactly once, from a HIP runtime thread, with a status;
+ *       pxcl_produce() hands back the results without blocking.
+ *  - Sec. 4.1 (asynchronous execution): during event processing only asynchronous
+ *    copies, memsets and kernel launches are issued, on the caller's stream; no
+ *    allocation and no synchronisation happens on the event path; completion is
+ *    signalled by a callback queued into the stream after the work.
+ *    -> the library never allocates device or pinned memory: the caller allocates
+ *       workspaces once (e.g. from PyTorch's caching allocator, the counterpart of
+ *       the memory pool of Sec. 4.1) and binds them; device-side errors are
+ *       accumulated in a device error word instead of device asserts.
+ *  - Sec. 4.2 (Product<T>): a data product carries the device, the stream its work
+ *    was queued on and an event marking completion.
+ *    -> pxcl_clusters carries device pointers, the stream and a hipEvent_t.
+ *
+ * The clustering itself is the work the paper's Figure 1 (Sec. 3) names as the
+ * "ClusterProducer" that turns raw detector data into clusters (the GPU variant
+ * goes from raw data straight on): per detector module (160 rows x 416 columns),
+ * the 8-connected components of the fired pixels ("digis"); per component its id
+ * = the smallest linear pixel index  module*66560 + col*160 + row, its charge = the
+ * sum of the digis' ADC counts (uint32 arithmetic, reported as int32) and its size;
+ * components with charge >= charge_cut are kept.  Every step is integer arithmetic
+ * and the result is unique, so results are bit-exact.
+ *
+ * Threading: a context serves any number of threads.  An event (or batch) object
+ * has one owner at a time and at most one piece of work in flight.
+ * All functions return PXCL_OK (0) or a negative PXCL_E_* code unless stated.
+ */
+#ifndef PXCL_H
+#define PXCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- geometry and limits ------------------------------------------------ */
+#define PXCL_ROWS 160u
+#define PXCL_COLS 416u
+#define PXCL_PIXELS_PER_MODULE 66560u        /* ROWS * COLS */
+#define PXCL_MAX_MODULES 32263u              /* so every cluster id fits in int32 */
+#define PXCL_MAX_BATCH 128u                  /* events per pxcl_acquire_batch */
+#define PXCL_MAX_EVENT_DIGIS (1u << 28)      /* capacity limit of one event slot */
+
+/* ---- status codes --------------------------------------------------------- */
+#define PXCL_OK 0
+#define PXCL_E_INVAL (-1)       /* bad argument (null pointer, zero size, bad config) */
+#define PXCL_E_CAPACITY (-2)    /* n digis > the event slot's capacity, k > batch capacity */
+#define PXCL_E_BUSY (-3)        /* the event/batch has work in flight; ctx has bound objects */
+#define PXCL_E_NOT_READY (-4)   /* produce() before completion */
+#define PXCL_E_DUP_PIXEL (-5)   /* async: the same pixel fired twice in one module */
+#define PXCL_E_RANGE (-6)       /* async: module >= n_modules, row >= 160 or col >= 416 */
+#define PXCL_E_ORDER (-7)       /* async: module ids decrease along the input */
+#define PXCL_E_HIP (-8)         /* a HIP runtime call failed */
+#define PXCL_E_INTERNAL (-10)   /* a bounded device-side wait expired (library bug) */
+#define PXCL_E_NOTFOUND (-11)   /* autotune cache file missing or without this key */
+
+/* Asynchronous error bits (pxcl_clusters.err_bits).  When several are set the
+ * status reports, in this order: RANGE, ORDER, DUP.  With RANGE or ORDER set the
+ * DUP bit is not reliable (grouping by module is then undefined). */
+#define PXCL_ERRBIT_RANGE 1u
+#define PXCL_ERRBIT_ORDER 2u
+#define PXCL_ERRBIT_DUP 4u
+#define PXCL_ERRBIT_INTERNAL 8u
+
+/* ---- types -------------------------------------------------------------------- */
+typedef struct pxcl_ctx pxcl_ctx;
+typedef struct pxcl_event pxcl_event;
+typedef struct pxcl_batch pxcl_batch;
+
+typedef struct {
+    uint32_t n_modules;   /* 1 .. PXCL_MAX_MODULES */
+    uint32_t charge_cut;  /* keep a cluster iff its charge >= charge_cut (unsigned compare) */
+} pxcl_config;
+
+#define PXCL_WHERE_HOST 0     /* pinned host memory (hipHostMalloc / torch pin_memory) */
+#define PXCL_WHERE_DEVICE 1   /* device memory on the context's device */
+
+/* Input digis: structure of arrays, grouped by non-decreasing module id, any order
+ * within a module.  All four arrays hold n uint16 values and must stay valid and
+ * unmodified until the done callback has fired. */
+typedef struct {
+    const uint16_t* module;
+    const uint16_t* row;
+    const uint16_t* col;
+    const uint16_t* adc;
+    uint32_t n;
+    int32_t where;        /* PXCL_WHERE_HOST or PXCL_WHERE_DEVICE */
+} pxcl_digis;
+
+/* Completion callback.  Runs on a HIP runtime thread once the event's (or batch's)
+ * device work and status write-back are complete; status = PXCL_OK or an async
+ * error code.  It must not call HIP and must not block: it only releases a waiting
+ * task (e.g. enqueues produce()).  It fires exactly once per successful
+ * pxcl_acquire / pxcl_acquire_batch and never when they return an error. */
+typedef void (*pxcl_done_cb)(void* user, int32_t status);
+
+/* Results of one event (device pointers into the event's workspace).  Valid until
+ * the next acquire on the event or its unbind. */
+typedef struct {
+    int32_t status;            /* PXCL_OK or the async error code */
+    uint32_t err_bits;         /* PXCL_ERRBIT_* */
+    uint32_t n_clusters;       /* kept clusters */
+    uint32_t n_digis;
+    const int32_t* id;         /* [n_clusters] ascending cluster ids */
+    const int32_t* charge;     /* [n_clusters] */
+    const int32_t* size;       /* [n_clusters] */
+    const int32_t* digi_cluster; /* [n_digis] id of the digi's cluster if kept, else -1 */
+    void* stream;              /* hipStream_t the work was queued on */
+    void* done_event;          /* hipEvent_t recorded after the work */
+    int32_t device;
+} pxcl_clusters;
+
+/* ---- context ---------------------------------------------------------------- */
+/* Create a context on `device`.  Queries the device and sets the default kernel
+ * configuration.  Allocates only small host metadata. */
+int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** out);
+/* PXCL_E_BUSY while events or batches are still bound. */
+int pxcl_ctx_destroy(pxcl_ctx* ctx);
+
+/* Clustering kernel shape: workgroup size wg in {64,128,256,512} and modules per
+ * workgroup mpw in {1,2,4} with wg/mpw >= 64.  Affects later acquires only. */
+int pxcl_set_kernel_config(pxcl_ctx* ctx, uint32_t wg, uint32_t mpw);
+int pxcl_get_kernel_config(const pxcl_ctx* ctx, uint32_t* wg, uint32_t* mpw);
+
+/* Per-kernel device timing (hipEvents around each kernel of non-graph launches).
+ * Off by default.  Stats: for each of the 4 kernels (0 segment, 1 cluster,
+ * 2 large-module cluster, 3 compaction) the summed milliseconds and launch count. */
+int pxcl_set_timing(pxcl_ctx* ctx, int enable);
+int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum /*[4]*/, uint64_t* launches /*[4]*/, int reset);
+
+/* ---- event slots ------------------------------------------------------------ */
+/* Device workspace bytes for an event slot of capacity max_digis (inputs staged for
+ * host digis, outputs, temporaries); 0 if max_digis is 0 or too large. */
+size_t pxcl_event_workspace_bytes(const pxcl_ctx* ctx, uint32_t max_digis);
+/* Pinned host bytes for an event slot's status block. */
+size_t pxcl_event_pinned_bytes(const pxcl_ctx* ctx);
+
+/* Bind caller-owned memory to a new event object.  d_ws: device memory on the
+ * context's device, 256-byte aligned, >= pxcl_event_workspace_bytes; h_pinned:
+ * pinned host memory, 64-byte aligned, >= pxcl_event_pinned_bytes.  The library
+ * borrows both until pxcl_event_unbind.  Clears the slot's control words with
+ * hipMemsetAsync on `stream` (a hipStream_t; NULL = the null stream). */
+int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void* h_pinned,
+                    size_t pinned_bytes, uint32_t max_digis, void* stream, pxcl_event** out);
+/* PXCL_E_BUSY while work is in flight. */
+int pxcl_event_unbind(pxcl_event* ev);
+uint32_t pxcl_event_capacity(const pxcl_event* ev);
+
+/* Enqueue the clustering of one event on `stream` (hipStream_t): an async copy of
+ * host digis into the slot (PXCL_WHERE_HOST), the device kernels, and a host
+ * callback.  Returns without waiting for the device.  Synchronous errors
+ * (PXCL_E_INVAL, PXCL_E_CAPACITY, PXCL_E_BUSY, PXCL_E_HIP) mean nothing was queued
+ * and `cb` will not be called; otherwise `cb` (may be NULL) fires exactly once. */
+int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, pxcl_done_cb cb,
+                 void* user);
+/* PXCL_OK once complete, PXCL_E_NOT_READY while in flight, PXCL_E_INVAL if never
+ * acquired.  Non-blocking. */
+int pxcl_query(const pxcl_event* ev);
+/* Non-blocking.  PXCL_E_NOT_READY before completion; otherwise fills *out and
+ * returns the event's status (PXCL_OK or the async error). */
+int pxcl_produce(pxcl_event* ev, pxcl_clusters* out);
+/* Blocking wait for tests and simple callers (hipEventSynchronize on the event's
+ * completion event followed by a wait for the callback); the contrast to the
+ * callback style, never used on the asynchronous paths. */
+int pxcl_wait(pxcl_event* ev);
+
+/* A ready-made callback: `user` points to a pxcl_flag; the callback stores the
+ * status and then increments `fired` (release order). */
+typedef struct {
+    volatile int32_t status;
+    volatile uint32_t fired;
+} pxcl_flag;
+void pxcl_flag_cb(void* user, int32_t status);
+
+/* ---- batches: many events in one launch --------------------------------------- */
+size_t pxcl_batch_workspace_bytes(const pxcl_ctx* ctx, uint32_t max_events);
+size_t pxcl_batch_pinned_bytes(const pxcl_ctx* ctx, uint32_t max_events);
+int pxcl_batch_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void* h_pinned,
+                    size_t pinned_bytes, uint32_t max_events, void* stream, pxcl_batch** out);
+int pxcl_batch_unbind(pxcl_batch* b);
+
+#define PXCL_BATCH_GRAPH 1u   /* replay a captured hipGraph of the per-batch pipeline */
+
+/* Enqueue k events (each bound to its own slot, none in flight) as one batch: one
+ * set of persistent kernels processes every module of every event.  ins[i] are
+ * event evs[i]'s digis.  `cb` fires once per batch with PXCL_OK if every event
+ * succeeded, else the first event error; each event's own status and results come
+ * from pxcl_produce(evs[i]).  Same synchronous-error rules as pxcl_acquire. */
+int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const pxcl_digis* ins,
+                       uint32_t k, void* stream, pxcl_done_cb cb, void* user, uint32_t flags);
+int pxcl_batch_query(const pxcl_batch* b);
+
+/* ---- autotuning ---------------------------------------------------------------- */
+/* Time every kernel configuration (wg x mpw) on the given batch (reps replays each,
+ * blocking: a setup-time call), select the fastest, and, if cache_path is not NULL,
+ * record it in that JSON file under a key of device architecture and shape bucket.
+ * us_out (may be NULL) receives 12 mean times in microseconds, wg-major
+ * (64,128,256,512) x mpw (1,2,4); invalid combinations report -1. */
+int pxcl_autotune(pxcl_ctx* ctx, pxcl_batch* b, pxcl_event* const* evs, const pxcl_digis* ins,
+                  uint32_t k, void* stream, uint32_t reps, const char* cache_path,
+                  float* us_out);
+/* Load a configuration recorded by pxcl_autotune for this device and shape bucket
+ * (mean digis per event).  PXCL_E_NOTFOUND if absent. */
+int pxcl_autotune_load(pxcl_ctx* ctx, const char* cache_path, uint32_t mean_digis);
+
+/* ---- drivers: the asynchronous and the serving forms ------------------------------ */
+typedef struct {
+    double wall_s;               /* timed wall-clock seconds */
+    uint64_t events;             /* events completed */
+    uint64_t digis;              /* digis clustered */
+    double lat_p50_us, lat_p99_us, lat_max_us;
+    double blocked_us_per_event; /* host wall time inside acquire + produce (+ waits) */
+    double cpu_tasks_per_s;      /* synthetic CPU tasks completed per second */
+    uint64_t cpu_tasks;
+    uint32_t errors;             /* events whose status was not PXCL_OK */
+    uint32_t max_inflight;       /* largest number of events in flight at once */
+    uint64_t peak_resident_bytes;/* largest sum of admitted workspace bytes */
+    uint64_t batches;            /* device launches (pxcl_acquire_batch calls) */
+} pxcl_run_stats;
+
+/* Asynchronous form: n_threads host threads, each owning evs[t] and stream
+ * streams[t], keep one event in flight each; while it is in flight the thread runs
+ * synthetic CPU tasks of cpu_task_ns nanoseconds (0 = none) and picks the event's
+ * produce as soon as its callback has fired.  Thread t processes pool entries
+ * t, t+n_threads, ... (mod pool_size), events_per_thread of them.  If blocking is
+ * non-zero the thread instead waits with hipStreamSynchronize (the contrast). */
+int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
+                   uint32_t n_threads, const pxcl_digis* pool, uint32_t pool_size,
+                   uint32_t events_per_thread, uint32_t cpu_task_ns, int blocking,
+                   pxcl_run_stats* out);
+
+/* Serving form: requests arrive as a Poisson process (rate_hz, seeded) and draw
+ * their digis round-robin from `pool`.  A request is admitted when its workspace
+ * fits in the device arena (first-fit sub-allocation of [d_arena, d_arena+arena_bytes),
+ * capped at budget_bytes) and an event object is free; every tick the admitted
+ * requests not yet launched go to the device as one batch on a free batch object
+ * (continuous batching: batches on different streams overlap).  n_cpu_threads
+ * threads run synthetic CPU tasks (cpu_task_ns each) and the produce work.
+ * Latency = arrival -> produce returned.  h_pinned must hold n_slots event status
+ * blocks (pxcl_event_pinned_bytes each).
+ * Verification mode: with d_results and result_offsets given, the produce step also
+ * copies request r's results to d_results + result_offsets[r] (int32 per-digi ids
+ * [n], then ids, charges, sizes [n_clusters each] at +4n, +8n, +12n bytes) and waits
+ * for the copy before the workspace is released; that wait counts as blocked time. */
+typedef struct {
+    double rate_hz;
+    uint32_t n_requests;
+    uint64_t budget_bytes;
+    uint32_t n_slots;            /* event objects (max requests resident at once) */
+    uint32_t max_batch;          /* events per launch (<= each batch's capacity) */
+    uint32_t n_cpu_threads;
+    uint32_t cpu_task_ns;
+    uint32_t flags;              /* PXCL_BATCH_GRAPH */
+    uint64_t seed;
+} pxcl_serve_opts;
+int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void* h_pinned,
+               size_t pinned_bytes, pxcl_batch* const* batches, void* const* streams,
+               uint32_t n_batches, const pxcl_digis* pool, uint32_t pool_size,
+               const pxcl_serve_opts* opts, pxcl_run_stats* out,
+               int32_t* request_status /* [n_requests] or NULL */,
+               uint32_t* request_nclusters /* [n_requests] or NULL */,
+               void* d_results /* device, or NULL */,
+               const uint64_t* result_offsets /* [n_requests] byte offsets, or NULL */);
+
+/* ---- misc --------------------------------------------------------------------- */
+const char* pxcl_strerror(int code);
+/* Library version string. */
+const char* pxcl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PXCL_H */

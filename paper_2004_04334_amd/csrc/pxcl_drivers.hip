@@ -1,0 +1,546 @@
+// Drivers around the acquire/produce boundary: the asynchronous form (host threads
+// keep doing CPU work while their event is on the device), the serving form
+// (Poisson arrivals, admission under a device-memory budget, continuous batching)
+// and the autotuner of the clustering kernel's shape.
+//
+// The asynchronous form is the External Worker pattern of the paper (Sec. 2): the
+// thread that called acquire() does not wait; the completion callback releases the
+// produce() step, which a thread picks up between other tasks.  The serving form's
+// memory handling follows Sec. 4.1: workspaces are carved out of one arena that the
+// caller allocated once (the role of the caching allocator), sized per event rather
+// than for the largest possible event.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <random>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/pxcl.h"
+#include "pxcl_internal.h"
+
+namespace pxcl {
+bool cluster_config_valid(u32 wg, u32 mpw);
+const std::string& ctx_arch(const pxcl_ctx* c);
+int ctx_device(const pxcl_ctx* c);
+}  // namespace pxcl
+
+using namespace pxcl;
+using clk = std::chrono::steady_clock;
+
+namespace {
+
+inline double us_since(clk::time_point t0, clk::time_point t1) {
+    return std::chrono::duration<double, std::micro>(t1 - t0).count();
+}
+
+// Synthetic CPU task: an integer hash loop that runs for `ns` nanoseconds.
+u64 cpu_task(u32 ns, u64 seed) {
+    const auto t0 = clk::now();
+    u64 x = seed | 1u;
+    for (;;) {
+        for (int i = 0; i < 256; ++i) {
+            x ^= x >> 31; x *= 0x7fb5d329728ea185ull; x ^= x >> 27; x *= 0x81dadef4bc2dd44dull;
+        }
+        if (std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - t0).count() >= (long long)ns) break;
+    }
+    return x;
+}
+
+double percentile(std::vector<double>& v, double p) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = p * double(v.size() - 1);
+    const size_t lo = size_t(std::floor(pos)), hi = std::min(v.size() - 1, lo + 1);
+    const double f = pos - double(lo);
+    return v[lo] * (1.0 - f) + v[hi] * f;
+}
+
+std::atomic<u64> g_sink{0};   // keeps the CPU tasks' results alive
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// asynchronous form
+// ---------------------------------------------------------------------------
+extern "C" int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams, uint32_t n_threads,
+                              const pxcl_digis* pool, uint32_t pool_size, uint32_t events_per_thread,
+                              uint32_t cpu_task_ns, int blocking, pxcl_run_stats* out) {
+    if (!ctx || !evs || !streams || !pool || !out || n_threads == 0 || pool_size == 0) return PXCL_E_INVAL;
+    std::vector<std::vector<double>> lat(n_threads);
+    std::vector<double> blocked(n_threads, 0.0);
+    std::vector<u64> tasks(n_threads, 0), digis(n_threads, 0);
+    std::vector<u32> errors(n_threads, 0);
+    std::atomic<int> rc{PXCL_OK};
+    std::atomic<u32> ready{0};
+    std::atomic<bool> go{false};
+    std::atomic<u32> inflight{0}, max_inflight{0};
+    const int dev = ctx_device(ctx);
+
+    auto worker = [&](u32 t) {
+        hipSetDevice(dev);
+        lat[t].reserve(events_per_thread);
+        ready.fetch_add(1);
+        while (!go.load(std::memory_order_acquire)) std::this_thread::yield();
+        for (u32 i = 0; i < events_per_thread && rc.load() == PXCL_OK; ++i) {
+            const pxcl_digis& in = pool[(t + u64(i) * n_threads) % pool_size];
+            pxcl_flag flag;
+            flag.status = 0;
+            flag.fired = 0;
+            const auto t0 = clk::now();
+            int r = pxcl_acquire(evs[t], &in, streams[t], pxcl_flag_cb, &flag);
+            const auto t1 = clk::now();
+            blocked[t] += us_since(t0, t1);
+            if (r != PXCL_OK) { rc.store(r); break; }
+            const u32 now_in = inflight.fetch_add(1) + 1;
+            u32 m = max_inflight.load();
+            while (now_in > m && !max_inflight.compare_exchange_weak(m, now_in)) {}
+            if (blocking) {
+                const auto w0 = clk::now();
+                hipStreamSynchronize(static_cast<hipStream_t>(streams[t]));
+                while (__atomic_load_n(&flag.fired, __ATOMIC_ACQUIRE) == 0) std::this_thread::yield();
+                blocked[t] += us_since(w0, clk::now());
+            } else {
+                while (__atomic_load_n(&flag.fired, __ATOMIC_ACQUIRE) == 0) {
+                    if (cpu_task_ns) {
+                        g_sink.fetch_add(cpu_task(cpu_task_ns, tasks[t] + t), std::memory_order_relaxed);
+                        ++tasks[t];
+                    } else {
+                        std::this_thread::yield();
+                    }
+                }
+            }
+            inflight.fetch_sub(1);
+            pxcl_clusters res;
+            const auto p0 = clk::now();
+            r = pxcl_produce(evs[t], &res);
+            const auto p1 = clk::now();
+            blocked[t] += us_since(p0, p1);
+            if (r != PXCL_OK) ++errors[t];
+            digis[t] += in.n;
+            lat[t].push_back(us_since(t0, p1));
+        }
+    };
+    std::vector<std::thread> th;
+    for (u32 t = 0; t < n_threads; ++t) th.emplace_back(worker, t);
+    while (ready.load() < n_threads) std::this_thread::yield();
+    const auto w0 = clk::now();
+    go.store(true, std::memory_order_release);
+    for (auto& x : th) x.join();
+    const auto w1 = clk::now();
+
+    std::memset(out, 0, sizeof(*out));
+    std::vector<double> all;
+    double bl = 0;
+    for (u32 t = 0; t < n_threads; ++t) {
+        all.insert(all.end(), lat[t].begin(), lat[t].end());
+        bl += blocked[t];
+        out->cpu_tasks += tasks[t];
+        out->digis += digis[t];
+        out->errors += errors[t];
+    }
+    out->wall_s = us_since(w0, w1) * 1e-6;
+    out->events = all.size();
+    out->lat_p50_us = percentile(all, 0.50);
+    out->lat_p99_us = percentile(all, 0.99);
+    out->lat_max_us = all.empty() ? 0 : all.back();
+    out->blocked_us_per_event = all.empty() ? 0 : bl / double(all.size());
+    out->cpu_tasks_per_s = out->wall_s > 0 ? double(out->cpu_tasks) / out->wall_s : 0;
+    out->max_inflight = max_inflight.load();
+    out->batches = all.size();
+    return rc.load();
+}
+
+// ---------------------------------------------------------------------------
+// serving form
+// ---------------------------------------------------------------------------
+namespace pxcl {
+int event_rebind(pxcl_event* ev, void* d_ws, size_t ws_bytes, uint32_t max_digis, hipStream_t s);
+}
+
+namespace {
+
+// First-fit sub-allocator over the arena, 256-byte granules, coalescing on free.
+class Arena {
+  public:
+    Arena(size_t size, size_t budget) : budget_(budget) { free_[0] = size & ~size_t(255); }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = al256(bytes);
+        if (used_ + bytes > budget_) return false;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = al256(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t peak() const { return peak_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0, peak_ = 0, budget_;
+};
+
+struct Request {
+    double arrival_us;
+    u32 pool_idx;
+    u32 slot;
+    size_t off, bytes;
+};
+
+struct ServeState;
+
+struct BatchCtx {
+    ServeState* S;
+    u32 bi;
+    u32 k;
+    u32 req[MAXB];
+};
+
+struct ServeState {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<u32> produce_q;          // requests whose batch completed
+    std::atomic<u32> done{0};
+    std::atomic<u32> batch_free_mask{0};
+};
+
+void serve_batch_done(void* user, int32_t) {
+    BatchCtx* bc = static_cast<BatchCtx*>(user);
+    ServeState* S = bc->S;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        for (u32 i = 0; i < bc->k; ++i) S->produce_q.push_back(bc->req[i]);
+    }
+    S->batch_free_mask.fetch_or(1u << bc->bi, std::memory_order_acq_rel);
+    S->cv.notify_one();
+}
+
+}  // namespace
+
+extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void* h_pinned, size_t pinned_bytes,
+                          pxcl_batch* const* batches, void* const* streams, uint32_t n_batches,
+                          const pxcl_digis* pool, uint32_t pool_size, const pxcl_serve_opts* o, pxcl_run_stats* out,
+                          int32_t* request_status, uint32_t* request_nclusters, void* d_results,
+                          const uint64_t* result_offsets) {
+    if (!ctx || !d_arena || !h_pinned || !batches || !streams || !pool || !o || !out) return PXCL_E_INVAL;
+    if (n_batches == 0 || n_batches > 32 || pool_size == 0 || o->n_slots == 0 || o->max_batch == 0 ||
+        o->max_batch > MAXB || o->n_requests == 0 || !(o->rate_hz > 0))
+        return PXCL_E_INVAL;
+    if (pinned_bytes < size_t(o->n_slots) * pxcl_event_pinned_bytes(ctx)) return PXCL_E_CAPACITY;
+    const int dev = ctx_device(ctx);
+    hipSetDevice(dev);
+    u32 max_n = 0;
+    for (u32 i = 0; i < pool_size; ++i) max_n = std::max(max_n, pool[i].n);
+    const size_t min_ws = pxcl_event_workspace_bytes(ctx, std::max<u32>(max_n, 1));
+    if (min_ws == 0 || min_ws > arena_bytes || min_ws > o->budget_bytes) return PXCL_E_CAPACITY;
+
+    // event objects: bound once to a placeholder range, rebound per request
+    std::vector<pxcl_event*> slot_ev(o->n_slots, nullptr);
+    const size_t hsb = pxcl_event_pinned_bytes(ctx);
+    hipStream_t s0 = static_cast<hipStream_t>(streams[0]);
+    int rc = PXCL_OK;
+    for (u32 i = 0; i < o->n_slots && rc == PXCL_OK; ++i)
+        rc = pxcl_event_bind(ctx, d_arena, arena_bytes, static_cast<u8*>(h_pinned) + i * hsb, hsb, 1, s0,
+                             &slot_ev[i]);
+    if (rc == PXCL_OK && hipStreamSynchronize(s0) != hipSuccess) rc = PXCL_E_HIP;
+    if (rc != PXCL_OK) {
+        for (auto* e : slot_ev) if (e) pxcl_event_unbind(e);
+        return rc;
+    }
+
+    // arrivals
+    std::vector<Request> req(o->n_requests);
+    {
+        std::mt19937_64 rng(o->seed);
+        std::exponential_distribution<double> gap(o->rate_hz * 1e-6);
+        double t = 0;
+        for (u32 i = 0; i < o->n_requests; ++i) {
+            t += gap(rng);
+            req[i].arrival_us = t;
+            req[i].pool_idx = i % pool_size;
+        }
+    }
+
+    Arena arena(arena_bytes, std::min<size_t>(o->budget_bytes, arena_bytes));
+    std::mutex amu;                       // arena + free slots
+    std::vector<u32> free_slots;
+    for (u32 i = 0; i < o->n_slots; ++i) free_slots.push_back(o->n_slots - 1 - i);
+    ServeState S;
+    S.batch_free_mask.store((n_batches >= 32 ? 0xFFFFFFFFu : ((1u << n_batches) - 1u)));
+    std::vector<BatchCtx> bctx(n_batches);
+    for (u32 b = 0; b < n_batches; ++b) { bctx[b].S = &S; bctx[b].bi = b; bctx[b].k = 0; }
+    std::vector<double> lat(o->n_requests, 0.0);
+    std::atomic<u64> blocked_ns{0}, tasks{0}, batches_launched{0};
+    std::atomic<u32> errors{0}, inflight{0}, max_inflight{0};
+    std::atomic<bool> stop{false};
+    std::atomic<int> err_rc{PXCL_OK};
+    const auto t0 = clk::now();
+
+    // CPU threads: produce first, else a synthetic task
+    auto cpu_worker = [&](u32 t) {
+        hipSetDevice(dev);
+        u64 local_tasks = 0;
+        for (;;) {
+            u32 r = 0xFFFFFFFFu;
+            {
+                std::unique_lock<std::mutex> g(S.mu);
+                if (!S.produce_q.empty()) { r = S.produce_q.front(); S.produce_q.pop_front(); }
+                else if (stop.load()) break;
+                else if (!o->cpu_task_ns) S.cv.wait_for(g, std::chrono::microseconds(50));
+            }
+            if (r != 0xFFFFFFFFu) {
+                Request& q = req[r];
+                pxcl_clusters res;
+                const auto p0 = clk::now();
+                const int st = pxcl_produce(slot_ev[q.slot], &res);
+                const auto p1 = clk::now();
+                blocked_ns.fetch_add(u64(std::chrono::duration_cast<std::chrono::nanoseconds>(p1 - p0).count()));
+                lat[r] = us_since(t0, p1) - q.arrival_us;
+                if (d_results && result_offsets) {   // verification mode: copy out, then release
+                    u8* dst = static_cast<u8*>(d_results) + result_offsets[r];
+                    const size_t nb = size_t(res.n_digis) * 4, cb = size_t(res.n_clusters) * 4;
+                    hipStream_t rs = static_cast<hipStream_t>(res.stream);
+                    const auto c0 = clk::now();
+                    hipError_t ce = hipSuccess;
+                    if (nb) ce = hipMemcpyAsync(dst, res.digi_cluster, nb, hipMemcpyDeviceToDevice, rs);
+                    if (cb && ce == hipSuccess) ce = hipMemcpyAsync(dst + nb, res.id, cb, hipMemcpyDeviceToDevice, rs);
+                    if (cb && ce == hipSuccess) ce = hipMemcpyAsync(dst + 2 * nb, res.charge, cb, hipMemcpyDeviceToDevice, rs);
+                    if (cb && ce == hipSuccess) ce = hipMemcpyAsync(dst + 3 * nb, res.size, cb, hipMemcpyDeviceToDevice, rs);
+                    if (ce == hipSuccess) ce = hipStreamSynchronize(rs);
+                    if (ce != hipSuccess) err_rc.store(PXCL_E_HIP);
+                    blocked_ns.fetch_add(u64(std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - c0).count()));
+                }
+                if (st != PXCL_OK) errors.fetch_add(1);
+                if (request_status) request_status[r] = st;
+                if (request_nclusters) request_nclusters[r] = res.n_clusters;
+                {
+                    std::lock_guard<std::mutex> g(amu);
+                    arena.release(q.off, q.bytes);
+                    free_slots.push_back(q.slot);
+                }
+                inflight.fetch_sub(1);
+                S.done.fetch_add(1, std::memory_order_acq_rel);
+            } else if (o->cpu_task_ns) {
+                g_sink.fetch_add(cpu_task(o->cpu_task_ns, local_tasks + t), std::memory_order_relaxed);
+                ++local_tasks;
+            }
+        }
+        tasks.fetch_add(local_tasks);
+    };
+    const u32 ncpu = std::max<u32>(1, o->n_cpu_threads);
+    std::vector<std::thread> th;
+    for (u32 t = 0; t < ncpu; ++t) th.emplace_back(cpu_worker, t);
+
+    // dispatcher: arrivals -> admission -> batches
+    std::deque<u32> arrived, admitted;
+    u32 next_arrival = 0;
+    std::vector<pxcl_event*> bev(MAXB);
+    std::vector<pxcl_digis> bin(MAXB);
+    while (S.done.load(std::memory_order_acquire) < o->n_requests && err_rc.load() == PXCL_OK) {
+        const double now = us_since(t0, clk::now());
+        while (next_arrival < o->n_requests && req[next_arrival].arrival_us <= now) arrived.push_back(next_arrival++);
+        {
+            std::lock_guard<std::mutex> g(amu);
+            while (!arrived.empty() && !free_slots.empty()) {
+                Request& q = req[arrived.front()];
+                q.bytes = pxcl_event_workspace_bytes(ctx, std::max<u32>(pool[q.pool_idx].n, 1));
+                if (!arena.alloc(q.bytes, &q.off)) break;
+                q.slot = free_slots.back();
+                free_slots.pop_back();
+                admitted.push_back(arrived.front());
+                arrived.pop_front();
+            }
+        }
+        u32 mask = S.batch_free_mask.load(std::memory_order_acquire);
+        if (!admitted.empty() && mask) {
+            const u32 b = __builtin_ctz(mask);
+            S.batch_free_mask.fetch_and(~(1u << b), std::memory_order_acq_rel);
+            BatchCtx& bc = bctx[b];
+            u32 k = 0;
+            hipStream_t s = static_cast<hipStream_t>(streams[b]);
+            const auto a0 = clk::now();
+            while (!admitted.empty() && k < o->max_batch) {
+                const u32 r = admitted.front();
+                admitted.pop_front();
+                Request& q = req[r];
+                pxcl::event_rebind(slot_ev[q.slot], static_cast<u8*>(d_arena) + q.off, q.bytes,
+                                   std::max<u32>(pool[q.pool_idx].n, 1), s);
+                bev[k] = slot_ev[q.slot];
+                bin[k] = pool[q.pool_idx];
+                bc.req[k] = r;
+                ++k;
+            }
+            bc.k = k;
+            const int r = pxcl_acquire_batch(batches[b], bev.data(), bin.data(), k, s, serve_batch_done, &bc,
+                                             o->flags);
+            blocked_ns.fetch_add(u64(std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - a0).count()));
+            if (r != PXCL_OK) { err_rc.store(r); break; }
+            batches_launched.fetch_add(1);
+            const u32 now_in = inflight.fetch_add(k) + k;
+            u32 m = max_inflight.load();
+            while (now_in > m && !max_inflight.compare_exchange_weak(m, now_in)) {}
+        } else {
+            std::this_thread::sleep_for(std::chrono::microseconds(2));
+        }
+    }
+    stop.store(true);
+    S.cv.notify_all();
+    for (auto& x : th) x.join();
+    const auto t1 = clk::now();
+    for (u32 b = 0; b < n_batches; ++b) hipStreamSynchronize(static_cast<hipStream_t>(streams[b]));
+    for (auto* e : slot_ev) pxcl_event_unbind(e);
+
+    std::memset(out, 0, sizeof(*out));
+    std::vector<double> l(lat);
+    u64 dg = 0;
+    for (u32 i = 0; i < o->n_requests; ++i) dg += pool[req[i].pool_idx].n;
+    out->wall_s = us_since(t0, t1) * 1e-6;
+    out->events = o->n_requests;
+    out->digis = dg;
+    out->lat_p50_us = percentile(l, 0.50);
+    out->lat_p99_us = percentile(l, 0.99);
+    out->lat_max_us = l.empty() ? 0 : l.back();
+    out->blocked_us_per_event = double(blocked_ns.load()) * 1e-3 / double(o->n_requests);
+    out->cpu_tasks = tasks.load();
+    out->cpu_tasks_per_s = out->wall_s > 0 ? double(out->cpu_tasks) / out->wall_s : 0;
+    out->errors = errors.load();
+    out->max_inflight = max_inflight.load();
+    out->peak_resident_bytes = arena.peak();
+    out->batches = batches_launched.load();
+    return err_rc.load();
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+namespace {
+const u32 kWG[4] = {64, 128, 256, 512};
+const u32 kMPW[3] = {1, 2, 4};
+
+std::string cache_key(pxcl_ctx* ctx, u32 mean_digis) {
+    u32 bucket = 0;
+    while ((2u << bucket) <= mean_digis && bucket < 31) ++bucket;
+    return ctx_arch(ctx) + "|" + std::to_string(bucket);
+}
+
+// The cache is a flat JSON object {"<arch>|<log2 bucket>": [wg, mpw], ...}.
+std::map<std::string, std::pair<u32, u32>> read_cache(const char* path) {
+    std::map<std::string, std::pair<u32, u32>> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t p = 0;
+    for (;;) {
+        const size_t q0 = s.find('"', p);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = s.find('"', q0 + 1);
+        const size_t b0 = s.find('[', q1);
+        const size_t b1 = s.find(']', b0);
+        if (q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
+        unsigned wg = 0, mpw = 0;
+        if (std::sscanf(s.substr(b0 + 1, b1 - b0 - 1).c_str(), "%u , %u", &wg, &mpw) == 2)
+            m[s.substr(q0 + 1, q1 - q0 - 1)] = {wg, mpw};
+        p = b1 + 1;
+    }
+    return m;
+}
+}  // namespace
+
+extern "C" int pxcl_autotune(pxcl_ctx* ctx, pxcl_batch* b, pxcl_event* const* evs, const pxcl_digis* ins, uint32_t k,
+                             void* stream, uint32_t reps, const char* cache_path, float* us_out) {
+    if (!ctx || !b || !evs || !ins || k == 0 || reps == 0) return PXCL_E_INVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipSetDevice(ctx_device(ctx));
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PXCL_E_HIP;
+    u32 best_wg = 0, best_mpw = 0;
+    float best = 0;
+    int rc = PXCL_OK;
+    u64 digis = 0;
+    for (u32 i = 0; i < k; ++i) digis += ins[i].n;
+    for (u32 a = 0; a < 4 && rc == PXCL_OK; ++a)
+        for (u32 c = 0; c < 3 && rc == PXCL_OK; ++c) {
+            const u32 wg = kWG[a], mpw = kMPW[c];
+            float* slot = us_out ? &us_out[a * 3 + c] : nullptr;
+            if (!cluster_config_valid(wg, mpw)) { if (slot) *slot = -1.f; continue; }
+            pxcl_set_kernel_config(ctx, wg, mpw);
+            double tot = 0;
+            for (u32 r = 0; r <= reps && rc == PXCL_OK; ++r) {   // r == 0 warms up
+                hipEventRecord(e0, s);
+                rc = pxcl_acquire_batch(b, evs, ins, k, s, nullptr, nullptr, 0);
+                hipEventRecord(e1, s);
+                if (rc != PXCL_OK) break;
+                hipEventSynchronize(e1);
+                while (pxcl_batch_query(b) == PXCL_E_NOT_READY) std::this_thread::yield();
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (r) tot += ms;
+            }
+            const float us = float(tot * 1e3 / reps);
+            if (slot) *slot = us;
+            if (best_wg == 0 || us < best) { best = us; best_wg = wg; best_mpw = mpw; }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != PXCL_OK) return rc;
+    pxcl_set_kernel_config(ctx, best_wg, best_mpw);
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        m[cache_key(ctx, u32(digis / k))] = {best_wg, best_mpw};
+        std::ofstream f(cache_path);
+        if (!f) return PXCL_E_INVAL;
+        f << "{\n";
+        size_t i = 0;
+        for (auto& kv : m)
+            f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+              << (++i < m.size() ? ",\n" : "\n");
+        f << "}\n";
+    }
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_autotune_load(pxcl_ctx* ctx, const char* cache_path, uint32_t mean_digis) {
+    if (!ctx || !cache_path) return PXCL_E_INVAL;
+    auto m = read_cache(cache_path);
+    auto it = m.find(cache_key(ctx, mean_digis));
+    if (it == m.end()) return PXCL_E_NOTFOUND;
+    return pxcl_set_kernel_config(ctx, it->second.first, it->second.second);
+}

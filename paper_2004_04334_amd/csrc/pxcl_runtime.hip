@@ -1,0 +1,704 @@
+// Host runtime of the pixel-clustering library: the C ABI of include/pxcl.h.
+//
+// acquire() only validates, stages host inputs with async copies, launches the
+// four kernels on the caller's stream and queues a host callback -- the split of a
+// module's work into acquire/produce with a completion callback that releases the
+// waiting task (paper Sec. 2 and Sec. 4.1).  No device or pinned allocation happens
+// after bind; the callback never calls HIP.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unistd.h>
+
+#include "../../include/pxcl.h"
+#include "pxcl_internal.h"
+
+namespace pxcl {
+bool cluster_config_valid(u32 wg, u32 mpw);
+u32 cluster_capacity(u32 wg, u32 mpw);
+int occupancy_segment();
+int occupancy_cluster(u32 wg, u32 mpw);
+int occupancy_large();
+int occupancy_compact();
+hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s);
+hipError_t launch_cluster(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s);
+hipError_t launch_large(const LaunchArgs& a, u32 grid, hipStream_t s);
+hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
+}  // namespace pxcl
+
+using namespace pxcl;
+
+namespace {
+
+enum : int { ST_IDLE = 0, ST_INFLIGHT = 1, ST_DONE = 2 };
+
+// Launch tags for look-back status words: unique within the process and seeded
+// per process so that stale words left in reused memory do not match.
+std::atomic<u32> g_epoch{0};
+u32 next_epoch() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        u64 t = (u64)std::chrono::steady_clock::now().time_since_epoch().count();
+        u64 x = t ^ ((u64)getpid() << 32) ^ 0x9E3779B97F4A7C15ull;
+        x ^= x >> 33; x *= 0xff51afd7ed558ccdull; x ^= x >> 33;
+        g_epoch.store(u32(x) | 1u);
+    });
+    u32 e;
+    do { e = g_epoch.fetch_add(1u); } while (e == 0u);
+    return e;
+}
+
+int status_from_bits(u32 bits) {
+    if (bits & EB_RANGE) return PXCL_E_RANGE;
+    if (bits & EB_ORDER) return PXCL_E_ORDER;
+    if (bits & EB_DUP) return PXCL_E_DUP_PIXEL;
+    if (bits & EB_INTERNAL) return PXCL_E_INTERNAL;
+    return PXCL_OK;
+}
+
+}  // namespace
+
+struct pxcl_ctx {
+    int device = 0;
+    u32 n_modules = 0, charge_cut = 0;
+    u32 n_cu = 0;
+    std::string arch;
+    std::atomic<u32> wg{256}, mpw{1};
+    int occ_a = 1, occ_l = 1, occ_c = 1;
+    std::atomic<int> bound{0};
+    std::atomic<int> timing{0};
+    std::mutex tmu;
+    double tsum[4] = {0, 0, 0, 0};
+    u64 tcnt[4] = {0, 0, 0, 0};
+};
+
+struct pxcl_event {
+    pxcl_ctx* ctx = nullptr;
+    u8* ws = nullptr;
+    size_t ws_bytes = 0;
+    u32 cap = 0;
+    u32* hs = nullptr;        // host view of the status block
+    u32* hs_dev = nullptr;    // device view of the same pinned memory
+    std::atomic<int> state{ST_IDLE};
+    u32 epoch = 0, n = 0;
+    int32_t status = PXCL_OK;
+    u32 err_bits = 0, ncl = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    hipEvent_t tev[5] = {};
+    bool timed = false;
+    pxcl_done_cb cb = nullptr;
+    void* user = nullptr;
+    pxcl_batch* batch = nullptr;
+};
+
+struct pxcl_batch {
+    pxcl_ctx* ctx = nullptr;
+    u8* ws = nullptr;
+    size_t ws_bytes = 0;
+    u8* hp = nullptr;         // pinned staging of the header
+    u32 max_events = 0;
+    std::atomic<int> state{ST_IDLE};
+    pxcl_event* evs[MAXB] = {};
+    u32 k = 0;
+    int32_t status = PXCL_OK;
+    pxcl_done_cb cb = nullptr;
+    void* user = nullptr;
+    hipEvent_t done_ev = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    u32 g_wg = 0, g_mpw = 0;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Grids {
+    u32 a, b, l, c;
+};
+
+// Grids of the four persistent kernels.  `bound_items` bounds the number of work
+// items (modules present) of the launch, `digis` the total digis; 0 = unknown (a
+// captured graph replays with any input), then every kernel gets a full device.
+Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 bound_items, bool full) {
+    Grids g;
+    const u64 ncu = ctx->n_cu;
+    const u64 fa = ncu * (u64)ctx->occ_a;
+    const u64 fb = ncu * (u64)occupancy_cluster(wg, mpw);
+    const u64 fl = ncu * (u64)ctx->occ_l;
+    const u64 fc = ncu * (u64)ctx->occ_c;
+    if (full) {
+        g.a = u32(fa); g.b = u32(fb); g.l = u32(fl); g.c = u32(fc);
+        return g;
+    }
+    const u32 dcap = cluster_capacity(wg, mpw);
+    g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + A_CH - 1) / A_CH)));
+    g.b = u32(std::max<u64>(1, std::min<u64>(fb, (bound_items + mpw - 1) / mpw)));
+    g.l = u32(std::max<u64>(1, std::min<u64>(fl, digis / (dcap + 1))));
+    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (bound_items + C_CH - 1) / C_CH)));
+    return g;
+}
+
+hipError_t launch_all(pxcl_ctx* ctx, const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipStream_t s,
+                      hipEvent_t* tev) {
+    hipError_t e;
+    if (tev && (e = hipEventRecord(tev[0], s)) != hipSuccess) return e;
+    if ((e = launch_segment(a, g.a, s)) != hipSuccess) return e;
+    if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
+    if ((e = launch_cluster(wg, mpw, a, g.b, s)) != hipSuccess) return e;
+    if (tev && (e = hipEventRecord(tev[2], s)) != hipSuccess) return e;
+    if ((e = launch_large(a, g.l, s)) != hipSuccess) return e;
+    if (tev && (e = hipEventRecord(tev[3], s)) != hipSuccess) return e;
+    if ((e = launch_compact(a, g.c, s)) != hipSuccess) return e;
+    if (tev && (e = hipEventRecord(tev[4], s)) != hipSuccess) return e;
+    (void)ctx;
+    return hipSuccess;
+}
+
+bool digis_ok(const pxcl_digis* in) {
+    if (!in) return false;
+    if (in->where != PXCL_WHERE_HOST && in->where != PXCL_WHERE_DEVICE) return false;
+    if (in->n && (!in->module || !in->row || !in->col || !in->adc)) return false;
+    return true;
+}
+
+// Stage host digis into the slot (async copies; one copy if the four arrays are
+// contiguous in the order module,row,col,adc) and describe the event.
+hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventDesc* d) {
+    const EvLayout L = ev_layout(ev->cap);
+    d->ws = ev->ws;
+    d->hstat = ev->hs_dev;
+    d->n = in->n;
+    d->cap = ev->cap;
+    d->epoch = ev->epoch;
+    d->pad = 0;
+    if (in->where == PXCL_WHERE_DEVICE) {
+        d->module = in->module; d->row = in->row; d->col = in->col; d->adc = in->adc;
+        return hipSuccess;
+    }
+    u16* m = reinterpret_cast<u16*>(ev->ws + L.in_mod);
+    u16* r = reinterpret_cast<u16*>(ev->ws + L.in_row);
+    u16* c = reinterpret_cast<u16*>(ev->ws + L.in_col);
+    u16* a = reinterpret_cast<u16*>(ev->ws + L.in_adc);
+    d->module = m; d->row = r; d->col = c; d->adc = a;
+    const size_t b = size_t(in->n) * 2;
+    if (!b) return hipSuccess;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(m, in->module, b, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(r, in->row, b, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(c, in->col, b, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    return hipMemcpyAsync(a, in->adc, b, hipMemcpyHostToDevice, s);
+}
+
+void finish_event_from_host_status(pxcl_event* ev) {
+    volatile u32* hs = ev->hs;
+    const u32 tag = __atomic_load_n(&ev->hs[HS_EPOCH], __ATOMIC_ACQUIRE);
+    u32 bits = hs[HS_ERR];
+    if (tag != ev->epoch) bits |= EB_INTERNAL;       // status write-back missing
+    ev->err_bits = bits;
+    ev->ncl = hs[HS_NCL];
+    ev->status = status_from_bits(bits);
+}
+
+void event_done_hostfn(void* p) {
+    pxcl_event* ev = static_cast<pxcl_event*>(p);
+    finish_event_from_host_status(ev);
+    pxcl_done_cb cb = ev->cb;
+    void* user = ev->user;
+    const int32_t st = ev->status;
+    ev->state.store(ST_DONE, std::memory_order_release);
+    if (cb) cb(user, st);
+}
+
+void batch_done_hostfn(void* p) {
+    pxcl_batch* b = static_cast<pxcl_batch*>(p);
+    int32_t bst = PXCL_OK;
+    for (u32 i = 0; i < b->k; ++i) {
+        pxcl_event* ev = b->evs[i];
+        finish_event_from_host_status(ev);
+        if (bst == PXCL_OK && ev->status != PXCL_OK) bst = ev->status;
+    }
+    b->status = bst;
+    pxcl_done_cb cb = b->cb;
+    void* user = b->user;
+    for (u32 i = 0; i < b->k; ++i) b->evs[i]->state.store(ST_DONE, std::memory_order_release);
+    b->state.store(ST_DONE, std::memory_order_release);
+    if (cb) cb(user, bst);
+}
+
+bool claim(std::atomic<int>& st) {
+    int cur = st.load(std::memory_order_acquire);
+    while (cur != ST_INFLIGHT) {
+        if (st.compare_exchange_weak(cur, ST_INFLIGHT, std::memory_order_acq_rel)) return true;
+    }
+    return false;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** out) {
+    if (!cfg || !out || cfg->n_modules == 0 || cfg->n_modules > PXCL_MAX_MODULES) return PXCL_E_INVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PXCL_E_INVAL;
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (hipSetDevice(device) != hipSuccess) return PXCL_E_HIP;
+    pxcl_ctx* c = new pxcl_ctx();
+    c->device = device;
+    c->n_modules = cfg->n_modules;
+    c->charge_cut = cfg->charge_cut;
+    int ncu = 0;
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    c->n_cu = ncu > 0 ? u32(ncu) : 1u;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        std::string a(prop.gcnArchName);
+        c->arch = a.substr(0, a.find(':'));
+    }
+    c->occ_a = occupancy_segment();
+    c->occ_l = occupancy_large();
+    c->occ_c = occupancy_compact();
+    hipSetDevice(prev);
+    *out = c;
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_ctx_destroy(pxcl_ctx* ctx) {
+    if (!ctx) return PXCL_E_INVAL;
+    if (ctx->bound.load() != 0) return PXCL_E_BUSY;
+    delete ctx;
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_set_kernel_config(pxcl_ctx* ctx, uint32_t wg, uint32_t mpw) {
+    if (!ctx || !cluster_config_valid(wg, mpw)) return PXCL_E_INVAL;
+    ctx->wg.store(wg);
+    ctx->mpw.store(mpw);
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_get_kernel_config(const pxcl_ctx* ctx, uint32_t* wg, uint32_t* mpw) {
+    if (!ctx || !wg || !mpw) return PXCL_E_INVAL;
+    *wg = ctx->wg.load();
+    *mpw = ctx->mpw.load();
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_set_timing(pxcl_ctx* ctx, int enable) {
+    if (!ctx) return PXCL_E_INVAL;
+    ctx->timing.store(enable ? 1 : 0);
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum, uint64_t* launches, int reset) {
+    if (!ctx) return PXCL_E_INVAL;
+    std::lock_guard<std::mutex> g(ctx->tmu);
+    for (int i = 0; i < 4; ++i) {
+        if (ms_sum) ms_sum[i] = ctx->tsum[i];
+        if (launches) launches[i] = ctx->tcnt[i];
+        if (reset) { ctx->tsum[i] = 0; ctx->tcnt[i] = 0; }
+    }
+    return PXCL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// events
+// ---------------------------------------------------------------------------
+extern "C" size_t pxcl_event_workspace_bytes(const pxcl_ctx* ctx, uint32_t max_digis) {
+    if (!ctx || max_digis == 0 || max_digis > PXCL_MAX_EVENT_DIGIS) return 0;
+    return ev_layout(max_digis).total;
+}
+
+extern "C" size_t pxcl_event_pinned_bytes(const pxcl_ctx* ctx) { return ctx ? HS_BYTES : 0; }
+
+extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void* h_pinned, size_t pinned_bytes,
+                               uint32_t max_digis, void* stream, pxcl_event** out) {
+    if (!ctx || !d_ws || !h_pinned || !out) return PXCL_E_INVAL;
+    if (max_digis == 0 || max_digis > PXCL_MAX_EVENT_DIGIS) return PXCL_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(d_ws) & 255u) || (reinterpret_cast<uintptr_t>(h_pinned) & 63u))
+        return PXCL_E_INVAL;
+    const EvLayout L = ev_layout(max_digis);
+    if (ws_bytes < L.total || pinned_bytes < HS_BYTES) return PXCL_E_CAPACITY;
+    void* hdev = nullptr;
+    if (hipHostGetDevicePointer(&hdev, h_pinned, 0) != hipSuccess || !hdev) {
+        (void)hipGetLastError();
+        return PXCL_E_INVAL;   // not pinned host memory
+    }
+    pxcl_event* ev = new pxcl_event();
+    ev->ctx = ctx;
+    ev->ws = static_cast<u8*>(d_ws);
+    ev->ws_bytes = ws_bytes;
+    ev->cap = max_digis;
+    ev->hs = static_cast<u32*>(h_pinned);
+    ev->hs_dev = static_cast<u32*>(hdev);
+    std::memset(h_pinned, 0, HS_BYTES);
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipEventCreateWithFlags(&ev->done_ev, hipEventDisableTiming);
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev->tev[i]);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.lb_a, 0, L.lb_c - L.lb_a, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.lb_c, 0, L.total - L.lb_c, s);
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (ev->done_ev) hipEventDestroy(ev->done_ev);
+        for (int i = 0; i < 5; ++i) if (ev->tev[i]) hipEventDestroy(ev->tev[i]);
+        delete ev;
+        return PXCL_E_HIP;
+    }
+    ctx->bound.fetch_add(1);
+    *out = ev;
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_event_unbind(pxcl_event* ev) {
+    if (!ev) return PXCL_E_INVAL;
+    if (ev->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+    hipEventDestroy(ev->done_ev);
+    for (int i = 0; i < 5; ++i) hipEventDestroy(ev->tev[i]);
+    ev->ctx->bound.fetch_sub(1);
+    delete ev;
+    return PXCL_OK;
+}
+
+extern "C" uint32_t pxcl_event_capacity(const pxcl_event* ev) { return ev ? ev->cap : 0; }
+
+extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, pxcl_done_cb cb, void* user) {
+    if (!ev || !digis_ok(in)) return PXCL_E_INVAL;
+    if (in->n > ev->cap) return PXCL_E_CAPACITY;
+    if (!claim(ev->state)) return PXCL_E_BUSY;
+    pxcl_ctx* ctx = ev->ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ev->epoch = next_epoch();
+    ev->n = in->n;
+    ev->cb = cb;
+    ev->user = user;
+    ev->stream = s;
+    ev->batch = nullptr;
+    ev->status = PXCL_OK;
+    __atomic_store_n(&ev->hs[HS_EPOCH], 0u, __ATOMIC_RELEASE);
+    const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
+    const bool timed = ctx->timing.load() != 0;
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    LaunchArgs a;
+    a.hdr = nullptr;
+    a.ctr = reinterpret_cast<u32*>(ev->ws + ev_layout(ev->cap).ctl) + CTL_CTR;
+    a.n_modules = ctx->n_modules;
+    a.charge_cut = ctx->charge_cut;
+    hipError_t e = make_desc(ev, in, s, &a.single);
+    const u64 items = std::min<u64>(in->n, (u64)ctx->n_modules);
+    const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), false);
+    if (e == hipSuccess) e = launch_all(ctx, a, g, wg, mpw, s, timed ? ev->tev : nullptr);
+    if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
+    if (e == hipSuccess) e = hipLaunchHostFunc(s, event_done_hostfn, ev);
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ev->state.store(ST_IDLE, std::memory_order_release);
+        return PXCL_E_HIP;
+    }
+    ev->timed = timed;
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_query(const pxcl_event* ev) {
+    if (!ev) return PXCL_E_INVAL;
+    const int st = ev->state.load(std::memory_order_acquire);
+    if (st == ST_DONE) return PXCL_OK;
+    if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
+    return PXCL_E_INVAL;
+}
+
+static void collect_timing(pxcl_event* ev) {
+    if (!ev->timed) return;
+    ev->timed = false;
+    float ms[4];
+    for (int i = 0; i < 4; ++i)
+        if (hipEventElapsedTime(&ms[i], ev->tev[i], ev->tev[i + 1]) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(ev->ctx->tmu);
+    for (int i = 0; i < 4; ++i) {
+        ev->ctx->tsum[i] += ms[i];
+        ev->ctx->tcnt[i] += 1;
+    }
+}
+
+extern "C" int pxcl_produce(pxcl_event* ev, pxcl_clusters* out) {
+    if (!ev || !out) return PXCL_E_INVAL;
+    const int st = ev->state.load(std::memory_order_acquire);
+    if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
+    if (st != ST_DONE) return PXCL_E_INVAL;
+    collect_timing(ev);
+    const EvLayout L = ev_layout(ev->cap);
+    out->status = ev->status;
+    out->err_bits = ev->err_bits;
+    out->n_clusters = ev->ncl;
+    out->n_digis = ev->n;
+    out->id = reinterpret_cast<const int32_t*>(ev->ws + L.id);
+    out->charge = reinterpret_cast<const int32_t*>(ev->ws + L.charge);
+    out->size = reinterpret_cast<const int32_t*>(ev->ws + L.size);
+    out->digi_cluster = reinterpret_cast<const int32_t*>(ev->ws + L.digi);
+    out->stream = ev->stream;
+    out->done_event = ev->batch ? ev->batch->done_ev : ev->done_ev;
+    out->device = ev->ctx->device;
+    return ev->status;
+}
+
+extern "C" int pxcl_wait(pxcl_event* ev) {
+    if (!ev) return PXCL_E_INVAL;
+    int st = ev->state.load(std::memory_order_acquire);
+    if (st == ST_IDLE) return PXCL_E_INVAL;
+    if (st == ST_INFLIGHT) {
+        hipEvent_t de = ev->batch ? ev->batch->done_ev : ev->done_ev;
+        if (hipEventSynchronize(de) != hipSuccess) return PXCL_E_HIP;
+        while (ev->state.load(std::memory_order_acquire) != ST_DONE) std::this_thread::yield();
+    }
+    return PXCL_OK;
+}
+
+extern "C" void pxcl_flag_cb(void* user, int32_t status) {
+    pxcl_flag* f = static_cast<pxcl_flag*>(user);
+    if (!f) return;
+    f->status = status;
+    __atomic_fetch_add(&f->fired, 1u, __ATOMIC_RELEASE);
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+extern "C" size_t pxcl_batch_workspace_bytes(const pxcl_ctx* ctx, uint32_t max_events) {
+    if (!ctx || max_events == 0 || max_events > MAXB) return 0;
+    return batch_ws_bytes(max_events);
+}
+
+extern "C" size_t pxcl_batch_pinned_bytes(const pxcl_ctx* ctx, uint32_t max_events) {
+    if (!ctx || max_events == 0 || max_events > MAXB) return 0;
+    return al256(header_bytes(max_events));
+}
+
+extern "C" int pxcl_batch_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void* h_pinned, size_t pinned_bytes,
+                               uint32_t max_events, void* stream, pxcl_batch** out) {
+    if (!ctx || !d_ws || !h_pinned || !out || max_events == 0 || max_events > MAXB) return PXCL_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(d_ws) & 255u) || (reinterpret_cast<uintptr_t>(h_pinned) & 63u))
+        return PXCL_E_INVAL;
+    if (ws_bytes < batch_ws_bytes(max_events) || pinned_bytes < header_bytes(max_events)) return PXCL_E_CAPACITY;
+    pxcl_batch* b = new pxcl_batch();
+    b->ctx = ctx;
+    b->ws = static_cast<u8*>(d_ws);
+    b->ws_bytes = ws_bytes;
+    b->hp = static_cast<u8*>(h_pinned);
+    b->max_events = max_events;
+    std::memset(h_pinned, 0, header_bytes(max_events));
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    hipError_t e = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ws, 0, BW_HDR, static_cast<hipStream_t>(stream));
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (b->done_ev) hipEventDestroy(b->done_ev);
+        if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+        delete b;
+        return PXCL_E_HIP;
+    }
+    ctx->bound.fetch_add(1);
+    *out = b;
+    return PXCL_OK;
+}
+
+static void drop_graph(pxcl_batch* b) {
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+extern "C" int pxcl_batch_unbind(pxcl_batch* b) {
+    if (!b) return PXCL_E_INVAL;
+    if (b->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+    drop_graph(b);
+    hipEventDestroy(b->done_ev);
+    hipStreamDestroy(b->cap_stream);
+    b->ctx->bound.fetch_sub(1);
+    delete b;
+    return PXCL_OK;
+}
+
+static LaunchArgs batch_args(pxcl_batch* b) {
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.hdr = reinterpret_cast<const u32*>(b->ws + BW_HDR);
+    a.ctr = reinterpret_cast<u32*>(b->ws + BW_CTR);
+    a.n_modules = b->ctx->n_modules;
+    a.charge_cut = b->ctx->charge_cut;
+    return a;
+}
+
+// Capture the per-batch pipeline (header copy + four kernels, full grids) once per
+// kernel configuration; replays read k and the event descriptors from the header.
+static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw) {
+    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw) return hipSuccess;
+    drop_graph(b);
+    pxcl_ctx* ctx = b->ctx;
+    const LaunchArgs a = batch_args(b);
+    const Grids g = grids_for(ctx, wg, mpw, 0, 0, true);
+    hipStream_t cs = b->cap_stream;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e2 = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(b->max_events), hipMemcpyHostToDevice, cs);
+    if (e2 == hipSuccess) e2 = launch_all(ctx, a, g, wg, mpw, cs, nullptr);
+    e = hipStreamEndCapture(cs, &b->graph);
+    if (e2 != hipSuccess) { if (b->graph) hipGraphDestroy(b->graph); b->graph = nullptr; return e2; }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { drop_graph(b); return e; }
+    b->g_wg = wg;
+    b->g_mpw = mpw;
+    return hipSuccess;
+}
+
+extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const pxcl_digis* ins, uint32_t k,
+                                  void* stream, pxcl_done_cb cb, void* user, uint32_t flags) {
+    if (!b || !evs || !ins || k == 0) return PXCL_E_INVAL;
+    if (k > b->max_events) return PXCL_E_CAPACITY;
+    for (u32 i = 0; i < k; ++i) {
+        if (!evs[i] || evs[i]->ctx != b->ctx || !digis_ok(&ins[i])) return PXCL_E_INVAL;
+        if (ins[i].n > evs[i]->cap) return PXCL_E_CAPACITY;
+        for (u32 j = 0; j < i; ++j)
+            if (evs[j] == evs[i]) return PXCL_E_INVAL;
+    }
+    if (!claim(b->state)) return PXCL_E_BUSY;
+    u32 got = 0;
+    for (; got < k; ++got)
+        if (!claim(evs[got]->state)) break;
+    if (got < k) {
+        for (u32 i = 0; i < got; ++i) evs[i]->state.store(ST_IDLE, std::memory_order_release);
+        b->state.store(ST_IDLE, std::memory_order_release);
+        return PXCL_E_BUSY;
+    }
+    pxcl_ctx* ctx = b->ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
+    b->k = k;
+    b->cb = cb;
+    b->user = user;
+    b->status = PXCL_OK;
+    *reinterpret_cast<u32*>(b->hp) = k;
+    EventDesc* hd = reinterpret_cast<EventDesc*>(b->hp + HDR_EV_OFFSET);
+    hipError_t e = hipSuccess;
+    u64 digis = 0, items = 0;
+    for (u32 i = 0; i < k && e == hipSuccess; ++i) {
+        pxcl_event* ev = evs[i];
+        b->evs[i] = ev;
+        ev->epoch = next_epoch();
+        ev->n = ins[i].n;
+        ev->cb = nullptr;
+        ev->user = nullptr;
+        ev->stream = s;
+        ev->batch = b;
+        ev->timed = false;
+        ev->status = PXCL_OK;
+        __atomic_store_n(&ev->hs[HS_EPOCH], 0u, __ATOMIC_RELEASE);
+        e = make_desc(ev, &ins[i], s, &hd[i]);
+        digis += ins[i].n;
+        items += std::min<u64>(ins[i].n, (u64)ctx->n_modules);
+    }
+    if (e == hipSuccess) {
+        if (flags & PXCL_BATCH_GRAPH) {
+            e = ensure_graph(b, wg, mpw);
+            if (e == hipSuccess) e = hipGraphLaunch(b->gexec, s);
+        } else {
+            const LaunchArgs a = batch_args(b);
+            e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
+            const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), false);
+            if (e == hipSuccess) e = launch_all(ctx, a, g, wg, mpw, s, nullptr);
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->done_ev, s);
+    if (e == hipSuccess) e = hipLaunchHostFunc(s, batch_done_hostfn, b);
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        for (u32 i = 0; i < k; ++i) evs[i]->state.store(ST_IDLE, std::memory_order_release);
+        b->state.store(ST_IDLE, std::memory_order_release);
+        return PXCL_E_HIP;
+    }
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_batch_query(const pxcl_batch* b) {
+    if (!b) return PXCL_E_INVAL;
+    const int st = b->state.load(std::memory_order_acquire);
+    if (st == ST_DONE) return PXCL_OK;
+    if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
+    return PXCL_E_INVAL;
+}
+
+// ---------------------------------------------------------------------------
+// misc
+// ---------------------------------------------------------------------------
+extern "C" const char* pxcl_strerror(int code) {
+    switch (code) {
+        case PXCL_OK: return "ok";
+        case PXCL_E_INVAL: return "invalid argument";
+        case PXCL_E_CAPACITY: return "capacity exceeded";
+        case PXCL_E_BUSY: return "work in flight";
+        case PXCL_E_NOT_READY: return "not ready";
+        case PXCL_E_DUP_PIXEL: return "pixel fired twice in a module";
+        case PXCL_E_RANGE: return "module, row or column out of range";
+        case PXCL_E_ORDER: return "digis not grouped by ascending module";
+        case PXCL_E_HIP: return "HIP runtime error";
+        case PXCL_E_INTERNAL: return "internal error (device wait expired)";
+        case PXCL_E_NOTFOUND: return "not found";
+        default: return "unknown error";
+    }
+}
+
+extern "C" const char* pxcl_version(void) { return "pxcl 0.1 gfx950"; }
+
+// internal accessors for the drivers and the autotuner
+namespace pxcl {
+u32 event_n(const pxcl_event* ev) { return ev->n; }
+hipEvent_t batch_done_event(const pxcl_batch* b) { return b->done_ev; }
+const std::string& ctx_arch(const pxcl_ctx* c) { return c->arch; }
+int ctx_device(const pxcl_ctx* c) { return c->device; }
+}  // namespace pxcl
+
+// Point an idle event object at another workspace range (serving: per-request
+// workspaces carved out of one arena).  Clears the slot's control words with an
+// async memset on `s`; look-back status words need no clearing because launch tags
+// are unique within the process.
+namespace pxcl {
+int event_rebind(pxcl_event* ev, void* d_ws, size_t ws_bytes, uint32_t max_digis, hipStream_t s) {
+    if (!ev || !d_ws || max_digis == 0 || max_digis > PXCL_MAX_EVENT_DIGIS) return PXCL_E_INVAL;
+    if (ev->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+    const EvLayout L = ev_layout(max_digis);
+    if (ws_bytes < L.total) return PXCL_E_CAPACITY;
+    ev->ws = static_cast<u8*>(d_ws);
+    ev->ws_bytes = ws_bytes;
+    ev->cap = max_digis;
+    ev->state.store(ST_IDLE, std::memory_order_release);
+    return hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s) == hipSuccess ? PXCL_OK : PXCL_E_HIP;
+}
+}  // namespace pxcl

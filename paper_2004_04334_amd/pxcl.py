@@ -1,0 +1,443 @@
+"""Python binding of the HIP pixel-clustering library (``libpxcl.so``, C ABI in
+``include/pxcl.h``).
+
+Argument marshalling only: every step of the clustering runs in the library's
+kernels.  PyTorch provides device memory (its caching allocator plays the role of
+the memory pool the paper describes in Sec. 4.1) and streams.  The names follow the
+External Worker split of the paper (Sec. 2): ``acquire(event, digis, stream,
+done_cb)`` enqueues the device work and returns at once; ``done_cb(status)`` fires
+once on completion; ``produce(event)`` returns the clusters as tensors that view the
+event's workspace (valid until the next acquire on that event).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Callable, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpxcl.so")
+
+OK, E_INVAL, E_CAPACITY, E_BUSY, E_NOT_READY = 0, -1, -2, -3, -4
+E_DUP_PIXEL, E_RANGE, E_ORDER, E_HIP, E_INTERNAL, E_NOTFOUND = -5, -6, -7, -8, -10, -11
+WHERE_HOST, WHERE_DEVICE = 0, 1
+BATCH_GRAPH = 1
+MAX_BATCH = 128
+ROWS, COLS, PIXELS_PER_MODULE = 160, 416, 66560
+
+
+class PxclError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})" if what else f"{strerror(code)} ({code})")
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n_modules", ctypes.c_uint32), ("charge_cut", ctypes.c_uint32)]
+
+
+class _Digis(ctypes.Structure):
+    _fields_ = [("module", ctypes.c_void_p), ("row", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("adc", ctypes.c_void_p), ("n", ctypes.c_uint32), ("where", ctypes.c_int32)]
+
+
+class _Clusters(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("err_bits", ctypes.c_uint32), ("n_clusters", ctypes.c_uint32),
+                ("n_digis", ctypes.c_uint32), ("id", ctypes.c_void_p), ("charge", ctypes.c_void_p),
+                ("size", ctypes.c_void_p), ("digi_cluster", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+                ("done_event", ctypes.c_void_p), ("device", ctypes.c_int32)]
+
+
+class Flag(ctypes.Structure):
+    """Host word pair written by the library's ready-made callback ``pxcl_flag_cb``."""
+    _fields_ = [("status", ctypes.c_int32), ("fired", ctypes.c_uint32)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("events", ctypes.c_uint64), ("digis", ctypes.c_uint64),
+                ("lat_p50_us", ctypes.c_double), ("lat_p99_us", ctypes.c_double), ("lat_max_us", ctypes.c_double),
+                ("blocked_us_per_event", ctypes.c_double), ("cpu_tasks_per_s", ctypes.c_double),
+                ("cpu_tasks", ctypes.c_uint64), ("errors", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
+                ("peak_resident_bytes", ctypes.c_uint64), ("batches", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("rate_hz", ctypes.c_double), ("n_requests", ctypes.c_uint32), ("budget_bytes", ctypes.c_uint64),
+                ("n_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("n_cpu_threads", ctypes.c_uint32),
+                ("cpu_task_ns", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32)
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "pxcl_ctx_create": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "pxcl_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_set_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
+    "pxcl_get_kernel_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                              ctypes.POINTER(ctypes.c_uint32)]),
+    "pxcl_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "pxcl_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
+    "pxcl_event_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
+    "pxcl_event_pinned_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "pxcl_event_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "pxcl_event_unbind": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_event_capacity": (ctypes.c_uint32, [ctypes.c_void_p]),
+    "pxcl_acquire": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Digis), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "pxcl_query": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_produce": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Clusters)]),
+    "pxcl_wait": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_flag_cb": (None, [ctypes.c_void_p, ctypes.c_int32]),
+    "pxcl_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
+    "pxcl_batch_pinned_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
+    "pxcl_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "pxcl_batch_unbind": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_acquire_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_Digis),
+                                          ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_uint32]),
+    "pxcl_batch_query": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.POINTER(_Digis), ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32,
+                                     ctypes.c_char_p, ctypes.POINTER(ctypes.c_float)]),
+    "pxcl_autotune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint32]),
+    "pxcl_run_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.POINTER(_Digis),
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                      ctypes.POINTER(RunStats)]),
+    "pxcl_serve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.c_uint32, ctypes.POINTER(_Digis), ctypes.c_uint32,
+                                  ctypes.POINTER(ServeOpts), ctypes.POINTER(RunStats),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32),
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "pxcl_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pxcl_version": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load ``libpxcl.so``; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_04334_amd.build`")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().pxcl_strerror(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise PxclError(code, what)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+FLAG_CB = None  # pxcl_flag_cb as a C function pointer, resolved on first use
+
+
+def flag_cb_ptr() -> int:
+    global FLAG_CB
+    if FLAG_CB is None:
+        FLAG_CB = ctypes.cast(lib().pxcl_flag_cb, ctypes.c_void_p).value
+    return FLAG_CB
+
+
+# ---------------------------------------------------------------------------
+@dataclass
+class Digis:
+    """Digis of one event as four uint16 tensors (CUDA or pinned CPU), grouped by
+    non-decreasing module.  Keep the object alive until the done callback."""
+    module: torch.Tensor
+    row: torch.Tensor
+    col: torch.Tensor
+    adc: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.module.numel())
+
+    @property
+    def where(self) -> int:
+        return WHERE_DEVICE if self.module.is_cuda else WHERE_HOST
+
+    def struct(self) -> _Digis:
+        ts = (self.module, self.row, self.col, self.adc)
+        for t in ts:
+            if t.dtype != torch.uint16 or not t.is_contiguous() or t.numel() != self.n:
+                raise ValueError("digis must be contiguous uint16 tensors of equal length")
+            if t.is_cuda != self.module.is_cuda or (not t.is_cuda and not t.is_pinned()):
+                raise ValueError("digis must all be on the device or all in pinned host memory")
+        return _Digis(*(t.data_ptr() if self.n else None for t in ts), self.n, self.where)
+
+    @staticmethod
+    def from_numpy(ev, device: str = "cuda") -> "Digis":
+        ts = []
+        for k in ("module", "row", "col", "adc"):
+            t = torch.from_numpy(ev[k].astype("uint16", copy=True))
+            if device == "cuda":
+                t = t.to("cuda", non_blocking=False)
+            elif device == "pinned":
+                t = t.pin_memory()
+            ts.append(t.contiguous())
+        return Digis(*ts)
+
+
+@dataclass
+class ClusterResult:
+    status: int
+    err_bits: int
+    n_clusters: int
+    id: torch.Tensor
+    charge: torch.Tensor
+    size: torch.Tensor
+    digi_cluster: torch.Tensor
+    stream: int
+    done_event: int
+
+    def numpy(self):
+        return {"status": self.status, "err_bits": self.err_bits, "n_clusters": self.n_clusters,
+                "id": self.id.cpu().numpy(), "charge": self.charge.cpu().numpy(),
+                "size": self.size.cpu().numpy(), "digi": self.digi_cluster.cpu().numpy()}
+
+
+class Context:
+    def __init__(self, n_modules: int, charge_cut: int = 2000, device: int = 0):
+        self._h = ctypes.c_void_p()
+        cfg = _Config(int(n_modules), int(charge_cut))
+        _check(lib().pxcl_ctx_create(ctypes.byref(cfg), int(device), ctypes.byref(self._h)), "ctx_create")
+        self.n_modules, self.charge_cut, self.device = int(n_modules), int(charge_cut), int(device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_kernel_config(self, wg: int, mpw: int):
+        _check(lib().pxcl_set_kernel_config(self._h, wg, mpw), "set_kernel_config")
+
+    def kernel_config(self):
+        a, b = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().pxcl_get_kernel_config(self._h, ctypes.byref(a), ctypes.byref(b)), "get_kernel_config")
+        return a.value, b.value
+
+    def set_timing(self, enable: bool):
+        _check(lib().pxcl_set_timing(self._h, 1 if enable else 0), "set_timing")
+
+    def timing(self, reset: bool = False):
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_uint64 * 4)()
+        _check(lib().pxcl_get_timing(self._h, ms, cnt, 1 if reset else 0), "get_timing")
+        return list(ms), list(cnt)
+
+    def workspace_bytes(self, max_digis: int) -> int:
+        return int(lib().pxcl_event_workspace_bytes(self._h, int(max_digis)))
+
+    def close(self):
+        if self._h:
+            _check(lib().pxcl_ctx_destroy(self._h), "ctx_destroy")
+            self._h = ctypes.c_void_p()
+
+
+class Event:
+    """An event slot: a device workspace and a pinned status block, bound once."""
+
+    def __init__(self, ctx: Context, max_digis: int, stream=None):
+        self.ctx = ctx
+        self.max_digis = int(max_digis)
+        nb = ctx.workspace_bytes(self.max_digis)
+        if nb == 0:
+            raise PxclError(E_INVAL, "workspace size")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        pb = int(lib().pxcl_event_pinned_bytes(ctx.handle))
+        self.pinned = torch.empty(max(pb, 64), dtype=torch.uint8, pin_memory=True)
+        self._h = ctypes.c_void_p()
+        _check(lib().pxcl_event_bind(ctx.handle, self.ws.data_ptr(), nb, self.pinned.data_ptr(), pb,
+                                     self.max_digis, _stream_ptr(stream), ctypes.byref(self._h)), "event_bind")
+        torch.cuda.synchronize(ctx.device)   # set-up time: the slot is clean before any stream uses it
+        self._keep = None
+        self._cb = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _view(self, ptr: int, count: int) -> torch.Tensor:
+        off = int(ptr) - self.ws.data_ptr()
+        return self.ws[off: off + 4 * count].view(torch.int32)
+
+    def close(self):
+        if self._h:
+            _check(lib().pxcl_event_unbind(self._h), "event_unbind")
+            self._h = ctypes.c_void_p()
+
+
+def acquire(event: Event, digis: Digis, stream=None, done_cb: Optional[Callable[[int], None]] = None,
+            flag: Optional[Flag] = None) -> None:
+    """Enqueue the clustering of one event; returns without waiting.  ``done_cb``
+    (a Python callable, called with the status from a HIP runtime thread) or
+    ``flag`` (filled by the library's own callback) signal completion."""
+    d = digis.struct()
+    cb_ptr, user = None, None
+    if flag is not None:
+        cb_ptr, user = flag_cb_ptr(), ctypes.addressof(flag)
+    elif done_cb is not None:
+        c = DONE_CB(lambda _u, st: done_cb(int(st)))
+        event._cb = c
+        cb_ptr = ctypes.cast(c, ctypes.c_void_p).value
+    event._keep = (digis, d, flag)
+    _check(lib().pxcl_acquire(event.handle, ctypes.byref(d), _stream_ptr(stream), cb_ptr, user), "acquire")
+
+
+def query(event: Event) -> int:
+    return int(lib().pxcl_query(event.handle))
+
+
+def wait(event: Event) -> None:
+    _check(lib().pxcl_wait(event.handle), "wait")
+
+
+def produce(event: Event) -> ClusterResult:
+    """Results of a completed event (E_NOT_READY raises).  Async input errors are
+    reported in ``status`` rather than raised."""
+    c = _Clusters()
+    st = int(lib().pxcl_produce(event.handle, ctypes.byref(c)))
+    if st in (E_NOT_READY, E_INVAL):
+        raise PxclError(st, "produce")
+    return ClusterResult(st, int(c.err_bits), int(c.n_clusters), event._view(c.id, c.n_clusters),
+                         event._view(c.charge, c.n_clusters), event._view(c.size, c.n_clusters),
+                         event._view(c.digi_cluster, c.n_digis), c.stream or 0, c.done_event or 0)
+
+
+class Batch:
+    def __init__(self, ctx: Context, max_events: int, stream=None):
+        self.ctx = ctx
+        self.max_events = int(max_events)
+        nb = int(lib().pxcl_batch_workspace_bytes(ctx.handle, self.max_events))
+        pb = int(lib().pxcl_batch_pinned_bytes(ctx.handle, self.max_events))
+        if nb == 0 or pb == 0:
+            raise PxclError(E_INVAL, "batch size")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.pinned = torch.empty(pb, dtype=torch.uint8, pin_memory=True)
+        self._h = ctypes.c_void_p()
+        _check(lib().pxcl_batch_bind(ctx.handle, self.ws.data_ptr(), nb, self.pinned.data_ptr(), pb,
+                                     self.max_events, _stream_ptr(stream), ctypes.byref(self._h)), "batch_bind")
+        torch.cuda.synchronize(ctx.device)
+        self._keep = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _check(lib().pxcl_batch_unbind(self._h), "batch_unbind")
+            self._h = ctypes.c_void_p()
+
+
+def _batch_arrays(events: Sequence[Event], digis: Sequence[Digis]):
+    k = len(events)
+    evs = (ctypes.c_void_p * k)(*[e.handle.value for e in events])
+    ins = (_Digis * k)(*[d.struct() for d in digis])
+    return k, evs, ins
+
+
+def acquire_batch(batch: Batch, events: Sequence[Event], digis: Sequence[Digis], stream=None,
+                  flag: Optional[Flag] = None, graph: bool = False) -> None:
+    if len(events) != len(digis):
+        raise ValueError("one Digis per event")
+    k, evs, ins = _batch_arrays(events, digis)
+    cb_ptr, user = (flag_cb_ptr(), ctypes.addressof(flag)) if flag is not None else (None, None)
+    batch._keep = (list(digis), evs, ins, flag)
+    _check(lib().pxcl_acquire_batch(batch.handle, evs, ins, k, _stream_ptr(stream), cb_ptr, user,
+                                    BATCH_GRAPH if graph else 0), "acquire_batch")
+
+
+def batch_query(batch: Batch) -> int:
+    return int(lib().pxcl_batch_query(batch.handle))
+
+
+def autotune(ctx: Context, batch: Batch, events: Sequence[Event], digis: Sequence[Digis], stream=None,
+             reps: int = 5, cache_path: Optional[str] = None):
+    """Time every (workgroup size, modules per workgroup) of the clustering kernel on
+    this batch, keep the fastest; returns {(wg, mpw): microseconds}."""
+    k, evs, ins = _batch_arrays(events, digis)
+    us = (ctypes.c_float * 12)()
+    _check(lib().pxcl_autotune(ctx.handle, batch.handle, evs, ins, k, _stream_ptr(stream), int(reps),
+                               cache_path.encode() if cache_path else None, us), "autotune")
+    out = {}
+    for i, wg in enumerate((64, 128, 256, 512)):
+        for j, mpw in enumerate((1, 2, 4)):
+            if us[i * 3 + j] >= 0:
+                out[(wg, mpw)] = float(us[i * 3 + j])
+    return out
+
+
+def autotune_load(ctx: Context, cache_path: str, mean_digis: int) -> bool:
+    r = int(lib().pxcl_autotune_load(ctx.handle, cache_path.encode(), int(mean_digis)))
+    if r == E_NOTFOUND:
+        return False
+    _check(r, "autotune_load")
+    return True
+
+
+def run_async(ctx: Context, events: Sequence[Event], streams, pool: Sequence[Digis], events_per_thread: int,
+              cpu_task_ns: int = 0, blocking: bool = False) -> dict:
+    n = len(events)
+    evs = (ctypes.c_void_p * n)(*[e.handle.value for e in events])
+    sts = (ctypes.c_void_p * n)(*[int(s.cuda_stream) for s in streams])
+    ins = (_Digis * len(pool))(*[d.struct() for d in pool])
+    st = RunStats()
+    _check(lib().pxcl_run_async(ctx.handle, evs, sts, n, ins, len(pool), int(events_per_thread),
+                                int(cpu_task_ns), 1 if blocking else 0, ctypes.byref(st)), "run_async")
+    return st.as_dict()
+
+
+def serve(ctx: Context, arena: torch.Tensor, pinned: torch.Tensor, batches: Sequence[Batch], streams,
+          pool: Sequence[Digis], rate_hz: float, n_requests: int, budget_bytes: int, n_slots: int,
+          max_batch: int, n_cpu_threads: int = 16, cpu_task_ns: int = 20000, graph: bool = True,
+          seed: int = 1, results: Optional[torch.Tensor] = None, result_offsets: Optional[Sequence[int]] = None):
+    """Serving form; returns (stats dict, per-request status, per-request n_clusters).
+    With ``results`` (a device uint8 tensor) and ``result_offsets`` every request's
+    outputs are copied there (verification mode)."""
+    nb = len(batches)
+    bh = (ctypes.c_void_p * nb)(*[b.handle.value for b in batches])
+    sts = (ctypes.c_void_p * nb)(*[int(s.cuda_stream) for s in streams])
+    ins = (_Digis * len(pool))(*[d.struct() for d in pool])
+    o = ServeOpts(float(rate_hz), int(n_requests), int(budget_bytes), int(n_slots), int(max_batch),
+                  int(n_cpu_threads), int(cpu_task_ns), BATCH_GRAPH if graph else 0, int(seed))
+    st = RunStats()
+    rs = (ctypes.c_int32 * n_requests)()
+    rn = (ctypes.c_uint32 * n_requests)()
+    _check(lib().pxcl_serve(ctx.handle, arena.data_ptr(), arena.numel() * arena.element_size(),
+                            pinned.data_ptr(), pinned.numel() * pinned.element_size(), bh, sts, nb, ins,
+                            len(pool), ctypes.byref(o), ctypes.byref(st), rs, rn,
+                            results.data_ptr() if results is not None else None,
+                            (ctypes.c_uint64 * n_requests)(*result_offsets) if result_offsets is not None
+                            else None), "serve")
+    return st.as_dict(), list(rs), list(rn)
