@@ -1,0 +1,352 @@
+#!/usr/bin/env python3
+"""Benchmark of the pixel-clustering path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload async|plain|batch|serve|stress]
+
+Default workload ("async"): full-size events (1,856 modules of 160x416 pixels,
+~50k digis each) through the non-blocking acquire/produce boundary, 4 host threads
+each with one event in flight and synthetic CPU tasks filling the wait.  A step is
+one event per host thread (4 events).  Inputs are resident in HBM before the timed
+region starts.  One JSON line is printed; ``roofline`` describes the dominant kernel
+(algorithmic bytes per launch / its mean duration, from hipEvents recorded on the
+launch stream during the timed region) and ``cpu_baseline`` the plain CPU oracle on
+a bounded sample of the same events.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+KERNELS = ["segment", "big", "small", "compact"]
+KERNEL_SYMBOLS = {"segment": "k_segment", "big": "k_big", "small": "k_small", "compact": "k_compact"}
+
+
+def event_bytes(n_digis: int, n_kept: int) -> int:
+    """Algorithmic HBM bytes of one event: read the 8 B/digi SoA, write a 4 B per-digi
+    id, 12 B per kept cluster and a 4 B count."""
+    return 8 * n_digis + 4 * n_digis + 12 * n_kept + 4
+
+
+def kernel_src_sha() -> str:
+    p = os.path.join(ROOT, "paper_2004_04334_amd", "csrc", "pxcl_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def roofline(ctx, bytes_per_launch: float, workload: str):
+    ms, cnt = ctx.timing(reset=True)
+    avg = {k: (ms[i] / cnt[i] if cnt[i] else 0.0) for i, k in enumerate(KERNELS)}
+    tot = {k: ms[i] for i, k in enumerate(KERNELS)}
+    dom = max(tot, key=tot.get)
+    t = avg[dom] * 1e-3
+    achieved = bytes_per_launch / t / 1e9 if t > 0 else 0.0
+    pipe = sum(avg.values()) * 1e-3
+    return {
+        "bound": "hbm", "kernel": KERNEL_SYMBOLS[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": load_traffic(workload, dom),
+        "algorithmic_bytes_per_launch": int(bytes_per_launch),
+        "kernel_mean_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
+        "launches": int(max(cnt)),
+        "pipeline_GBps": round(bytes_per_launch / pipe / 1e9, 2) if pipe > 0 else 0.0,
+    }
+
+
+def cpu_baseline(events, seconds: float, unit_events: bool = True):
+    """The oracle as it stands, single-threaded, over the workload's events for about
+    `seconds` of CPU time."""
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    n_ev = n_dg = 0
+    i = 0
+    while time.perf_counter() - t0 < seconds:
+        ev = events[i % len(events)]
+        oracle.cluster_event(ev, 2000)
+        n_ev += 1
+        n_dg += ev["module"].size
+        i += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(n_ev / dt, 2), "unit": "events/s", "cores": 1, "kind": "oracle",
+            "digis_per_s": round(n_dg / dt, 1),
+            "sample": f"{n_ev} events ({n_dg} digis) cycled from the workload's {len(events)} distinct "
+                      f"events, one thread, {dt:.1f} s"}
+
+
+def gen_events(maker, count, **kw):
+    return [maker(i, **kw) for i in range(count)]
+
+
+# ---------------------------------------------------------------------------
+def bench_async(px, torch, args, synth):
+    n_threads = 4
+    evs = gen_events(synth.async_event, 32)
+    ctx = px.Context(1856, 2000)
+    pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
+    cap = max(e["module"].size for e in evs)
+    slots = [px.Event(ctx, cap) for _ in range(n_threads)]
+    streams = [torch.cuda.Stream() for _ in range(n_threads)]
+    kept = []
+    for d in pool:                       # one pass for the kept-cluster counts (bytes per event)
+        px.acquire(slots[0], d)
+        px.wait(slots[0])
+        kept.append(px.produce(slots[0]).n_clusters)
+    px.run_async(ctx, slots, streams, pool, max(1, args.warmup), cpu_task_ns=args.cpu_task_ns)
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = px.run_async(ctx, slots, streams, pool, args.steps, cpu_task_ns=args.cpu_task_ns)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_timing(False)
+    n_ev = st["events"]
+    b_mean = float(np.mean([event_bytes(e["module"].size, k) for e, k in zip(evs, kept)]))
+    rl = roofline(ctx, b_mean, "async")
+    out = {
+        "value": n_ev / wall, "ms_per_step": wall * 1e3 / args.steps,
+        "digis_per_s": st["digis"] / wall,
+        "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
+        "host_blocked_us_per_event": st["blocked_us_per_event"],
+        "cpu_tasks_per_s": st["cpu_tasks_per_s"], "errors": st["errors"],
+        "config": {"workload": "async: 1856 modules x 160x416, ~50k digis/event, 4 host threads x 1 event "
+                               "in flight, synthetic CPU tasks while waiting",
+                   "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
+                   "host_threads": n_threads, "cpu_task_ns": args.cpu_task_ns, "distinct_events": len(evs)},
+        "roofline": rl, "events": evs,
+    }
+    for s in slots:
+        s.close()
+    ctx.close()
+    return out
+
+
+def bench_plain(px, torch, args, synth):
+    evs = gen_events(synth.plain_event, 32)
+    ctx = px.Context(64, 2000)
+    pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
+    slot = px.Event(ctx, max(e["module"].size for e in evs))
+    stream = torch.cuda.Stream()
+    kept = []
+    for d in pool:
+        px.acquire(slot, d)
+        px.wait(slot)
+        kept.append(px.produce(slot).n_clusters)
+    px.run_async(ctx, [slot], [stream], pool, max(1, args.warmup), blocking=True)
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = px.run_async(ctx, [slot], [stream], pool, args.steps, blocking=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_timing(False)
+    b_mean = float(np.mean([event_bytes(e["module"].size, k) for e, k in zip(evs, kept)]))
+    out = {
+        "value": st["events"] / wall, "ms_per_step": wall * 1e3 / args.steps, "digis_per_s": st["digis"] / wall,
+        "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
+        "host_blocked_us_per_event": st["blocked_us_per_event"], "errors": st["errors"],
+        "config": {"workload": "plain: 64 modules x 160x416, 46,912 digis/event, one event per synchronous launch",
+                   "n_modules": 64, "mean_digis": 46912, "distinct_events": len(evs)},
+        "roofline": roofline(ctx, b_mean, "plain"), "events": evs,
+    }
+    slot.close()
+    ctx.close()
+    return out
+
+
+def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_modules=1856):
+    """Graph-replayed batches over `n_copies` device-resident copies of the events (a
+    working set larger than the 256 MB Infinity Cache); each copy has its own batch
+    object and event slots, so the host only waits when it wraps around."""
+    ctx = px.Context(n_modules, 2000)
+    if args.autotune:
+        px.autotune_load(ctx, os.path.join(ROOT, "profiles", "autotune.json"),
+                         int(np.mean([e["module"].size for e in evs])))
+    stream = torch.cuda.Stream()
+    cap = max(e["module"].size for e in evs)
+    groups = []
+    for c in range(n_copies):
+        digis = [px.Digis.from_numpy(e, "cuda") for e in evs]
+        slots = [px.Event(ctx, cap) for _ in range(per_batch)]
+        groups.append((px.Batch(ctx, per_batch), slots, digis))
+    flags = [px.Flag() for _ in range(n_copies)]
+
+    def launch(i):
+        b, slots, digis = groups[i % n_copies]
+        while px.batch_query(b) == px.E_NOT_READY:     # this copy's previous launch
+            time.sleep(0)
+        px.acquire_batch(b, slots, digis, stream, flag=flags[i % n_copies], graph=not args.no_graph)
+
+    def drain():
+        torch.cuda.synchronize()
+        for g in groups:
+            while px.batch_query(g[0]) == px.E_NOT_READY:
+                time.sleep(0)
+
+    for i in range(max(args.warmup, n_copies)):          # also captures every graph
+        launch(i)
+    drain()
+    res = [px.produce(s).n_clusters for s in groups[0][1]]
+    b_batch = float(sum(event_bytes(e["module"].size, k) for e, k in zip(evs, res)))
+    ctx.set_timing(True)
+    for i in range(n_copies):                            # re-capture with timing events
+        launch(i)
+    drain()
+    ctx.timing(reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        launch(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    drain()
+    for b, slots, _ in groups:
+        b.close()
+        for s in slots:
+            s.close()
+    rl = roofline(ctx, b_batch, workload)
+    ctx.set_timing(False)
+    n_dg = sum(e["module"].size for e in evs)
+    out = {
+        "value": per_batch * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
+        "digis_per_s": n_dg * args.steps / wall,
+        "config": {"workload": desc, "n_modules": n_modules, "events_per_launch": per_batch,
+                   "mean_digis": int(n_dg / len(evs)), "device_copies": n_copies,
+                   "kernel_config": list(ctx.kernel_config())},
+        "roofline": rl, "events": evs,
+    }
+    ctx.close()
+    return out
+
+
+def bench_batch(px, torch, args, synth):
+    evs = gen_events(synth.batch_event, 64)
+    return _batched(px, torch, args, evs, 8, 64, "batch",
+                    "batch: 64 events/launch (persistent kernels, captured graph), 1856 modules, "
+                    "10k-120k digis/event, log-normal module occupancy")
+
+
+def bench_stress(px, torch, args, synth):
+    evs = gen_events(synth.stress_event, 16)
+    return _batched(px, torch, args, evs, 4, 16, "stress",
+                    "stress: 16 events/launch of ~320k digis, 16 modules at 20% occupancy with "
+                    "mean-40 clusters, a full-column track and a serpentine per event")
+
+
+def bench_serve(px, torch, args, synth):
+    evs = gen_events(synth.serve_event, 32)
+    ctx = px.Context(1856, 2000)
+    pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
+    arena = torch.empty(16 << 30, dtype=torch.uint8, device="cuda")
+    n_slots, n_b, max_batch = 512, 4, 64
+    pinned = torch.empty(n_slots * 64, dtype=torch.uint8, pin_memory=True)
+    batches = [px.Batch(ctx, max_batch) for _ in range(n_b)]
+    streams = [torch.cuda.Stream() for _ in range(n_b)]
+    common = dict(budget_bytes=16 << 30, n_slots=n_slots, max_batch=max_batch, n_cpu_threads=16,
+                  cpu_task_ns=args.cpu_task_ns, graph=True)
+    # calibration: saturated throughput (all requests arrive at once)
+    cal, _, _ = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=1e9, n_requests=4000, seed=7, **common)
+    sat = cal["events"] / cal["wall_s"]
+    rate = 0.7 * sat
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=rate,
+                               n_requests=args.steps, seed=11, **common)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for b in batches:
+        b.close()
+    b_mean = float(np.mean([event_bytes(evs[r % len(evs)]["module"].size, ncl[r]) for r in range(args.steps)]))
+    n_batches = max(1, st["batches"])
+    rl = roofline(ctx, b_mean * args.steps / n_batches, "serve")
+    ctx.set_timing(False)
+    out = {
+        "value": st["events"] / st["wall_s"], "ms_per_step": st["wall_s"] * 1e3 / args.steps,
+        "digis_per_s": st["digis"] / st["wall_s"],
+        "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
+        "host_blocked_us_per_event": st["blocked_us_per_event"], "cpu_tasks_per_s": st["cpu_tasks_per_s"],
+        "errors": st["errors"], "saturated_events_per_s": sat, "arrival_rate_hz": rate,
+        "config": {"workload": "serve: Poisson arrivals at 0.7x saturated rate, 10k-200k digis/event, "
+                               "16 GB admission budget, continuous batching over 4 streams, 16 CPU threads",
+                   "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
+                   "requests": args.steps, "mean_events_per_launch": round(args.steps / n_batches, 2),
+                   "peak_resident_bytes": st["peak_resident_bytes"]},
+        "roofline": rl, "events": evs,
+    }
+    ctx.close()
+    return out
+
+
+WORKLOADS = {"async": (bench_async, 2000, 100), "plain": (bench_plain, 2000, 100),
+             "batch": (bench_batch, 200, 10), "stress": (bench_stress, 100, 5),
+             "serve": (bench_serve, 20000, 0)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="async")
+    ap.add_argument("--cpu-task-ns", type=int, default=20000)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="batched workloads: plain launches, no captured graph")
+    ap.add_argument("--autotune", action="store_true", help="load the kernel shape from profiles/autotune.json")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              "(events shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    fn, d_steps, d_warm = WORKLOADS[args.workload]
+    args.steps = args.steps or d_steps
+    args.warmup = d_warm if args.warmup is None else args.warmup
+
+    import torch
+    from paper_2004_04334_amd import pxcl as px
+    from paper_2004_04334_amd import synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    px.lib()
+    torch.cuda.set_device(0)
+    r = fn(px, torch, args, synth)
+    evs = r.pop("events")
+    line = {
+        "metric": "events/s + digis/s clustered (frac HBM peak); p50/p99 event latency; host block time",
+        "value": round(r.pop("value"), 2), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r.pop("ms_per_step"), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16/i32", "data": "synthetic",
+    }
+    line.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()})
+    line["device"] = torch.cuda.get_device_name(0)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(evs, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -28,24 +28,26 @@ constexpr u32 MAXB = 128;                // events per batch
 
 // Kernel shapes.
 constexpr u32 A_WG = 256, A_PER = 8, A_CH = A_WG * A_PER;   // segmentation: digis per chunk
-constexpr u32 C_WG = 256, C_CH = 256;                       // compaction: items per chunk
-constexpr u32 K_PER = 8;                                    // digis per thread held in registers
-constexpr u32 DCAP_MIN = 64 * K_PER;                        // smallest in-LDS module capacity
-constexpr u32 L_WG = 1024;                                  // large-module kernel
+constexpr u32 C_WG = 256, C_ITEMS = 32;                     // compaction: items per workgroup
+constexpr u32 K_SMALL = 8;                                  // digis per thread (small-module kernel)
+constexpr u32 B_WG = 512, K_BIG = 32;                       // big-module kernel
+constexpr u32 BIG_RCAP = B_WG * K_BIG;                      // 16384: larger modules use scratch mode
 
 // Per-event control words (u32) at the start of an event workspace.
 enum : u32 {
     CTL_ERR = 0,      // accumulated PXCL_ERRBIT_* of the launch in progress
     CTL_ITEMS = 1,    // number of modules present (work items)
     CTL_NCL = 2,      // kept clusters
-    CTL_LARGE = 3,    // items deferred to the large-module kernel
-    CTL_CTR = 8,      // 8 launch counters when the event is launched on its own
+    CTL_SMALL = 3,    // items for the small-module kernel
+    CTL_BIG = 4,      // items for the big-module kernel
+    CTL_SEGDONE = 5,  // segmentation chunks finished (the last one indexes the event)
+    CTL_CTR = 8,      // launch counters when the event is launched on its own
     CTL_WORDS = 64
 };
-// Launch counters (tickets and exit counts of the four persistent kernels).
-enum : u32 { A_TICK = 0, A_EXIT, B_TICK, B_EXIT, L_TICK, L_EXIT, C_TICK, C_EXIT, N_CTR };
-// Host status block (pinned) written by the last kernel of a launch.
-enum : u32 { HS_EPOCH = 0, HS_ERR = 1, HS_NCL = 2, HS_ITEMS = 3, HS_LARGE = 4, HS_WORDS = 16 };
+// Launch counters: the small-module kernel's ticket.
+enum : u32 { S_TICK = 0, N_CTR = 8 };
+// Host status block (pinned) written by the compaction kernel.
+enum : u32 { HS_EPOCH = 0, HS_ERR = 1, HS_NCL = 2, HS_ITEMS = 3, HS_BIG = 4, HS_WORDS = 16 };
 constexpr u32 HS_BYTES = HS_WORDS * 4;
 
 // Error bits (same values as PXCL_ERRBIT_*).
@@ -61,7 +63,7 @@ struct EventDesc {
     u32* hstat;      // host status block (pinned, device-accessible)
     u32 n;           // digis
     u32 cap;         // workspace capacity in digis
-    u32 epoch;       // launch tag for look-back status words
+    u32 epoch;       // launch tag of the segment words
     u32 pad;
 };
 static_assert(sizeof(EventDesc) == 64, "EventDesc is 64 bytes");
@@ -75,26 +77,29 @@ struct LaunchArgs {
     u32* ctr;           // N_CTR launch counters (device)
     u32 n_modules;
     u32 charge_cut;
+    u32 dcap;           // largest module (digis) the small-module kernel takes
+    u32 pad;
     EventDesc single;
 };
 
 PXCL_HD inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Byte offsets of the arrays of an event workspace with capacity N digis.
+// Byte offsets of the arrays of an event workspace with capacity N digis and M
+// modules per event.
 struct EvLayout {
     size_t ctl, in_mod, in_row, in_col, in_adc;
     size_t digi, id, charge, size;           // outputs
     size_t tid, tcharge, tsize;              // cluster records before compaction
+    size_t seg;                              // per module: launch tag << 32 | first digi
     size_t item_start, item_mod, item_kept;  // modules present (work items)
-    size_t large;                            // items deferred to the large-module kernel
-    size_t lb_a, lb_c;                       // look-back status words
+    size_t small, big;                       // item lists of the two clustering kernels
     size_t total;
 };
 
-PXCL_HD inline EvLayout ev_layout(u32 N) {
+PXCL_HD inline EvLayout ev_layout(u32 N, u32 M) {
     EvLayout L;
     size_t o = 0;
-    const size_t n = N;
+    const size_t n = N, m = M;
     L.ctl = o;        o = al256(o + CTL_WORDS * 4);
     L.in_mod = o;     o = al256(o + 2 * n);
     L.in_row = o;     o = al256(o + 2 * n);
@@ -107,19 +112,15 @@ PXCL_HD inline EvLayout ev_layout(u32 N) {
     L.tid = o;        o = al256(o + 4 * n);
     L.tcharge = o;    o = al256(o + 4 * n);
     L.tsize = o;      o = al256(o + 4 * n);
-    L.item_start = o; o = al256(o + 4 * (n + 1));
-    L.item_mod = o;   o = al256(o + 4 * n);
-    L.item_kept = o;  o = al256(o + 4 * n);
-    L.large = o;      o = al256(o + 4 * (n / DCAP_MIN + 2));
-    L.lb_a = o;       o = al256(o + 8 * ((n + A_CH - 1) / A_CH + 1));
-    L.lb_c = o;       o = al256(o + 8 * ((n + C_CH - 1) / C_CH + 1));
+    L.seg = o;        o = al256(o + 8 * m);
+    L.item_start = o; o = al256(o + 4 * (m + 1));
+    L.item_mod = o;   o = al256(o + 4 * m);
+    L.item_kept = o;  o = al256(o + 4 * m);
+    L.small = o;      o = al256(o + 4 * m);
+    L.big = o;        o = al256(o + 4 * m);
     L.total = o;
     return L;
 }
-
-// Bytes that must be zeroed when a workspace is bound: control words and look-back
-// status words (everything else is written before it is read).
-PXCL_HD inline size_t ev_ctl_bytes() { return CTL_WORDS * 4; }
 
 // Batch workspace: counters then the header.
 constexpr size_t BW_CTR = 0;

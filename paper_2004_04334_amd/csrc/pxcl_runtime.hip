@@ -26,11 +26,11 @@ bool cluster_config_valid(u32 wg, u32 mpw);
 u32 cluster_capacity(u32 wg, u32 mpw);
 int occupancy_segment();
 int occupancy_cluster(u32 wg, u32 mpw);
-int occupancy_large();
+int occupancy_big();
 int occupancy_compact();
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s);
-hipError_t launch_cluster(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s);
-hipError_t launch_large(const LaunchArgs& a, u32 grid, hipStream_t s);
+hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s);
+hipError_t launch_big(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
 }  // namespace pxcl
 
@@ -117,6 +117,9 @@ struct pxcl_batch {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     u32 g_wg = 0, g_mpw = 0;
+    bool g_timed = false;
+    hipEvent_t tev[5] = {};
+    bool timed = false;       // the launch in flight records per-kernel events
 };
 
 // ---------------------------------------------------------------------------
@@ -125,44 +128,42 @@ struct pxcl_batch {
 namespace {
 
 struct Grids {
-    u32 a, b, l, c;
+    u32 a, b, s, c;   // segment, big, small, compact
 };
 
-// Grids of the four persistent kernels.  `bound_items` bounds the number of work
-// items (modules present) of the launch, `digis` the total digis; 0 = unknown (a
-// captured graph replays with any input), then every kernel gets a full device.
-Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 bound_items, bool full) {
+// Grids of the four kernels.  `digis` and `items` bound the launch's digis and work
+// items (modules present); with `full` (a captured graph replays with any input)
+// every kernel gets what fits on the device at once.
+Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 items, u32 k, bool full) {
     Grids g;
     const u64 ncu = ctx->n_cu;
     const u64 fa = ncu * (u64)ctx->occ_a;
-    const u64 fb = ncu * (u64)occupancy_cluster(wg, mpw);
-    const u64 fl = ncu * (u64)ctx->occ_l;
+    const u64 fb = ncu * (u64)ctx->occ_l;
+    const u64 fs = ncu * (u64)occupancy_cluster(wg, mpw);
     const u64 fc = ncu * (u64)ctx->occ_c;
     if (full) {
-        g.a = u32(fa); g.b = u32(fb); g.l = u32(fl); g.c = u32(fc);
+        g.a = u32(fa); g.b = u32(fb); g.s = u32(fs); g.c = u32(fc);
         return g;
     }
     const u32 dcap = cluster_capacity(wg, mpw);
-    g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + A_CH - 1) / A_CH)));
-    g.b = u32(std::max<u64>(1, std::min<u64>(fb, (bound_items + mpw - 1) / mpw)));
-    g.l = u32(std::max<u64>(1, std::min<u64>(fl, digis / (dcap + 1))));
-    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (bound_items + C_CH - 1) / C_CH)));
+    g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + A_CH - 1) / A_CH + k)));
+    g.b = u32(std::max<u64>(1, std::min<u64>(fb, digis / (dcap + 1))));
+    g.s = u32(std::max<u64>(1, std::min<u64>(fs, (items + mpw - 1) / mpw)));
+    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (items + C_ITEMS - 1) / C_ITEMS + k)));
     return g;
 }
 
-hipError_t launch_all(pxcl_ctx* ctx, const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipStream_t s,
-                      hipEvent_t* tev) {
+hipError_t launch_all(const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipStream_t s, hipEvent_t* tev) {
     hipError_t e;
     if (tev && (e = hipEventRecord(tev[0], s)) != hipSuccess) return e;
     if ((e = launch_segment(a, g.a, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
-    if ((e = launch_cluster(wg, mpw, a, g.b, s)) != hipSuccess) return e;
+    if ((e = launch_big(a, g.b, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[2], s)) != hipSuccess) return e;
-    if ((e = launch_large(a, g.l, s)) != hipSuccess) return e;
+    if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[3], s)) != hipSuccess) return e;
     if ((e = launch_compact(a, g.c, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[4], s)) != hipSuccess) return e;
-    (void)ctx;
     return hipSuccess;
 }
 
@@ -176,7 +177,7 @@ bool digis_ok(const pxcl_digis* in) {
 // Stage host digis into the slot (async copies; one copy if the four arrays are
 // contiguous in the order module,row,col,adc) and describe the event.
 hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventDesc* d) {
-    const EvLayout L = ev_layout(ev->cap);
+    const EvLayout L = ev_layout(ev->cap, ev->ctx->n_modules);
     d->ws = ev->ws;
     d->hstat = ev->hs_dev;
     d->n = in->n;
@@ -270,7 +271,7 @@ extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** ou
         c->arch = a.substr(0, a.find(':'));
     }
     c->occ_a = occupancy_segment();
-    c->occ_l = occupancy_large();
+    c->occ_l = occupancy_big();
     c->occ_c = occupancy_compact();
     hipSetDevice(prev);
     *out = c;
@@ -320,7 +321,7 @@ extern "C" int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum, uint64_t* launches
 // ---------------------------------------------------------------------------
 extern "C" size_t pxcl_event_workspace_bytes(const pxcl_ctx* ctx, uint32_t max_digis) {
     if (!ctx || max_digis == 0 || max_digis > PXCL_MAX_EVENT_DIGIS) return 0;
-    return ev_layout(max_digis).total;
+    return ev_layout(max_digis, ctx->n_modules).total;
 }
 
 extern "C" size_t pxcl_event_pinned_bytes(const pxcl_ctx* ctx) { return ctx ? HS_BYTES : 0; }
@@ -331,7 +332,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     if (max_digis == 0 || max_digis > PXCL_MAX_EVENT_DIGIS) return PXCL_E_INVAL;
     if ((reinterpret_cast<uintptr_t>(d_ws) & 255u) || (reinterpret_cast<uintptr_t>(h_pinned) & 63u))
         return PXCL_E_INVAL;
-    const EvLayout L = ev_layout(max_digis);
+    const EvLayout L = ev_layout(max_digis, ctx->n_modules);
     if (ws_bytes < L.total || pinned_bytes < HS_BYTES) return PXCL_E_CAPACITY;
     void* hdev = nullptr;
     if (hipHostGetDevicePointer(&hdev, h_pinned, 0) != hipSuccess || !hdev) {
@@ -353,8 +354,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     hipError_t e = hipEventCreateWithFlags(&ev->done_ev, hipEventDisableTiming);
     for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev->tev[i]);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
-    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.lb_a, 0, L.lb_c - L.lb_a, s);
-    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.lb_c, 0, L.total - L.lb_c, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.seg, 0, L.item_start - L.seg, s);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (ev->done_ev) hipEventDestroy(ev->done_ev);
@@ -399,14 +399,16 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
     LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.hdr = nullptr;
-    a.ctr = reinterpret_cast<u32*>(ev->ws + ev_layout(ev->cap).ctl) + CTL_CTR;
+    a.ctr = reinterpret_cast<u32*>(ev->ws + ev_layout(ev->cap, ctx->n_modules).ctl) + CTL_CTR;
     a.n_modules = ctx->n_modules;
     a.charge_cut = ctx->charge_cut;
+    a.dcap = cluster_capacity(wg, mpw);
     hipError_t e = make_desc(ev, in, s, &a.single);
     const u64 items = std::min<u64>(in->n, (u64)ctx->n_modules);
-    const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), false);
-    if (e == hipSuccess) e = launch_all(ctx, a, g, wg, mpw, s, timed ? ev->tev : nullptr);
+    const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, false);
+    if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) e = hipLaunchHostFunc(s, event_done_hostfn, ev);
     if (prev != ctx->device) hipSetDevice(prev);
@@ -427,17 +429,21 @@ extern "C" int pxcl_query(const pxcl_event* ev) {
     return PXCL_E_INVAL;
 }
 
+static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev) {
+    float ms[4];
+    for (int i = 0; i < 4; ++i)
+        if (hipEventElapsedTime(&ms[i], tev[i], tev[i + 1]) != hipSuccess) { (void)hipGetLastError(); return; }
+    std::lock_guard<std::mutex> g(ctx->tmu);
+    for (int i = 0; i < 4; ++i) {
+        ctx->tsum[i] += ms[i];
+        ctx->tcnt[i] += 1;
+    }
+}
+
 static void collect_timing(pxcl_event* ev) {
     if (!ev->timed) return;
     ev->timed = false;
-    float ms[4];
-    for (int i = 0; i < 4; ++i)
-        if (hipEventElapsedTime(&ms[i], ev->tev[i], ev->tev[i + 1]) != hipSuccess) return;
-    std::lock_guard<std::mutex> g(ev->ctx->tmu);
-    for (int i = 0; i < 4; ++i) {
-        ev->ctx->tsum[i] += ms[i];
-        ev->ctx->tcnt[i] += 1;
-    }
+    add_timing(ev->ctx, ev->tev);
 }
 
 extern "C" int pxcl_produce(pxcl_event* ev, pxcl_clusters* out) {
@@ -446,7 +452,7 @@ extern "C" int pxcl_produce(pxcl_event* ev, pxcl_clusters* out) {
     if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
     if (st != ST_DONE) return PXCL_E_INVAL;
     collect_timing(ev);
-    const EvLayout L = ev_layout(ev->cap);
+    const EvLayout L = ev_layout(ev->cap, ev->ctx->n_modules);
     out->status = ev->status;
     out->err_bits = ev->err_bits;
     out->n_clusters = ev->ncl;
@@ -510,11 +516,13 @@ extern "C" int pxcl_batch_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     hipGetDevice(&prev);
     hipSetDevice(ctx->device);
     hipError_t e = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming);
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&b->tev[i]);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemsetAsync(b->ws, 0, BW_HDR, static_cast<hipStream_t>(stream));
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (b->done_ev) hipEventDestroy(b->done_ev);
+        for (int i = 0; i < 5; ++i) if (b->tev[i]) hipEventDestroy(b->tev[i]);
         if (b->cap_stream) hipStreamDestroy(b->cap_stream);
         delete b;
         return PXCL_E_HIP;
@@ -534,37 +542,40 @@ static void drop_graph(pxcl_batch* b) {
 extern "C" int pxcl_batch_unbind(pxcl_batch* b) {
     if (!b) return PXCL_E_INVAL;
     if (b->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+    if (b->timed) { b->timed = false; add_timing(b->ctx, b->tev); }
     drop_graph(b);
     hipEventDestroy(b->done_ev);
+    for (int i = 0; i < 5; ++i) hipEventDestroy(b->tev[i]);
     hipStreamDestroy(b->cap_stream);
     b->ctx->bound.fetch_sub(1);
     delete b;
     return PXCL_OK;
 }
 
-static LaunchArgs batch_args(pxcl_batch* b) {
+static LaunchArgs batch_args(pxcl_batch* b, u32 wg, u32 mpw) {
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
     a.hdr = reinterpret_cast<const u32*>(b->ws + BW_HDR);
     a.ctr = reinterpret_cast<u32*>(b->ws + BW_CTR);
     a.n_modules = b->ctx->n_modules;
     a.charge_cut = b->ctx->charge_cut;
+    a.dcap = cluster_capacity(wg, mpw);
     return a;
 }
 
 // Capture the per-batch pipeline (header copy + four kernels, full grids) once per
 // kernel configuration; replays read k and the event descriptors from the header.
-static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw) {
-    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw) return hipSuccess;
+static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, bool timed) {
+    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw && b->g_timed == timed) return hipSuccess;
     drop_graph(b);
     pxcl_ctx* ctx = b->ctx;
-    const LaunchArgs a = batch_args(b);
-    const Grids g = grids_for(ctx, wg, mpw, 0, 0, true);
+    const LaunchArgs a = batch_args(b, wg, mpw);
+    const Grids g = grids_for(ctx, wg, mpw, 0, 0, 0, true);
     hipStream_t cs = b->cap_stream;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t e2 = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(b->max_events), hipMemcpyHostToDevice, cs);
-    if (e2 == hipSuccess) e2 = launch_all(ctx, a, g, wg, mpw, cs, nullptr);
+    if (e2 == hipSuccess) e2 = launch_all(a, g, wg, mpw, cs, timed ? b->tev : nullptr);
     e = hipStreamEndCapture(cs, &b->graph);
     if (e2 != hipSuccess) { if (b->graph) hipGraphDestroy(b->graph); b->graph = nullptr; return e2; }
     if (e != hipSuccess) return e;
@@ -572,6 +583,7 @@ static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw) {
     if (e != hipSuccess) { drop_graph(b); return e; }
     b->g_wg = wg;
     b->g_mpw = mpw;
+    b->g_timed = timed;
     return hipSuccess;
 }
 
@@ -600,6 +612,8 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
     const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
+    if (b->timed) { b->timed = false; add_timing(ctx, b->tev); }   // the previous launch is complete
+    const bool timed = ctx->timing.load() != 0;
     b->k = k;
     b->cb = cb;
     b->user = user;
@@ -626,13 +640,13 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     }
     if (e == hipSuccess) {
         if (flags & PXCL_BATCH_GRAPH) {
-            e = ensure_graph(b, wg, mpw);
+            e = ensure_graph(b, wg, mpw, timed);
             if (e == hipSuccess) e = hipGraphLaunch(b->gexec, s);
         } else {
-            const LaunchArgs a = batch_args(b);
+            const LaunchArgs a = batch_args(b, wg, mpw);
             e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
-            const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), false);
-            if (e == hipSuccess) e = launch_all(ctx, a, g, wg, mpw, s, nullptr);
+            const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), k, false);
+            if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? b->tev : nullptr);
         }
     }
     if (e == hipSuccess) e = hipEventRecord(b->done_ev, s);
@@ -644,6 +658,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         b->state.store(ST_IDLE, std::memory_order_release);
         return PXCL_E_HIP;
     }
+    b->timed = timed;
     return PXCL_OK;
 }
 
@@ -693,7 +708,7 @@ namespace pxcl {
 int event_rebind(pxcl_event* ev, void* d_ws, size_t ws_bytes, uint32_t max_digis, hipStream_t s) {
     if (!ev || !d_ws || max_digis == 0 || max_digis > PXCL_MAX_EVENT_DIGIS) return PXCL_E_INVAL;
     if (ev->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
-    const EvLayout L = ev_layout(max_digis);
+    const EvLayout L = ev_layout(max_digis, ev->ctx->n_modules);
     if (ws_bytes < L.total) return PXCL_E_CAPACITY;
     ev->ws = static_cast<u8*>(d_ws);
     ev->ws_bytes = ws_bytes;

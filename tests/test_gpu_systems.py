@@ -1,0 +1,238 @@
+"""Boundary semantics and the systems forms on the device: non-blocking acquire,
+exactly-once callbacks, synchronous error codes, batches and captured graphs, the
+asynchronous driver, serving with continuous batching, the autotuner.  Every result
+is checked bit-exactly against the oracle, alone / in a batch / in the serving mix."""
+from __future__ import annotations
+
+import json
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_04334_amd import synth
+from tests.gpu_util import compare, run_events
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def px():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_04334_amd import pxcl
+    pxcl.lib()
+    oracle.build()
+    return pxcl
+
+
+@pytest.fixture(scope="module")
+def batch_events():
+    return [synth.batch_event(i) for i in range(8)]
+
+
+def test_acquire_returns_before_completion(px):
+    import torch
+    ev = synth.stress_event(2)
+    ctx = px.Context(1856)
+    slot = px.Event(ctx, ev["module"].size)
+    d = px.Digis.from_numpy(ev, "cuda")
+    s = torch.cuda.Stream()
+    calls = []
+    done = threading.Event()
+
+    def cb(status):
+        calls.append(status)
+        done.set()
+
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(200_000_000)          # keep the stream busy (~0.1 s)
+    t0 = time.perf_counter()
+    px.acquire(slot, d, s, done_cb=cb)
+    t_acq = time.perf_counter() - t0
+    assert px.query(slot) == px.E_NOT_READY
+    with pytest.raises(px.PxclError) as ei:
+        px.produce(slot)
+    assert ei.value.code == px.E_NOT_READY
+    with pytest.raises(px.PxclError) as ei:      # one event in flight per slot
+        px.acquire(slot, d, s)
+    assert ei.value.code == px.E_BUSY
+    assert done.wait(30)
+    px.wait(slot)
+    time.sleep(0.05)
+    assert calls == [0], "done_cb fires exactly once, with the status"
+    assert t_acq < 0.02, f"acquire blocked for {t_acq * 1e3:.2f} ms"
+    compare(px.produce(slot).numpy(), oracle.cluster_event(ev, 2000), "stress after sleep")
+    slot.close()
+    ctx.close()
+
+
+def test_synchronous_errors(px):
+    ctx = px.Context(64)
+    slot = px.Event(ctx, 100)
+    ev = synth.plain_event(0)
+    d = px.Digis.from_numpy(ev, "cuda")
+    with pytest.raises(px.PxclError) as ei:
+        px.acquire(slot, d)
+    assert ei.value.code == px.E_CAPACITY
+    with pytest.raises(px.PxclError) as ei:
+        px.produce(slot)                       # never acquired
+    assert ei.value.code == px.E_INVAL
+    with pytest.raises(px.PxclError) as ei:
+        ctx.close()                            # a slot is still bound
+    assert ei.value.code == px.E_BUSY
+    slot.close()
+    ctx.close()
+
+
+def test_two_streams_overlap(px):
+    import torch
+    evs = [synth.async_event(20), synth.async_event(21)]
+    ctx = px.Context(1856)
+    slots = [px.Event(ctx, e["module"].size) for e in evs]
+    ds = [px.Digis.from_numpy(e, "cuda") for e in evs]
+    ss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    flags = [px.Flag(), px.Flag()]
+    for sl, d, s, f in zip(slots, ds, ss, flags):
+        px.acquire(sl, d, s, flag=f)
+    for sl in slots:
+        px.wait(sl)
+    for i, (sl, e) in enumerate(zip(slots, evs)):
+        compare(px.produce(sl).numpy(), oracle.cluster_event(e, 2000), f"stream {i}")
+        sl.close()
+    ctx.close()
+
+
+def test_batch_identity_alone_batch_graph(px, batch_events):
+    import torch
+    ctx = px.Context(1856)
+    alone = run_events(px, ctx, batch_events)
+    refs = [oracle.cluster_event(e, 2000) for e in batch_events]
+    for i, (a, r) in enumerate(zip(alone, refs)):
+        compare(a, r, f"alone {i}")
+    b = px.Batch(ctx, 16)
+    slots = [px.Event(ctx, max(e["module"].size for e in batch_events)) for _ in range(8)]
+    res = run_events(px, ctx, batch_events, batch=b, slots=slots)
+    for i, (x, a) in enumerate(zip(res, alone)):
+        compare(x, a, f"batch vs alone {i}")
+    # graph replays: different subsets and orders, eager work in between
+    for rep, order in enumerate([[0, 1, 2, 3, 4, 5, 6, 7], [7, 2, 5], [3], [6, 5, 4, 3, 2, 1, 0, 7]]):
+        sub = [batch_events[j] for j in order]
+        res = run_events(px, ctx, sub, batch=b, graph=True, slots=[slots[j] for j in range(len(order))])
+        torch.ones(1000, device="cuda").sum().item()
+        for j, x in zip(order, res):
+            compare(x, alone[j], f"graph replay {rep} event {j}")
+    for s in slots:
+        s.close()
+    b.close()
+    ctx.close()
+
+
+def test_full_batch_of_64(px):
+    """Batching configuration at full size: 64 events, one captured-graph launch."""
+    evs = [synth.batch_event(100 + i) for i in range(64)]
+    ctx = px.Context(1856)
+    b = px.Batch(ctx, 64)
+    res = run_events(px, ctx, evs, batch=b, graph=True)
+    for i, (r, e) in enumerate(zip(res, evs)):
+        compare(r, oracle.cluster_event(e, 2000), f"batch64 ev {i}")
+    b.close()
+    ctx.close()
+
+
+def test_full_stress_batch_of_16(px):
+    """Stress configuration at full size: 16 events of ~320k digis in one launch."""
+    evs = [synth.stress_event(i) for i in range(16)]
+    ctx = px.Context(1856)
+    b = px.Batch(ctx, 16)
+    res = run_events(px, ctx, evs, batch=b, graph=True)
+    for i, (r, e) in enumerate(zip(res, evs)):
+        compare(r, oracle.cluster_event(e, 2000), f"stress ev {i}")
+    b.close()
+    ctx.close()
+
+
+def test_async_driver(px):
+    import torch
+    pool_np = [synth.async_event(30 + i) for i in range(6)]
+    ctx = px.Context(1856)
+    pool = [px.Digis.from_numpy(e, "cuda") for e in pool_np]
+    slots = [px.Event(ctx, 60000) for _ in range(4)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    st = px.run_async(ctx, slots, streams, pool, events_per_thread=25, cpu_task_ns=20000)
+    assert st["events"] == 100 and st["errors"] == 0
+    assert st["cpu_tasks"] > 0
+    assert st["blocked_us_per_event"] < st["lat_p50_us"]
+    blk = px.run_async(ctx, slots, streams, pool, events_per_thread=10, blocking=True)
+    assert blk["errors"] == 0 and blk["cpu_tasks"] == 0
+    # each thread's last event is still readable and exact
+    for t, sl in enumerate(slots):
+        idx = (t + 9 * 4) % len(pool_np)
+        compare(px.produce(sl).numpy(), oracle.cluster_event(pool_np[idx], 2000), f"thread {t}")
+    for s in slots:
+        s.close()
+    ctx.close()
+
+
+def test_serving_mix_identical_to_alone(px):
+    import torch
+    pool_np = [synth.serve_event(i) for i in range(12)]
+    refs = [oracle.cluster_event(e, 2000) for e in pool_np]
+    ctx = px.Context(1856)
+    pool = [px.Digis.from_numpy(e, "cuda") for e in pool_np]
+    n_req = 48
+    budget = 64 << 20                                 # small, so that admission binds
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    pinned = torch.empty(32 * 64, dtype=torch.uint8, pin_memory=True)
+    batches = [px.Batch(ctx, 16) for _ in range(3)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    sizes = [pool_np[r % len(pool_np)]["module"].size for r in range(n_req)]
+    offs = np.concatenate([[0], np.cumsum([16 * n for n in sizes])]).astype(np.int64)
+    results = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+    st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=20000.0, n_requests=n_req,
+                               budget_bytes=budget, n_slots=32, max_batch=16, n_cpu_threads=4,
+                               cpu_task_ns=10000, graph=True, seed=3, results=results,
+                               result_offsets=offs[:-1].tolist())
+    assert st["errors"] == 0 and st["events"] == n_req
+    assert st["peak_resident_bytes"] <= budget
+    assert st["max_inflight"] > 1, "requests overlap on the device"
+    host = results.cpu().numpy()
+    for r in range(n_req):
+        ref = refs[r % len(pool_np)]
+        n, k = sizes[r], int(ncl[r])
+        assert status[r] == 0 and k == ref["n_clusters"]
+        blob = host[offs[r]: offs[r] + 16 * n].view(np.int32)
+        got = {"status": 0, "n_clusters": k, "digi": blob[:n], "id": blob[n:n + k],
+               "charge": blob[2 * n:2 * n + k], "size": blob[3 * n:3 * n + k]}
+        compare(got, ref, f"served request {r}")
+    for b in batches:
+        b.close()
+    ctx.close()
+
+
+def test_autotune_and_cache(px, batch_events, tmp_path):
+    ctx = px.Context(1856)
+    b = px.Batch(ctx, 8)
+    slots = [px.Event(ctx, max(e["module"].size for e in batch_events)) for _ in batch_events]
+    digis = [px.Digis.from_numpy(e, "cuda") for e in batch_events]
+    path = str(tmp_path / "tune.json")
+    times = px.autotune(ctx, b, slots, digis, reps=2, cache_path=path)
+    assert len(times) == 9 and all(t > 0 for t in times.values())
+    best = min(times, key=times.get)
+    assert ctx.kernel_config() == best
+    data = json.load(open(path))
+    assert list(data.values()) == [list(best)]
+    ctx.set_kernel_config(64, 1)
+    mean = int(np.mean([e["module"].size for e in batch_events]))
+    assert px.autotune_load(ctx, path, mean)
+    assert ctx.kernel_config() == best
+    res = run_events(px, ctx, batch_events, batch=b, slots=slots)
+    for i, (r, e) in enumerate(zip(res, batch_events)):
+        compare(r, oracle.cluster_event(e, 2000), f"tuned {i}")
+    for s in slots:
+        s.close()
+    b.close()
+    ctx.close()
