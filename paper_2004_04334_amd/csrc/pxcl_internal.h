@@ -28,7 +28,7 @@ constexpr u32 MAXB = 128;                // events per batch
 
 // Kernel shapes.
 constexpr u32 A_WG = 256, A_PER = 8, A_CH = A_WG * A_PER;   // segmentation: digis per chunk
-constexpr u32 C_WG = 256, C_ITEMS = 32;                     // compaction: items per workgroup
+constexpr u32 C_WG = 256, C_ITEMS = 8;                      // compaction: items per workgroup
 constexpr u32 K_SMALL = 8;                                  // digis per thread (small-module kernel)
 constexpr u32 B_WG = 512, K_BIG = 32;                       // big-module kernel
 constexpr u32 BIG_RCAP = B_WG * K_BIG;                      // 16384: larger modules use scratch mode
@@ -68,6 +68,11 @@ struct EventDesc {
 };
 static_assert(sizeof(EventDesc) == 64, "EventDesc is 64 bytes");
 
+// A work-list entry: item index (module order), first digi, digis, module id.
+struct ItemEntry {
+    u32 it, st, n, mod;
+};
+
 // Batch header in device memory: u32 k, padding to 64 bytes, then EventDesc[k].
 constexpr u32 HDR_EV_OFFSET = 64;
 PXCL_HD inline size_t header_bytes(u32 max_events) { return HDR_EV_OFFSET + size_t(max_events) * sizeof(EventDesc); }
@@ -91,8 +96,8 @@ struct EvLayout {
     size_t digi, id, charge, size;           // outputs
     size_t tid, tcharge, tsize;              // cluster records before compaction
     size_t seg;                              // per module: launch tag << 32 | first digi
-    size_t item_start, item_mod, item_kept;  // modules present (work items)
-    size_t small, big;                       // item lists of the two clustering kernels
+    size_t item_start, item_kept;            // modules present (work items), in module order
+    size_t small, big;                       // work lists of the two clustering kernels (ItemEntry)
     size_t total;
 };
 
@@ -114,10 +119,9 @@ PXCL_HD inline EvLayout ev_layout(u32 N, u32 M) {
     L.tsize = o;      o = al256(o + 4 * n);
     L.seg = o;        o = al256(o + 8 * m);
     L.item_start = o; o = al256(o + 4 * (m + 1));
-    L.item_mod = o;   o = al256(o + 4 * m);
     L.item_kept = o;  o = al256(o + 4 * m);
-    L.small = o;      o = al256(o + 4 * m);
-    L.big = o;        o = al256(o + 4 * m);
+    L.small = o;      o = al256(o + 16 * m);
+    L.big = o;        o = al256(o + 16 * m);
     L.total = o;
     return L;
 }

@@ -232,49 +232,81 @@ __device__ __forceinline__ void link_right(u32* par, const u32* bm, const u16* r
 // ---------------------------------------------------------------------------
 // segment
 // ---------------------------------------------------------------------------
-// Turn the event's per-module table into the ordered item list and the two class
-// lists.  Run by one whole workgroup of A_WG threads.
-__device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc& E, const EvLayout& L, u32* wsum) {
+constexpr u32 IDX_PER = 8, IDX_SPAN = A_WG * IDX_PER;   // modules per thread / per pass
+
+// Turn the event's per-module table into the ordered item list and the two work
+// lists.  Run by one whole workgroup of A_WG threads; s_st holds IDX_SPAN + 1 words.
+__device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc& E, const EvLayout& L,
+                                            u32* wsum, u32* s_st, u32* s_cnt) {
     const u32 tid = threadIdx.x;
     const u32 M = a.n_modules, n = E.n;
     const u64* seg = ws_ptr<const u64>(E, L.seg);
     u32* item_start = ws_ptr<u32>(E, L.item_start);
-    u32* item_mod = ws_ptr<u32>(E, L.item_mod);
     u32* ctl = ws_ptr<u32>(E, L.ctl);
+    ItemEntry* small = ws_ptr<ItemEntry>(E, L.small);
+    ItemEntry* big = ws_ptr<ItemEntry>(E, L.big);
+    const bool one_pass = M <= IDX_SPAN;
+    // pass 1: modules present, in module order (one load round per IDX_SPAN modules)
     u32 items = 0;
-    for (u32 base = 0; base < M; base += A_WG) {
-        const u32 m = base + tid;
-        u64 v = 0;
-        if (m < M) v = ld_ag64(&seg[m]);
-        const bool act = m < M && u32(v >> 32) == E.epoch;
-        u32 tot;
-        const u32 ex = group_excl_scan<A_WG>(act ? 1u : 0u, tid, wsum, tot);
-        if (act) {
-            st_ag(&item_start[items + ex], min(u32(v), n));
-            st_ag(&item_mod[items + ex], m);
+    for (u32 base = 0; base < M; base += IDX_SPAN) {
+        u64 v[IDX_PER];
+#pragma unroll
+        for (u32 j = 0; j < IDX_PER; ++j) {
+            const u32 m = base + tid * IDX_PER + j;
+            v[j] = m < M ? ld_ag64(&seg[m]) : 0ull;
         }
+        u32 flags = 0;
+#pragma unroll
+        for (u32 j = 0; j < IDX_PER; ++j)
+            if (base + tid * IDX_PER + j < M && u32(v[j] >> 32) == E.epoch) flags |= 1u << j;
+        u32 tot;
+        u32 r = items + group_excl_scan<A_WG>(__popc(flags), tid, wsum, tot);
+#pragma unroll
+        for (u32 j = 0; j < IDX_PER; ++j)
+            if (flags & (1u << j)) {
+                const u32 st = min(u32(v[j]), n);
+                st_ag(&item_start[r], st);
+                if (one_pass) {
+                    s_st[r] = st;
+                    s_cnt[r] = base + tid * IDX_PER + j;   // module id
+                }
+                ++r;
+            }
         items += tot;
     }
     if (tid == 0) {
         st_ag(&item_start[items], n);
         st_ag(&ctl[CTL_ITEMS], items);
+        if (one_pass) s_st[items] = n;
     }
     wait_all_mem();
     lds_barrier();
-    u32* small = ws_ptr<u32>(E, L.small);
-    u32* big = ws_ptr<u32>(E, L.big);
+    // pass 2: split into small and big modules.  A module whose start does not
+    // increase (module ids out of order, already flagged) gets no entry.
     u32 ns = 0, nb = 0;
     for (u32 base = 0; base < items; base += A_WG) {
         const u32 i = base + tid;
-        u32 cls = 0;   // 1 small, 2 big
+        u32 cls = 0, s0 = 0, s1 = 0, m = 0;   // cls: 1 small, 2 big
         if (i < items) {
-            const u32 s0 = ld_ag(&item_start[i]), s1 = ld_ag(&item_start[i + 1]);
-            if (s1 > s0) cls = (s1 - s0 <= a.dcap) ? 1u : 2u;   // starts out of order: no item
+            if (one_pass) {
+                s0 = s_st[i];
+                s1 = s_st[i + 1];
+                m = s_cnt[i];
+            } else {
+                s0 = ld_ag(&item_start[i]);
+                s1 = ld_ag(&item_start[i + 1]);
+                m = 0xFFFFFFFFu;
+            }
+            if (s1 > s0) cls = (s1 - s0 <= a.dcap) ? 1u : 2u;
         }
         u32 tot;
         const u32 ex = group_excl_scan<A_WG>((cls == 1 ? 1u : 0u) | (cls == 2 ? 1u << 16 : 0u), tid, wsum, tot);
-        if (cls == 1) small[ns + (ex & 0xFFFFu)] = i;
-        if (cls == 2) big[nb + (ex >> 16)] = i;
+        if (cls) {
+            if (m == 0xFFFFFFFFu) m = E.module[s0];   // module id from its first digi
+            const ItemEntry ent{i, s0, s1 - s0, m};
+            if (cls == 1) small[ns + (ex & 0xFFFFu)] = ent;
+            else big[nb + (ex >> 16)] = ent;
+        }
         ns += tot & 0xFFFFu;
         nb += tot >> 16;
     }
@@ -288,6 +320,8 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
 __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
     __shared__ u32 s_pref[MAXB + 1];
     __shared__ u32 s_wsum[A_WG / 64];
+    __shared__ u32 s_st[IDX_SPAN + 1];
+    __shared__ u32 s_md[IDX_SPAN];
     __shared__ u32 s_err, s_last;
     const u32 tid = threadIdx.x;
     const u32 k = num_events(a);
@@ -329,7 +363,7 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
             s_last = (atomicAdd(&ctl[CTL_SEGDONE], 1u) == chunks - 1) ? 1u : 0u;
         }
         lds_barrier();
-        if (s_last) index_event(a, E, L, s_wsum);
+        if (s_last) index_event(a, E, L, s_wsum, s_st, s_md);
         lds_barrier();
     }
 }
@@ -356,12 +390,10 @@ struct Item {
     bool ok;
 };
 
-constexpr u32 BADPIX = 0xFFFFFFFEu;          // a digi whose row or column is out of range
-
-// Linear pixel index (or NOPIX / BADPIX) and ADC of the module's digis j = lt + q*G.
+// Issue the loads of the module's digis j = lt + q*G (raw row, col, adc); the values
+// are only used when the module is clustered, so the loads stay in flight meanwhile.
 template <u32 G, u32 K>
-__device__ __forceinline__ void load_digis(const EventDesc& E, const Item& I, u32 lt, u32* LIN, u32* A) {
-    u32 R[K], C[K];
+__device__ __forceinline__ void fetch_digis(const EventDesc& E, const Item& I, u32 lt, u32* R, u32* C, u32* A) {
 #pragma unroll
     for (u32 q = 0; q < K; ++q) {
         const u32 j = lt + q * G;
@@ -370,40 +402,38 @@ __device__ __forceinline__ void load_digis(const EventDesc& E, const Item& I, u3
         C[q] = E.col[i];
         A[q] = E.adc[i];
     }
-#pragma unroll
-    for (u32 q = 0; q < K; ++q) {
-        const u32 j = lt + q * G;
-        LIN[q] = j >= I.n ? NOPIX : (R[q] < ROWS && C[q] < COLS) ? C[q] * ROWS + R[q] : BADPIX;
-    }
 }
 
-// Cluster module I (n <= G*K) whose digis are in LIN/AR (load_digis; AR holds the
-// ADC in its low 16 bits, the digi's run and then its root go in the high 16 bits).
-// Every thread of the group calls it; with G > 64 all groups of the workgroup call
-// it together.  `mid(stage)` runs after phases 1, 3, 5 and 8 (the next module's
-// prefetch).
+// Cluster module I (n <= G*K) whose raw digis are in R/C/A (fetch_digis).  Every
+// thread of the group calls it; with G > 64 all groups of the workgroup call it
+// together.  `mid(stage)` runs at the end of phase 1, at the start of phase 3, at
+// the end of phase 5 and at the end of phase 8 (the next module's prefetch).
 template <u32 G, u32 K, typename Mid>
 __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDesc& E, const EvLayout& L,
-                                             const Item& I, RegModuleSmem<G, K>& gp, u32 lt, u32* LIN, u32* AR,
-                                             Mid mid) {
+                                             const Item& I, RegModuleSmem<G, K>& gp, u32 lt, const u32* R,
+                                             const u32* C, const u32* A, Mid mid) {
     static_assert(G * K <= 65536, "run indices are kept in 16 bits");
     constexpr u32 KBW = G * K / 32, WPT = (WORDS + G - 1) / G;
     u32* par = reinterpret_cast<u32*>(gp.acc);
     const bool act = I.ok;
     u32 err = 0;
+    // LIN: linear pixel index or NOPIX; AR: adc in the low 16 bits, then run / root
+    u32 LIN[K], AR[K];
     // P1: insert the module's digis into the bitmap
 #pragma unroll
     for (u32 q = 0; q < K; ++q) {
-        AR[q] &= 0xFFFFu;
-        if (!act) LIN[q] = NOPIX;
-        if (LIN[q] == BADPIX) {
-            err |= EB_RANGE;
-            LIN[q] = NOPIX;
-        }
-        if (LIN[q] != NOPIX) {
-            const u32 lin = LIN[q];
-            const u32 bit = 1u << (lin & 31u);
-            if (atomicOr(&gp.bm[lin >> 5], bit) & bit) err |= EB_DUP;
+        const u32 j = lt + q * G;
+        LIN[q] = NOPIX;
+        AR[q] = A[q] & 0xFFFFu;
+        if (act && j < I.n) {
+            if (R[q] < ROWS && C[q] < COLS) {
+                const u32 lin = C[q] * ROWS + R[q];
+                const u32 bit = 1u << (lin & 31u);
+                if (atomicOr(&gp.bm[lin >> 5], bit) & bit) err |= EB_DUP;
+                LIN[q] = lin;
+            } else {
+                err |= EB_RANGE;
+            }
         }
     }
     mid(0);
@@ -432,6 +462,7 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
     if (act)
         for (u32 r = lt; r < nruns; r += G) par[r] = r;
     gsync<G>();
+    mid(1);
     // P3: unions with the next column
 #pragma unroll
     for (u32 q = 0; q < K; ++q) {
@@ -443,7 +474,6 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
             link_right(par, gp.bm, gp.rpre, lin, row, col, r);
         }
     }
-    mid(1);
     gsync<G>();
     // P4: roots; the digi that starts its root's run speaks for the cluster
     u32 starts = 0;
@@ -521,7 +551,7 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
         }
 #pragma unroll
         for (u32 q = 0; q < K; ++q)
-            if (LIN[q] != NOPIX) gp.bm[LIN[q] >> 5] = 0u;
+            if (LIN[q] != NOPIX) st_wg(&gp.bm[LIN[q] >> 5], 0u);   // several digis may share a word
         if (err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, err);
     }
     gsync<G>();
@@ -539,26 +569,6 @@ struct SmallSmem {
     u32 tick[2];
 };
 
-// Resolve position t of the concatenated small lists into a module.  Items that
-// fail the consistency checks are reported by the caller.
-template <u32 G, u32 K>
-__device__ __forceinline__ Item small_item(const LaunchArgs& a, const u32* pref, u32 k, u32 total, u32 t,
-                                           EventDesc& E) {
-    Item I{0, 0, 0, 0, 0, false};
-    if (t >= total) return I;
-    I.e = find_slot(pref, k, t);
-    E = get_event(a, I.e);
-    const EvLayout L = ev_layout(E.cap, a.n_modules);
-    I.it = ws_ptr<const u32>(E, L.small)[t - pref[I.e]];
-    const u32* item_start = ws_ptr<const u32>(E, L.item_start);
-    I.st = item_start[I.it];
-    const u32 en = item_start[I.it + 1];
-    I.mod = ws_ptr<const u32>(E, L.item_mod)[I.it];
-    I.n = en - I.st;
-    I.ok = en > I.st && en <= E.n && I.n <= G * K && I.mod < a.n_modules;
-    return I;
-}
-
 template <u32 WG, u32 MPW, u32 K>
 __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     using S = SmallSmem<WG, MPW, K>;
@@ -571,52 +581,86 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     RegModuleSmem<G, K>& gp = s.grp[g];
     for (u32 w = lt; w < WORDS; w += G) gp.bm[w] = 0u;
     const u32 k = num_events(a);
-    const u32 total = event_prefix<WG>(a, k, s.pref, s.wsum, CTL_SMALL, 1, 0);
-
-    // first ticket: a wave draws with lane 0 and broadcasts with readfirstlane; a
-    // lockstep workgroup draws MPW modules with thread 0 and broadcasts through LDS
-    u32 base;
-    if constexpr (WAVE) {
-        u32 v = 0;
-        if (lt == 0) v = atomicAdd(&a.ctr[S_TICK], 1u);
-        base = __builtin_amdgcn_readfirstlane(v);
-    } else {
-        if (tid == 0) s.tick[0] = atomicAdd(&a.ctr[S_TICK], STEP);
+    u32 total;
+    if (k == 1) {                             // one event, alone or in a header
+        const EventDesc E0 = get_event(a, 0);
+        total = E0.n ? ld_ag(ws_ptr<u32>(E0, ev_layout(E0.cap, a.n_modules).ctl) + CTL_SMALL) : 0u;
+        if (tid == 0) s.pref[0] = 0;
         lds_barrier();
-        base = s.tick[0];
+    } else {
+        total = event_prefix<WG>(a, k, s.pref, s.wsum, CTL_SMALL, 1, 0);
     }
+    auto entry_of = [&](u32 t, EventDesc& Ev, u32& e) -> const ItemEntry* {
+        e = k == 1 ? 0u : find_slot(s.pref, k, t);
+        Ev = get_event(a, e);
+        return ws_ptr<const ItemEntry>(Ev, ev_layout(Ev.cap, a.n_modules).small) + (t - s.pref[e]);
+    };
+    auto make_item = [&](const ItemEntry& ent, const EventDesc& Ev, u32 e, bool valid) {
+        Item I{e, ent.it, ent.st, ent.n, ent.mod, false};
+        I.ok = valid && I.n > 0 && I.st + I.n <= Ev.n && I.n <= G * K && I.mod < a.n_modules;
+        return I;
+    };
+
+    // The first MPW modules of every workgroup are assigned statically, later ones
+    // come from a ticket counter offset by the static assignment.  The ticket of the
+    // module after next is drawn while the current one is clustered, the next
+    // module's work-list entry and digis are loaded meanwhile.
+    const u32 nstatic = gridDim.x * MPW;
+    u32 base = blockIdx.x * MPW + (WAVE ? g : 0u);
     EventDesc E{};
-    Item I = small_item<G, K>(a, s.pref, k, total, base + gofs, E);
-    u32 LIN[K], A[K];
-    if (I.ok) load_digis<G, K>(E, I, lt, LIN, A);
+    Item I{0, 0, 0, 0, 0, false};
+    u32 R[K], C[K], A[K];
+    {
+        const u32 t = base + gofs;
+        if (t < total) {
+            u32 e;
+            const ItemEntry ent = *entry_of(t, E, e);
+            I = make_item(ent, E, e, true);
+        }
+        if (I.ok) fetch_digis<G, K>(E, I, lt, R, C, A);
+    }
+    u32 nv = 0;                                   // ticket of the next module (in flight)
+    if ((WAVE && lt == 0) || (!WAVE && tid == 0)) nv = atomicAdd(&a.ctr[S_TICK], STEP) + nstatic;
 
     while (base < total) {
-        u32 nbase = total, nv = 0;
+        u32 nbase = total, nv2 = 0, ne = 0;
         EventDesc En{};
+        const ItemEntry* pent = nullptr;
+        ItemEntry ent{0, 0, 0, 0};
         Item In{0, 0, 0, 0, 0, false};
-        u32 NLIN[K], NA[K];
+        u32 NR[K], NC[K], NA[K];
+        auto issue_entry = [&]() {
+            const u32 t = nbase + gofs;
+            if (t < total) {
+                pent = entry_of(t, En, ne);
+                ent = *pent;                      // load issued; used at stage 2
+            }
+        };
         auto mid = [&](int stage) {
-            if (stage == 0) {                      // draw the next ticket
+            if (stage == 0) {
                 if constexpr (WAVE) {
-                    if (lt == 0) nv = atomicAdd(&a.ctr[S_TICK], 1u);
-                } else {
-                    if (tid == 0) nv = atomicAdd(&a.ctr[S_TICK], STEP);
+                    nbase = __builtin_amdgcn_readfirstlane(nv);
+                    if (lt == 0) nv2 = atomicAdd(&a.ctr[S_TICK], 1u) + nstatic;
+                    issue_entry();
+                } else if (tid == 0) {
+                    s.tick[1] = nv;
+                    nv2 = atomicAdd(&a.ctr[S_TICK], STEP) + nstatic;
                 }
-            } else if (stage == 1) {               // publish it
-                if constexpr (WAVE) nbase = __builtin_amdgcn_readfirstlane(nv);
-                else if (tid == 0) s.tick[1] = nv;
-            } else if (stage == 2) {               // resolve it
-                if constexpr (!WAVE) nbase = s.tick[1];
-                In = small_item<G, K>(a, s.pref, k, total, nbase + gofs, En);
-            } else {                               // load its digis
-                if (In.ok) load_digis<G, K>(En, In, lt, NLIN, NA);
+            } else if (stage == 1) {
+                if constexpr (!WAVE) {
+                    nbase = s.tick[1];
+                    issue_entry();
+                }
+            } else if (stage == 2) {
+                In = make_item(ent, En, ne, pent != nullptr);
+                if (In.ok) fetch_digis<G, K>(En, In, lt, NR, NC, NA);
             }
         };
         if (base + gofs < total && !I.ok && lt == 0)
             atomicOr(ws_ptr<u32>(E, ev_layout(E.cap, a.n_modules).ctl) + CTL_ERR, EB_INTERNAL);
         if (!WAVE || I.ok) {
             const EvLayout L = ev_layout(E.cap, a.n_modules);
-            cluster_regs<G, K>(a, E, L, I, gp, lt, LIN, A, mid);
+            cluster_regs<G, K>(a, E, L, I, gp, lt, R, C, A, mid);
         } else {
             mid(0);
             mid(1);
@@ -626,53 +670,118 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         base = nbase;
         E = En;
         I = In;
+        nv = nv2;
 #pragma unroll
-        for (u32 q = 0; q < K; ++q) { LIN[q] = NLIN[q]; A[q] = NA[q]; }
+        for (u32 q = 0; q < K; ++q) { R[q] = NR[q]; C[q] = NC[q]; A[q] = NA[q]; }
     }
 }
 
 // ---------------------------------------------------------------------------
 // big: one module per 512-thread workgroup
 // ---------------------------------------------------------------------------
-// Scratch mode (more than BIG_RCAP digis): up to MAX_RUNS parents in LDS; digis are
-// re-read from memory in every phase; per-digi roots and root charges go to global
-// scratch that only the same thread reads back (the module's slice of the event's
-// final charge/size arrays, which the compaction kernel overwrites later).
+// Scratch mode (more than BIG_RCAP digis).  Connectivity is computed on the bitmap
+// alone: every vertical run is linked to the runs of the next column that touch it,
+// with the parents of up to MAX_RUNS runs in LDS.  The roots, in run order (= order
+// of their smallest linear index), number the clusters.  Three passes over the digis
+// follow: charge and size (device atomics into the module's slice of the event's
+// final charge/size arrays, which the compaction kernel overwrites later; a wave
+// whose digis all belong to one cluster adds once), then per-digi ids.
 struct BigScratchSmem {
     u32 bm[WORDS];
     u32 par[MAX_RUNS];
-    u32 kb[MAX_RUNS / 32];
+    u32 rootb[MAX_RUNS / 32];   // root runs, then kept clusters (over cluster index)
     u16 rpre[WORDS];
-    u16 kpre[MAX_RUNS / 32];
+    u16 rootp[MAX_RUNS / 32];   // roots before each word, then kept clusters before each word
     u32 wsum[B_WG / 64];
+    u32 misc[4];
 };
 union BigSmem {
     RegModuleSmem<B_WG, K_BIG> reg;
     BigScratchSmem scr;
 };
 
-constexpr u32 UNR = 4;                        // digis per thread fetched at once
+constexpr u32 UNR = 8;                        // digis per thread fetched at once
 constexpr u32 SPAN = UNR * B_WG;
 
 __device__ __forceinline__ u32 clampj(u32 j, u32 n) { return j < n ? j : 0u; }
 
-__device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const EventDesc& E, const EvLayout& L, const Item& I,
-                                BigScratchSmem& s) {
+// Add `val` at base[key] for every lane with `valid`; one atomic per wave when all
+// valid lanes share the key.  Called by all lanes of the wave.
+__device__ __forceinline__ void wave_add(u32* base, u32 key, u32 val, bool valid) {
+    const u64 vm = __ballot(valid);
+    if (!vm) return;
+    const u32 first = __ffsll((unsigned long long)vm) - 1;
+    const u32 lead = __shfl(key, first, 64);
+    const u64 same = __ballot(valid && key == lead);
+    if (same == vm) {
+        u32 sum = valid ? val : 0u;
+#pragma unroll
+        for (u32 d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+        if ((threadIdx.x & 63u) == first) atomicAdd(&base[lead], sum);
+    } else if (valid) {
+        atomicAdd(&base[key], val);
+    }
+}
+
+// Last row of the run that starts at row r0 of column col.
+__device__ __forceinline__ u32 run_end(const u32* bm, u32 col, u32 r0) {
+    const u32 lin = col * ROWS + r0;
+    u32 w = lin >> 5;
+    u32 x = ~bm[w] & (0xFFFFFFFFu << (lin & 31u));
+    while (x == 0 && (w % WPC) != WPC - 1) x = ~bm[++w];
+    if (x == 0) return ROWS - 1;
+    return (w << 5) + (__ffs(x) - 1) - col * ROWS - 1;
+}
+
+// Links of run r (rows r0..r1 of column col) to the runs of column col+1 it touches
+// (rows r0-1..r1+1): the run holding the first fired pixel of that range and every
+// run that starts inside it.
+__device__ __forceinline__ void link_run(u32* par, const u32* bm, const u16* rpre, u32 r, u32 col, u32 r0,
+                                         u32 r1) {
+    if (col + 1 >= COLS) return;
+    const u32 lo = (r0 > 0 ? r0 - 1 : 0u), hi = min(r1 + 1, ROWS - 1);
+    const u32 base = (col + 1) * ROWS;
+    bool first = true;
+    for (u32 row = lo; row <= hi;) {
+        const u32 lin = base + row, w = lin >> 5, b = lin & 31u;
+        const u32 span = min(32u - b, hi - row + 1);                 // rows left in this word
+        const u32 mask = (span == 32u ? 0xFFFFFFFFu : ((1u << span) - 1u)) << b;
+        u32 bits = bm[w] & mask;
+        if (first && bits) {                                           // run holding the first fired pixel
+            const u32 fb = __ffs(bits) - 1;
+            uf_unite(par, r, run_of(bm, rpre, (w << 5) + fb));
+            first = false;
+            bits &= ~(1u << fb);
+        }
+        u32 sb = run_starts(bm, w) & bits;                             // runs starting later in the range
+        while (sb) {
+            const u32 fb = __ffs(sb) - 1;
+            sb &= sb - 1;
+            uf_unite(par, r, run_of(bm, rpre, (w << 5) + fb));
+        }
+        row += span;
+    }
+}
+
+__device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const EventDesc& E, const EvLayout& L,
+                                                const Item& I, BigScratchSmem& s) {
     constexpr u32 WPT = (WORDS + B_WG - 1) / B_WG;
     constexpr u32 KW = MAX_RUNS / 32, KPT = (KW + B_WG - 1) / B_WG;
     const u32 tid = threadIdx.x, n = I.n, st = I.st;
-    u32* groot = ws_ptr<u32>(E, L.charge) + st;
-    u32* gchg = ws_ptr<u32>(E, L.size) + st;
+    u32* cid = ws_ptr<u32>(E, L.id) + st;        // per cluster: id (or -1 once cut)
+    u32* cch = ws_ptr<u32>(E, L.charge) + st;    // per cluster: charge
+    u32* csz = ws_ptr<u32>(E, L.size) + st;      // per cluster: size
     int32_t* od = ws_ptr<int32_t>(E, L.digi) + st;
     u32 err = 0;
     // UNR digis' linear index (NOPIX when absent or out of range), loads first
-    auto fetch = [&](u32 base, u32* lin) {
+    auto fetch = [&](u32 base, u32* lin, u32* adc) {
         u32 r[UNR], c[UNR];
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
             const u32 i = st + clampj(base + u * B_WG + tid, n);
             r[u] = E.row[i];
             c[u] = E.col[i];
+            if (adc) adc[u] = E.adc[i];
         }
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
@@ -681,12 +790,14 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             if (j < n && lin[u] == NOPIX) err |= EB_RANGE;
         }
     };
-    auto is_root_start = [&](u32 lin, u32 root) {
-        return !((lin % ROWS) > 0 && fired(s.bm, lin - 1)) && run_of(s.bm, s.rpre, lin) == root;
+    // cluster index of the root of run `run`
+    auto cluster_of = [&](u32 run) {
+        const u32 root = uf_find(s.par, run);
+        return u32(s.rootp[root >> 5]) + __popc(s.rootb[root >> 5] & ((1u << (root & 31u)) - 1u));
     };
-    for (u32 base = 0; base < n; base += SPAN) {               // P1: bitmap
+    for (u32 base = 0; base < n; base += SPAN) {               // pass 1: bitmap
         u32 lin[UNR];
-        fetch(base, lin);
+        fetch(base, lin, nullptr);
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u)
             if (lin[u] != NOPIX) {
@@ -696,7 +807,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     }
     lds_barrier();
     u32 nruns;
-    {                                                           // P2: runs
+    {                                                           // runs
         u32 sw[WPT], cnt = 0;
 #pragma unroll
         for (u32 i = 0; i < WPT; ++i) {
@@ -713,130 +824,178 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
         }
     }
     for (u32 r = tid; r < nruns; r += B_WG) s.par[r] = r;
-    for (u32 w = tid; w < KW; w += B_WG) s.kb[w] = 0u;
     lds_barrier();
-    for (u32 base = 0; base < n; base += SPAN) {               // P3: unions
-        u32 lin[UNR];
-        fetch(base, lin);
-#pragma unroll
-        for (u32 u = 0; u < UNR; ++u)
-            if (lin[u] != NOPIX) {
-                const u32 col = lin[u] / ROWS, row = lin[u] - col * ROWS;
-                link_right(s.par, s.bm, s.rpre, lin[u], row, col, run_of(s.bm, s.rpre, lin[u]));
-            }
-    }
-    lds_barrier();
-    for (u32 base = 0; base < n; base += SPAN) {               // P4: roots to scratch
-        u32 lin[UNR];
-        fetch(base, lin);
-#pragma unroll
-        for (u32 u = 0; u < UNR; ++u)
-            if (lin[u] != NOPIX) groot[base + u * B_WG + tid] = uf_find(s.par, run_of(s.bm, s.rpre, lin[u]));
-    }
-    lds_barrier();
-    for (u32 r = tid; r < nruns; r += B_WG) s.par[r] = 0u;     // parents -> charge sums
-    lds_barrier();
-    for (u32 base = 0; base < n; base += SPAN) {               // P5: charge
-        u32 lin[UNR], rt[UNR], ad[UNR];
-        fetch(base, lin);
-#pragma unroll
-        for (u32 u = 0; u < UNR; ++u) {
-            const u32 jj = clampj(base + u * B_WG + tid, n);
-            rt[u] = groot[jj];
-            ad[u] = E.adc[st + jj];
+    // unions, one run at a time, from the bitmap only
+    for (u32 w = tid; w < WORDS; w += B_WG) {
+        u32 sb = run_starts(s.bm, w);
+        u32 r = s.rpre[w];
+        const u32 col = w / WPC;
+        while (sb) {
+            const u32 b = __ffs(sb) - 1;
+            sb &= sb - 1;
+            const u32 r0 = (w % WPC) * 32 + b;                        // first row of the run
+            link_run(s.par, s.bm, s.rpre, r, col, r0, run_end(s.bm, col, r0));
+            ++r;
         }
-#pragma unroll
-        for (u32 u = 0; u < UNR; ++u)
-            if (lin[u] != NOPIX) atomicAdd(&s.par[rt[u]], ad[u]);
     }
     lds_barrier();
-    for (u32 base = 0; base < n; base += SPAN) {               // P6: cut at the root-start digi
-        u32 lin[UNR], rt[UNR];
-        fetch(base, lin);
+    // roots (parent == self) number the clusters in order of their smallest index
+    for (u32 w = tid; w < KW; w += B_WG) {
+        u32 bits = 0;
 #pragma unroll
-        for (u32 u = 0; u < UNR; ++u) rt[u] = groot[clampj(base + u * B_WG + tid, n)];
-#pragma unroll
-        for (u32 u = 0; u < UNR; ++u)
-            if (lin[u] != NOPIX && is_root_start(lin[u], rt[u])) {
-                const u32 charge = s.par[rt[u]];
-                gchg[base + u * B_WG + tid] = charge;
-                if (charge >= a.charge_cut) atomicOr(&s.kb[rt[u] >> 5], 1u << (rt[u] & 31u));
-            }
+        for (u32 i = 0; i < 32; ++i) {
+            const u32 r = w * 32 + i;
+            if (r < nruns && ld_wg(&s.par[r]) == r) bits |= 1u << i;
+        }
+        s.rootb[w] = bits;
     }
     lds_barrier();
-    {                                                           // P7: kept roots before each word
+    u32 ncl;
+    {
         u32 sw[KPT], cnt = 0;
 #pragma unroll
         for (u32 i = 0; i < KPT; ++i) {
             const u32 w = tid * KPT + i;
-            sw[i] = w < KW ? __popc(s.kb[w]) : 0u;
+            sw[i] = w < KW ? __popc(s.rootb[w]) : 0u;
             cnt += sw[i];
         }
-        u32 Kc;
-        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, Kc);
+        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, ncl);
 #pragma unroll
         for (u32 i = 0; i < KPT; ++i) {
             const u32 w = tid * KPT + i;
-            if (w < KW) s.kpre[w] = u16(run);
+            if (w < KW) s.rootp[w] = u16(run);
             run += sw[i];
         }
-        if (tid == 0) ws_ptr<u32>(E, L.item_kept)[I.it] = Kc;
-    }
-    for (u32 r = tid; r < nruns; r += B_WG) s.par[r] = 0u;     // charge sums -> sizes
-    lds_barrier();
-    for (u32 base = 0; base < n; base += SPAN) {               // P8: sizes
-        u32 lin[UNR], rt[UNR];
-        fetch(base, lin);
-#pragma unroll
-        for (u32 u = 0; u < UNR; ++u) rt[u] = groot[clampj(base + u * B_WG + tid, n)];
-#pragma unroll
-        for (u32 u = 0; u < UNR; ++u)
-            if (lin[u] != NOPIX) atomicAdd(&s.par[rt[u]], 1u);
     }
     lds_barrier();
-    {                                                           // P9: records; root slot -> id
+    // per cluster: id from the start of its root run; zero the sums
+    for (u32 w = tid; w < WORDS; w += B_WG) {
+        u32 sb = run_starts(s.bm, w);
+        u32 r = s.rpre[w];
+        while (sb) {
+            const u32 b = __ffs(sb) - 1;
+            sb &= sb - 1;
+            if (s.rootb[r >> 5] & (1u << (r & 31u))) {
+                const u32 c = u32(s.rootp[r >> 5]) + __popc(s.rootb[r >> 5] & ((1u << (r & 31u)) - 1u));
+                cid[c] = I.mod * PIX + (w << 5) + b;
+                cch[c] = 0u;
+                csz[c] = 0u;
+            }
+            ++r;
+        }
+    }
+    wait_all_mem();
+    lds_barrier();
+    for (u32 base = 0; base < n; base += SPAN) {               // pass 2: charge and size
+        u32 lin[UNR], adc[UNR];
+        fetch(base, lin, adc);
+#pragma unroll
+        for (u32 u = 0; u < UNR; ++u) {
+            const bool v = lin[u] != NOPIX;
+            const u32 c = v ? cluster_of(run_of(s.bm, s.rpre, lin[u])) : 0u;
+            wave_add(cch, c, adc[u], v);
+            wave_add(csz, c, 1u, v);
+        }
+    }
+    wait_all_mem();
+    lds_barrier();
+    // cut; kept clusters -> staging records in cluster (= ascending id) order
+    for (u32 w = tid; w < KW; w += B_WG) {
+        u32 bits = 0;
+        if (w * 32 < ncl) {
+            u32 ch[32];
+#pragma unroll
+            for (u32 i = 0; i < 32; ++i) ch[i] = ld_ag(&cch[min(w * 32 + i, ncl - 1)]);
+#pragma unroll
+            for (u32 i = 0; i < 32; ++i)
+                if (w * 32 + i < ncl && ch[i] >= a.charge_cut) bits |= 1u << i;
+        }
+        s.rootb[w] = bits;                                     // kept clusters (roots rebuilt below)
+    }
+    lds_barrier();
+    u32 Kc;
+    {
+        u32 sw[KPT], cnt = 0;
+#pragma unroll
+        for (u32 i = 0; i < KPT; ++i) {
+            const u32 w = tid * KPT + i;
+            sw[i] = w < KW ? __popc(s.rootb[w]) : 0u;
+            cnt += sw[i];
+        }
+        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, Kc);
+        u32 keep_pre[KPT];
+#pragma unroll
+        for (u32 i = 0; i < KPT; ++i) {
+            keep_pre[i] = run;
+            run += sw[i];
+        }
         int32_t* tid_ = ws_ptr<int32_t>(E, L.tid);
         int32_t* tch = ws_ptr<int32_t>(E, L.tcharge);
         int32_t* tsz = ws_ptr<int32_t>(E, L.tsize);
-        for (u32 base = 0; base < n; base += SPAN) {
-            u32 lin[UNR], rt[UNR], ch[UNR];
-            fetch(base, lin);
 #pragma unroll
-            for (u32 u = 0; u < UNR; ++u) {
-                const u32 jj = clampj(base + u * B_WG + tid, n);
-                rt[u] = groot[jj];
-                ch[u] = gchg[jj];
-            }
-#pragma unroll
-            for (u32 u = 0; u < UNR; ++u)
-                if (lin[u] != NOPIX && is_root_start(lin[u], rt[u])) {
-                    const u32 r = rt[u];
-                    const u32 size = s.par[r];
-                    u32 id = NOPIX;
-                    if (ch[u] >= a.charge_cut) {
-                        const u32 pos = s.kpre[r >> 5] + __popc(s.kb[r >> 5] & ((1u << (r & 31u)) - 1u));
-                        id = I.mod * PIX + lin[u];
-                        tid_[st + pos] = int32_t(id);
-                        tch[st + pos] = int32_t(ch[u]);
-                        tsz[st + pos] = int32_t(size);
-                    }
-                    s.par[r] = id;
+        for (u32 i = 0; i < KPT; ++i) {
+            const u32 w = tid * KPT + i;
+            if (w >= KW) continue;
+            u32 pos = keep_pre[i];
+            for (u32 b = 0; b < 32; ++b) {
+                const u32 c = w * 32 + b;
+                if (c >= ncl) break;
+                if (s.rootb[w] & (1u << b)) {
+                    tid_[st + pos] = int32_t(ld_ag(&cid[c]));
+                    tch[st + pos] = int32_t(ld_ag(&cch[c]));
+                    tsz[st + pos] = int32_t(ld_ag(&csz[c]));
+                    ++pos;
+                } else {
+                    st_ag(&cid[c], NOPIX);
                 }
+            }
+        }
+        if (tid == 0) ws_ptr<u32>(E, L.item_kept)[I.it] = Kc;
+    }
+    wait_all_mem();
+    lds_barrier();
+    // the kept bits replaced the root bits: rebuild the roots for the last pass
+    for (u32 w = tid; w < KW; w += B_WG) {
+        u32 bits = 0;
+#pragma unroll
+        for (u32 i = 0; i < 32; ++i) {
+            const u32 r = w * 32 + i;
+            if (r < nruns && ld_wg(&s.par[r]) == r) bits |= 1u << i;
+        }
+        s.rootb[w] = bits;
+    }
+    lds_barrier();
+    {
+        u32 sw[KPT], cnt = 0, tot;
+#pragma unroll
+        for (u32 i = 0; i < KPT; ++i) {
+            const u32 w = tid * KPT + i;
+            sw[i] = w < KW ? __popc(s.rootb[w]) : 0u;
+            cnt += sw[i];
+        }
+        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, tot);
+#pragma unroll
+        for (u32 i = 0; i < KPT; ++i) {
+            const u32 w = tid * KPT + i;
+            if (w < KW) s.rootp[w] = u16(run);
+            run += sw[i];
         }
     }
     lds_barrier();
-    for (u32 base = 0; base < n; base += SPAN) {               // P10: per-digi ids
-        u32 lin[UNR], rt[UNR];
-        fetch(base, lin);
+    for (u32 base = 0; base < n; base += SPAN) {               // pass 3: per-digi ids
+        u32 lin[UNR];
+        fetch(base, lin, nullptr);
+        u32 c[UNR];
 #pragma unroll
-        for (u32 u = 0; u < UNR; ++u) rt[u] = groot[clampj(base + u * B_WG + tid, n)];
+        for (u32 u = 0; u < UNR; ++u) c[u] = lin[u] != NOPIX ? cluster_of(run_of(s.bm, s.rpre, lin[u])) : 0u;
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
             const u32 j = base + u * B_WG + tid;
-            if (j < n) od[j] = lin[u] != NOPIX ? int32_t(s.par[rt[u]]) : -1;
+            if (j < n) od[j] = lin[u] != NOPIX ? int32_t(ld_ag(&cid[c[u]])) : -1;
         }
     }
     if (err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, err);
+    lds_barrier();                                              // every thread is done with the bitmap
     for (u32 w = tid; w < WORDS; w += B_WG) s.bm[w] = 0u;
     lds_barrier();
 }
@@ -854,21 +1013,20 @@ __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
         I.e = find_slot(s_pref, k, t);
         const EventDesc E = get_event(a, I.e);
         const EvLayout L = ev_layout(E.cap, a.n_modules);
-        I.it = ws_ptr<const u32>(E, L.big)[t - s_pref[I.e]];
-        const u32* item_start = ws_ptr<const u32>(E, L.item_start);
-        I.st = item_start[I.it];
-        const u32 en = item_start[I.it + 1];
-        I.mod = ws_ptr<const u32>(E, L.item_mod)[I.it];
-        I.n = en - I.st;
-        I.ok = en > I.st && en <= E.n && I.mod < a.n_modules;
+        const ItemEntry ent = ws_ptr<const ItemEntry>(E, L.big)[t - s_pref[I.e]];
+        I.it = ent.it;
+        I.st = ent.st;
+        I.n = ent.n;
+        I.mod = ent.mod;
+        I.ok = I.n > 0 && I.st + I.n <= E.n && I.mod < a.n_modules;
         if (!I.ok) {
             if (tid == 0) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, EB_INTERNAL);
             continue;
         }
         if (I.n <= BIG_RCAP) {
-            u32 LIN[K_BIG], A[K_BIG];
-            load_digis<B_WG, K_BIG>(E, I, tid, LIN, A);
-            cluster_regs<B_WG, K_BIG>(a, E, L, I, s.reg, tid, LIN, A, [](int) {});
+            u32 R[K_BIG], C[K_BIG], A[K_BIG];
+            fetch_digis<B_WG, K_BIG>(E, I, tid, R, C, A);
+            cluster_regs<B_WG, K_BIG>(a, E, L, I, s.reg, tid, R, C, A, [](int) {});
         } else {
             cluster_scratch(a, E, L, I, s.scr);
         }
@@ -877,12 +1035,16 @@ __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
 
 // ---------------------------------------------------------------------------
 // compact: per event, chunks of C_ITEMS modules; a chunk's offset is the sum of the
-// kept counts of all earlier modules; one wave copies one module's records
+// kept counts of all earlier modules; each wave copies the records of C_ITEMS/4
+// modules, CP_UNR records per lane at a time
 // ---------------------------------------------------------------------------
+constexpr u32 CP_UNR = 4, SUM_UNR = 8;
+
 __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
     __shared__ u32 s_pref[MAXB + 1];
     __shared__ u32 s_wsum[C_WG / 64];
     __shared__ u32 s_off[C_ITEMS + 1];
+    __shared__ u32 s_src[C_ITEMS];
     __shared__ u32 s_red[C_WG / 64];
     const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const u32 k = num_events(a);
@@ -896,12 +1058,24 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         u32* ctl = ws_ptr<u32>(E, L.ctl);
         const u32 items = E.n ? ctl[CTL_ITEMS] : 0u;
         const u32* kept = ws_ptr<const u32>(E, L.item_kept);
+        const u32* item_start = ws_ptr<const u32>(E, L.item_start);
         const u32 i0 = c * C_ITEMS, i1 = min(i0 + C_ITEMS, items);
         u32 part = 0;                                      // kept clusters of items [0, i0)
-        for (u32 i = tid; i < i0; i += C_WG) part += kept[i];
+        for (u32 b = 0; b < i0; b += C_WG * SUM_UNR) {
+            u32 v[SUM_UNR];
+#pragma unroll
+            for (u32 u = 0; u < SUM_UNR; ++u) {
+                const u32 i = b + u * C_WG + tid;
+                v[u] = i < i0 ? kept[i] : 0u;
+            }
+#pragma unroll
+            for (u32 u = 0; u < SUM_UNR; ++u) part += v[u];
+        }
         const u32 wtot = __shfl(wave_incl_scan(part), 63, 64);
         if (lane == 0) s_red[wv] = wtot;
-        const u32 v = (tid < C_ITEMS && i0 + tid < i1) ? kept[i0 + tid] : 0u;
+        const bool mine = tid < C_ITEMS && i0 + tid < i1;
+        const u32 v = mine ? kept[i0 + tid] : 0u;
+        if (tid < C_ITEMS) s_src[tid] = mine ? item_start[i0 + tid] : 0u;
         const u32 inc = wave_incl_scan(v);                 // offsets inside the chunk (wave 0)
         lds_barrier();
         u32 before = 0;
@@ -910,7 +1084,6 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         if (tid < C_ITEMS) s_off[tid] = before + inc - v;
         if (tid == C_ITEMS - 1) s_off[C_ITEMS] = before + inc;
         lds_barrier();
-        const u32* item_start = ws_ptr<const u32>(E, L.item_start);
         const int32_t* tid_ = ws_ptr<const int32_t>(E, L.tid);
         const int32_t* tch = ws_ptr<const int32_t>(E, L.tcharge);
         const int32_t* tsz = ws_ptr<const int32_t>(E, L.tsize);
@@ -919,13 +1092,27 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         int32_t* osz = ws_ptr<int32_t>(E, L.size);
         for (u32 x = i0 + wv; x < i1; x += C_WG / 64) {
             const u32 off = s_off[x - i0], cnt = s_off[x - i0 + 1] - off;
-            const u32 src = item_start[x];
+            const u32 src = s_src[x - i0];
             if (off + cnt > E.n || src + cnt > E.n) continue;   // inconsistent input (flagged)
-            for (u32 j = lane; j < cnt; j += 64) {
-                const int32_t a0 = tid_[src + j], a1 = tch[src + j], a2 = tsz[src + j];
-                oid[off + j] = a0;
-                och[off + j] = a1;
-                osz[off + j] = a2;
+            for (u32 j0 = 0; j0 < cnt; j0 += 64 * CP_UNR) {
+                int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
+#pragma unroll
+                for (u32 u = 0; u < CP_UNR; ++u) {
+                    const u32 j = j0 + u * 64 + lane;
+                    const u32 jj = j < cnt ? j : 0u;
+                    r0[u] = tid_[src + jj];
+                    r1[u] = tch[src + jj];
+                    r2[u] = tsz[src + jj];
+                }
+#pragma unroll
+                for (u32 u = 0; u < CP_UNR; ++u) {
+                    const u32 j = j0 + u * 64 + lane;
+                    if (j < cnt) {
+                        oid[off + j] = r0[u];
+                        och[off + j] = r1[u];
+                        osz[off + j] = r2[u];
+                    }
+                }
             }
         }
         if (i1 >= items && tid == 0) {                     // the event's last chunk: status

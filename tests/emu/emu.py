@@ -1,0 +1,81 @@
+"""Build and run the device kernels on the CPU (hip_runtime.h shim + run_emu.cpp,
+AddressSanitizer on) -- test infrastructure for checking kernel indexing and
+results without a GPU."""
+from __future__ import annotations
+
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+BIN = os.path.join(tempfile.gettempdir(), f"pxcl_run_emu_{os.getuid()}")
+
+
+def build(force: bool = False, sanitizer: str = "address") -> str:
+    """Build the emulator and return its path; `sanitizer` is "address" (out-of-bounds
+    and null accesses) or "thread" (unsynchronised accesses between the work items of
+    a workgroup)."""
+    assert sanitizer in ("address", "thread")
+    exe = BIN + ("" if sanitizer == "address" else "_tsan")
+    srcs = [os.path.join(HERE, "run_emu.cpp"), os.path.join(HERE, "hip", "hip_runtime.h"),
+            os.path.join(ROOT, "paper_2004_04334_amd", "csrc", "pxcl_kernels.hip"),
+            os.path.join(ROOT, "paper_2004_04334_amd", "csrc", "pxcl_internal.h")]
+    if force or not os.path.exists(exe) or os.path.getmtime(exe) < max(os.path.getmtime(s) for s in srcs):
+        tmp = exe + f".tmp{os.getpid()}"
+        subprocess.check_call(["g++", "-std=c++20", "-O1", "-g", "-x", "c++", f"-fsanitize={sanitizer}",
+                               "-fno-omit-frame-pointer", "-pthread", "-I" + HERE,
+                               "-I" + os.path.join(ROOT, "paper_2004_04334_amd", "csrc"),
+                               os.path.join(HERE, "run_emu.cpp"), "-o", tmp])
+        os.replace(tmp, exe)
+    return exe
+
+
+def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, grids=(2, 2, 2, 2), caps=None,
+        header: bool = False, sanitizer: str = "address"):
+    """Cluster `events` (list of dicts of uint16 arrays) as one launch; returns a list
+    of result dicts like the oracle's (status from the error bits).  With `header` the
+    events are passed through a batch header even when there is only one."""
+    exe = build(sanitizer=sanitizer)
+    with tempfile.TemporaryDirectory() as d:
+        fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
+        with open(fin, "wb") as f:
+            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header)], dtype=np.uint32).tofile(f)
+            for i, ev in enumerate(events):
+                n = ev["module"].size
+                cap = max(1, n) if caps is None else caps[i]
+                np.array([n, cap], dtype=np.uint32).tofile(f)
+                for key in ("module", "row", "col", "adc"):
+                    np.ascontiguousarray(ev[key], dtype=np.uint16).tofile(f)
+        env = dict(os.environ)
+        if sanitizer == "thread":        # a smaller history per thread: thousands of short threads
+            env["TSAN_OPTIONS"] = "history_size=2 " + env.get("TSAN_OPTIONS", "")
+        r = subprocess.run([exe, fin, fout], capture_output=True, text=True, env=env)
+        if r.returncode != 0:
+            raise RuntimeError(f"emulated kernels failed ({r.returncode}):\n{r.stderr[-4000:]}")
+        raw = np.fromfile(fout, dtype=np.int32)
+    out, p = [], 0
+    for ev in events:
+        n = ev["module"].size
+        err, ncl = int(np.uint32(raw[p])), int(raw[p + 1])
+        p += 2
+        digi = raw[p:p + n]; p += n
+        cid = raw[p:p + ncl]; p += ncl
+        chg = raw[p:p + ncl]; p += ncl
+        siz = raw[p:p + ncl]; p += ncl
+        st = 0
+        if err & 0x80000000:
+            st = -10
+        elif err & 1:
+            st = -6
+        elif err & 2:
+            st = -7
+        elif err & 4:
+            st = -5
+        elif err & 8:
+            st = -10
+        out.append({"status": st, "err_bits": err, "n_clusters": ncl, "digi": digi.copy(), "id": cid.copy(),
+                    "charge": chg.copy(), "size": siz.copy()})
+    return out

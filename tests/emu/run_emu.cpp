@@ -1,0 +1,98 @@
+// Runs the device kernel source on the CPU (tests/emu/hip/hip_runtime.h) for one
+// launch of k events and writes the results; built with AddressSanitizer so that
+// any out-of-bounds access of the kernels aborts the run.  Test infrastructure.
+//
+// input:  u32 k, n_modules, cut, wg, mpw, grid_a, grid_b, grid_s, grid_c, header
+//         (1: the events go through a batch header even when k == 1);
+//         per event: u32 n, u32 cap, u16 module[n], row[n], col[n], adc[n]
+// output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
+#include "../../paper_2004_04334_amd/csrc/pxcl_kernels.hip"
+
+#include <cstdlib>
+#include <random>
+
+using namespace pxcl;
+
+static void rd(FILE* f, void* p, size_t b) {
+    if (b && fread(p, 1, b, f) != b) { fprintf(stderr, "short read\n"); exit(2); }
+}
+
+int main(int argc, char** argv) {
+    if (argc != 3) { fprintf(stderr, "usage: run_emu in out\n"); return 2; }
+    FILE* f = fopen(argv[1], "rb");
+    if (!f) return 2;
+    u32 h[10];
+    rd(f, h, sizeof(h));
+    const u32 k = h[0], M = h[1];
+    std::vector<EventDesc> evs(k);
+    std::vector<std::vector<u16>> in(k);
+    std::vector<u8*> ws(k);
+    std::vector<u32*> hs(k);
+    std::mt19937 rng(7);
+    for (u32 e = 0; e < k; ++e) {
+        u32 nc[2];
+        rd(f, nc, 8);
+        const u32 n = nc[0], cap = nc[1];
+        in[e].resize(4 * size_t(n) + 4);
+        rd(f, in[e].data(), 8 * size_t(n));
+        const EvLayout L = ev_layout(cap, M);
+        ws[e] = static_cast<u8*>(aligned_alloc(256, (L.total + 255) / 256 * 256));
+        for (size_t i = 0; i < L.total; ++i) ws[e][i] = u8(rng());        // garbage, as fresh device memory
+        memset(ws[e] + L.ctl, 0, CTL_WORDS * 4);                           // what binding clears
+        memset(ws[e] + L.seg, 0, L.item_start - L.seg);
+        hs[e] = static_cast<u32*>(aligned_alloc(64, HS_BYTES));
+        memset(hs[e], 0, HS_BYTES);
+        EventDesc& d = evs[e];
+        d.module = in[e].data();
+        d.row = in[e].data() + n;
+        d.col = in[e].data() + 2 * size_t(n);
+        d.adc = in[e].data() + 3 * size_t(n);
+        d.ws = ws[e];
+        d.hstat = hs[e];
+        d.n = n;
+        d.cap = cap;
+        d.epoch = 1000 + e;
+        d.pad = 0;
+    }
+    fclose(f);
+    LaunchArgs a;
+    memset(&a, 0, sizeof(a));
+    std::vector<u8> hdr;
+    u32 ctr[N_CTR] = {};
+    a.ctr = ctr;
+    a.n_modules = M;
+    a.charge_cut = h[2];
+    a.dcap = cluster_capacity(h[3], h[4]);
+    const bool use_header = h[9] != 0;
+    if (k == 1 && !use_header) {
+        a.single = evs[0];
+    } else {
+        hdr.resize(header_bytes(k));
+        memcpy(hdr.data(), &k, 4);
+        memcpy(hdr.data() + HDR_EV_OFFSET, evs.data(), k * sizeof(EventDesc));
+        a.hdr = reinterpret_cast<const u32*>(hdr.data());
+        a.ctr = reinterpret_cast<u32*>(aligned_alloc(64, 64));
+        memset(a.ctr, 0, 64);
+    }
+    if (launch_segment(a, h[5], nullptr) || launch_big(a, h[6], nullptr) ||
+        launch_small(h[3], h[4], a, h[7], nullptr) || launch_compact(a, h[8], nullptr)) {
+        fprintf(stderr, "launch failed\n");
+        return 3;
+    }
+    FILE* o = fopen(argv[2], "wb");
+    for (u32 e = 0; e < k; ++e) {
+        const EvLayout L = ev_layout(evs[e].cap, M);
+        const u32 err = hs[e][HS_ERR], ncl = hs[e][HS_NCL];
+        const u32 tag = hs[e][HS_EPOCH];
+        const u32 hdr2[2] = {tag == evs[e].epoch ? err : (err | 0x80000000u), ncl};
+        fwrite(hdr2, 4, 2, o);
+        fwrite(ws[e] + L.digi, 4, evs[e].n, o);
+        fwrite(ws[e] + L.id, 4, ncl, o);
+        fwrite(ws[e] + L.charge, 4, ncl, o);
+        fwrite(ws[e] + L.size, 4, ncl, o);
+    }
+    fclose(o);
+    for (u32 e = 0; e < k; ++e) { free(ws[e]); free(hs[e]); }
+    if (a.hdr) free(a.ctr);
+    return 0;
+}

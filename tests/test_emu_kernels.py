@@ -1,0 +1,78 @@
+"""The device kernel source run on the CPU: tests/emu holds a shim of the HIP subset
+the kernels use (one host thread per work item, barriers, wave-wide exchanges) and a
+driver built with AddressSanitizer, so that an out-of-bounds or null access of a
+kernel aborts the run, or with ThreadSanitizer, so that two work items of a
+workgroup touching the same shared word without a barrier or an atomic between them
+fail the run.  Results are compared bit-exactly with the oracle for the launch forms
+the library uses: one event alone, one event through a batch header, several events
+per launch, every small-module kernel shape, the big-module kernel in register and
+in scratch mode.  Workgroups run one after another, so ordering between workgroups
+is not exercised here."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2004_04334_amd import synth
+from tests.emu import emu
+from tests.gpu_util import compare
+
+
+@pytest.fixture(scope="module")
+def emulator(oracle_mod):
+    emu.build(sanitizer="address")
+    emu.build(sanitizer="thread")
+    return oracle_mod
+
+
+SHAPES = [(64, 1), (128, 1), (128, 2), (256, 1), (256, 2), (256, 4), (512, 1), (512, 2), (512, 4)]
+
+
+def _check(oracle_mod, events, n_modules, **kw):
+    res = emu.run(events, n_modules, **kw)
+    for i, (r, e) in enumerate(zip(res, events)):
+        compare(r, oracle_mod.cluster_event(e, 2000), f"event {i}")
+
+
+def test_one_event_through_a_header(emulator):
+    """A batch of one event: the kernels read the event from the header, not from the
+    single-event argument (which is zero in batch launches)."""
+    ev = synth.plain_event(0, n_modules=8)
+    _check(emulator, [ev], 8, header=True, grids=(2, 2, 3, 2))
+    _check(emulator, [ev], 8, header=False, grids=(2, 2, 3, 2))
+
+
+def _mixed_events():
+    big = synth.from_pixels(np.full(700, 2), *np.divmod(np.arange(700) * 7 % (160 * 416), 160)[::-1],
+                            n_modules=6, seed=11)
+    empty = {k: np.zeros(0, np.uint16) for k in ("module", "row", "col", "adc")}
+    evs = [synth.plain_event(1, n_modules=4), empty, big, synth.plain_event(2, n_modules=6)]
+    return [dict(e, n_modules=6) for e in evs]
+
+
+@pytest.mark.parametrize("wg,mpw", SHAPES)
+def test_kernel_shapes(emulator, wg, mpw):
+    """Several events per launch (one empty, one with a module above the small
+    kernel's capacity for the narrow shapes) on every group shape."""
+    evs = _mixed_events()
+    _check(emulator, evs, 6, wg=wg, mpw=mpw, grids=(2, 2, 3, 2), caps=[max(1, e["module"].size) + 5 for e in evs])
+
+
+@pytest.mark.parametrize("wg,mpw", [(64, 1), (256, 2), (512, 1)])
+def test_no_unsynchronised_shared_access(emulator, wg, mpw):
+    """ThreadSanitizer over the small-module and compaction kernels (wave groups,
+    lock-step groups of 2 and 1 per workgroup) and the big-module register mode."""
+    evs = _mixed_events()
+    _check(emulator, evs, 6, wg=wg, mpw=mpw, grids=(2, 2, 3, 2), caps=[max(1, e["module"].size) + 5 for e in evs],
+           sanitizer="thread")
+
+
+def test_scratch_mode_big_module(emulator):
+    """A module above the register capacity of the big-module kernel (a serpentine
+    of 33,359 pixels) next to a full-column track."""
+    sr, sc = synth.serpentine(row_wise=True)
+    tr, tc = synth.column_track(7)
+    m = np.concatenate([np.zeros(tr.size, np.int64), np.ones(sr.size, np.int64)])
+    ev = synth.from_pixels(m, np.concatenate([tr, sr]), np.concatenate([tc, sc]), n_modules=3, seed=5)
+    _check(emulator, [ev], 3, header=True, grids=(2, 2, 2, 2))
+    _check(emulator, [ev], 3, header=True, grids=(2, 2, 2, 2), sanitizer="thread")
