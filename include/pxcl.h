@@ -160,7 +160,9 @@ size_t pxcl_event_pinned_bytes(const pxcl_ctx* ctx);
  * hipMemsetAsync on `stream` (a hipStream_t; NULL = the null stream). */
 int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void* h_pinned,
                     size_t pinned_bytes, uint32_t max_digis, void* stream, pxcl_event** out);
-/* PXCL_E_BUSY while work is in flight. */
+/* PXCL_E_BUSY while work is in flight.  Waits for a completion callback of the
+ * event that is still running on another thread; called from inside such a
+ * callback it returns PXCL_E_BUSY instead. */
 int pxcl_event_unbind(pxcl_event* ev);
 uint32_t pxcl_event_capacity(const pxcl_event* ev);
 
@@ -177,9 +179,10 @@ int pxcl_query(const pxcl_event* ev);
 /* Non-blocking.  PXCL_E_NOT_READY before completion; otherwise fills *out and
  * returns the event's status (PXCL_OK or the async error). */
 int pxcl_produce(pxcl_event* ev, pxcl_clusters* out);
-/* Blocking wait for tests and simple callers (hipEventSynchronize on the event's
- * completion event followed by a wait for the callback); the contrast to the
- * callback style, never used on the asynchronous paths. */
+/* Blocking wait for tests and simple callers: hipEventSynchronize on the event's
+ * completion event, then a wait until the completion callback of the launch has
+ * returned (skipped when called from inside a completion callback).  The contrast
+ * to the callback style, never used on the asynchronous paths. */
 int pxcl_wait(pxcl_event* ev);
 
 /* A ready-made callback: `user` points to a pxcl_flag; the callback stores the

@@ -98,6 +98,7 @@ struct pxcl_event {
     pxcl_done_cb cb = nullptr;
     void* user = nullptr;
     pxcl_batch* batch = nullptr;
+    std::atomic<int> cb_pending{0};   // launches whose completion callback has not returned
 };
 
 struct pxcl_batch {
@@ -212,14 +213,23 @@ void finish_event_from_host_status(pxcl_event* ev) {
     ev->status = status_from_bits(bits);
 }
 
+// Set while a completion callback runs on this thread: a wait called from inside
+// the callback must not wait for the callback itself.
+thread_local int t_in_callback = 0;
+
 void event_done_hostfn(void* p) {
     pxcl_event* ev = static_cast<pxcl_event*>(p);
     finish_event_from_host_status(ev);
     pxcl_done_cb cb = ev->cb;
     void* user = ev->user;
     const int32_t st = ev->status;
-    ev->state.store(ST_DONE, std::memory_order_release);
-    if (cb) cb(user, st);
+    ev->state.store(ST_DONE, std::memory_order_release);   // the callback may produce and re-acquire
+    if (cb) {
+        ++t_in_callback;
+        cb(user, st);
+        --t_in_callback;
+    }
+    ev->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
 }
 
 void batch_done_hostfn(void* p) {
@@ -233,9 +243,17 @@ void batch_done_hostfn(void* p) {
     b->status = bst;
     pxcl_done_cb cb = b->cb;
     void* user = b->user;
-    for (u32 i = 0; i < b->k; ++i) b->evs[i]->state.store(ST_DONE, std::memory_order_release);
+    const u32 k = b->k;
+    pxcl_event* evs[MAXB];                         // the callback may launch the batch again
+    for (u32 i = 0; i < k; ++i) evs[i] = b->evs[i];
+    for (u32 i = 0; i < k; ++i) evs[i]->state.store(ST_DONE, std::memory_order_release);
     b->state.store(ST_DONE, std::memory_order_release);
-    if (cb) cb(user, bst);
+    if (cb) {
+        ++t_in_callback;
+        cb(user, bst);
+        --t_in_callback;
+    }
+    for (u32 i = 0; i < k; ++i) evs[i]->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
 }
 
 bool claim(std::atomic<int>& st) {
@@ -370,6 +388,10 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
 extern "C" int pxcl_event_unbind(pxcl_event* ev) {
     if (!ev) return PXCL_E_INVAL;
     if (ev->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+    if (ev->cb_pending.load(std::memory_order_acquire) > 0) {     // its callback is still running
+        if (t_in_callback) return PXCL_E_BUSY;
+        while (ev->cb_pending.load(std::memory_order_acquire) > 0) std::this_thread::yield();
+    }
     hipEventDestroy(ev->done_ev);
     for (int i = 0; i < 5; ++i) hipEventDestroy(ev->tev[i]);
     ev->ctx->bound.fetch_sub(1);
@@ -410,7 +432,11 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, false);
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
-    if (e == hipSuccess) e = hipLaunchHostFunc(s, event_done_hostfn, ev);
+    if (e == hipSuccess) {
+        ev->cb_pending.fetch_add(1, std::memory_order_acq_rel);
+        e = hipLaunchHostFunc(s, event_done_hostfn, ev);
+        if (e != hipSuccess) ev->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
+    }
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -476,6 +502,9 @@ extern "C" int pxcl_wait(pxcl_event* ev) {
         if (hipEventSynchronize(de) != hipSuccess) return PXCL_E_HIP;
         while (ev->state.load(std::memory_order_acquire) != ST_DONE) std::this_thread::yield();
     }
+    // the completion callback has returned too (unless this is that callback)
+    if (!t_in_callback)
+        while (ev->cb_pending.load(std::memory_order_acquire) > 0) std::this_thread::yield();
     return PXCL_OK;
 }
 
@@ -650,7 +679,12 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         }
     }
     if (e == hipSuccess) e = hipEventRecord(b->done_ev, s);
-    if (e == hipSuccess) e = hipLaunchHostFunc(s, batch_done_hostfn, b);
+    if (e == hipSuccess) {
+        for (u32 i = 0; i < k; ++i) evs[i]->cb_pending.fetch_add(1, std::memory_order_acq_rel);
+        e = hipLaunchHostFunc(s, batch_done_hostfn, b);
+        if (e != hipSuccess)
+            for (u32 i = 0; i < k; ++i) evs[i]->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
+    }
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
         (void)hipGetLastError();
