@@ -45,7 +45,7 @@ def kernel_src_sha() -> str:
 def load_traffic(workload: str, kernel: str):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if it was
     taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    p = os.path.join(ROOT, "profiles", f"pmc_{KERNEL_SYMBOLS[kernel]}_{workload}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -73,6 +73,52 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
     }
 
 
+COPY_BYTES = 1 << 30
+N_STREAMS = 4              # streams the batched workloads spread their launches over
+
+
+def profile_commands(workload: str) -> dict:
+    """The rocprofv3 commands whose output --summarize-profiles reads (run from the
+    repository root with the output directory DIR)."""
+    extra = "" if workload == "async" else " --no-graph"
+    steps = {"async": 100, "batch": 20, "stress": 10}.get(workload, 20)
+    b = f"python3 bench.py --workload {workload}{extra} --no-cpu-baseline"
+    pmc = f"{b} --steps {steps} --warmup 2"
+    return {
+        "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d DIR/kt_{workload} -o run -- {b}",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_{workload} -o run -- {pmc}",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_{workload} -o run -- {pmc}",
+        "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_copy -o run -- "
+                      "python3 bench.py --copy-calibration 5",
+        "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_copy -o run -- "
+                      "python3 bench.py --copy-calibration 5",
+    }
+
+
+def copy_bandwidth(torch, reps: int = 10):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy of
+    COPY_BYTES (read + write counted), timed with hipEvents."""
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    dt = t0.elapsed_time(t1) * 1e-3 / reps
+    del src, dst
+    return round(2 * COPY_BYTES / dt / 1e9, 1)
+
+
+def copy_calibration(torch, reps: int):
+    """Only the device copy (reps launches of COPY_BYTES): the reference for scaling
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    gbs = copy_bandwidth(torch, reps)
+    print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps, "copy_GBps": gbs}), flush=True)
+
+
 def cpu_baseline(events, seconds: float, unit_events: bool = True):
     """The oracle as it stands, single-threaded, over the workload's events for about
     `seconds` of CPU time."""
@@ -94,6 +140,86 @@ def cpu_baseline(events, seconds: float, unit_events: bool = True):
                       f"events, one thread, {dt:.1f} s"}
 
 
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    for k in KERNEL_SYMBOLS.values():
+        if f"::{k}(" in name or f"::{k}<" in name:
+            return k
+    return name
+
+
+def summarize_profiles(prof: str, workload: str, command: dict):
+    """Turn rocprofv3 output of one workload into the committed summaries:
+    profiles/kernels_<workload>.txt (kernel-trace statistics) and
+    profiles/pmc_<kernel>_<workload>.json per kernel (FETCH_SIZE and WRITE_SIZE per
+    dispatch, in KiB, scaled to bytes by the same counters on a device copy of
+    COPY_BYTES, whose true traffic is COPY_BYTES read and COPY_BYTES written)."""
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    stats = _read_csv(os.path.join(prof, f"kt_{workload}", "run_kernel_stats.csv"))
+    lines = [f"rocprofv3 kernel-trace statistics, workload {workload}",
+             f"command: {command['kt']}", "",
+             f"{'kernel':<40}{'calls':>8}{'avg_us':>10}{'min_us':>10}{'max_us':>10}{'pct':>8}"]
+    for r in stats:
+        lines.append(f"{_short(r['Name'])[:39]:<40}{int(r['Calls']):>8}{float(r['AverageNs']) / 1e3:>10.2f}"
+                     f"{float(r['MinNs']) / 1e3:>10.2f}{float(r['MaxNs']) / 1e3:>10.2f}{float(r['Percentage']):>8.2f}")
+    open(os.path.join(out_dir, f"kernels_{workload}.txt"), "w").write("\n".join(lines) + "\n")
+
+    def per_kernel(kind):
+        rows = _read_csv(os.path.join(prof, f"{kind}_{workload}", "run_counter_collection.csv"))
+        acc = {}
+        for r in rows:
+            acc.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+    def copy_factor(kind):
+        rows = _read_csv(os.path.join(prof, f"{kind}_copy", "run_counter_collection.csv"))
+        vals = [float(r["Counter_Value"]) for r in rows]
+        return COPY_BYTES / (sum(vals) / len(vals) * 1024.0)
+
+    fetch, write = per_kernel("fetch"), per_kernel("write")
+    ff, fw = copy_factor("fetch"), copy_factor("write")
+    sha = kernel_src_sha()
+    for k in KERNEL_SYMBOLS.values():
+        if k not in fetch or k not in write:
+            continue
+        fk, nf = fetch[k]
+        wk, nw = write[k]
+        d = {"kernel": k, "workload": workload, "kernel_src_sha": sha,
+             "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
+             "dispatches": [nf, nw], "copy_scale_fetch": round(ff, 4), "copy_scale_write": round(fw, 4),
+             "traffic_bytes_per_launch": int(fk * 1024 * ff + wk * 1024 * fw),
+             "commands": {"fetch": command["fetch"], "write": command["write"],
+                          "copy_fetch": command["copy_fetch"], "copy_write": command["copy_write"]}}
+        json.dump(d, open(os.path.join(out_dir, f"pmc_{k}_{workload}.json"), "w"), indent=1)
+    print(json.dumps({"workload": workload, "fetch_scale": ff, "write_scale": fw,
+                      "kernels": {k: [fetch.get(k), write.get(k)] for k in KERNEL_SYMBOLS.values()}}))
+
+
+def tune(px, ctx, args, events, digis, slots=None, batch=None):
+    """Run the library's autotuner on one representative launch of the workload
+    (every kernel shape, a few replays each) and keep the fastest shape; returns the
+    table of mean microseconds per shape."""
+    if args.no_autotune:
+        return None
+    own_b = batch is None
+    b = batch or px.Batch(ctx, len(events))
+    own_s = slots is None
+    sl = slots or [px.Event(ctx, max(1, e["module"].size)) for e in events]
+    times = px.autotune(ctx, b, sl[:len(events)], digis, reps=5)
+    if own_s:
+        for x in sl:
+            x.close()
+    if own_b:
+        b.close()
+    return {f"{wg}x{mpw}": round(t, 1) for (wg, mpw), t in sorted(times.items())}
+
+
 def gen_events(maker, count, **kw):
     return [maker(i, **kw) for i in range(count)]
 
@@ -107,6 +233,7 @@ def bench_async(px, torch, args, synth):
     cap = max(e["module"].size for e in evs)
     slots = [px.Event(ctx, cap) for _ in range(n_threads)]
     streams = [torch.cuda.Stream() for _ in range(n_threads)]
+    tuned = tune(px, ctx, args, evs[:1], pool[:1])
     kept = []
     for d in pool:                       # one pass for the kept-cluster counts (bytes per event)
         px.acquire(slots[0], d)
@@ -133,7 +260,8 @@ def bench_async(px, torch, args, synth):
         "config": {"workload": "async: 1856 modules x 160x416, ~50k digis/event, 4 host threads x 1 event "
                                "in flight, synthetic CPU tasks while waiting",
                    "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
-                   "host_threads": n_threads, "cpu_task_ns": args.cpu_task_ns, "distinct_events": len(evs)},
+                   "host_threads": n_threads, "cpu_task_ns": args.cpu_task_ns, "distinct_events": len(evs),
+                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
         "roofline": rl, "events": evs,
     }
     for s in slots:
@@ -148,6 +276,7 @@ def bench_plain(px, torch, args, synth):
     pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
     slot = px.Event(ctx, max(e["module"].size for e in evs))
     stream = torch.cuda.Stream()
+    tuned = tune(px, ctx, args, evs[:1], pool[:1])
     kept = []
     for d in pool:
         px.acquire(slot, d)
@@ -168,7 +297,8 @@ def bench_plain(px, torch, args, synth):
         "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
         "host_blocked_us_per_event": st["blocked_us_per_event"], "errors": st["errors"],
         "config": {"workload": "plain: 64 modules x 160x416, 46,912 digis/event, one event per synchronous launch",
-                   "n_modules": 64, "mean_digis": 46912, "distinct_events": len(evs)},
+                   "n_modules": 64, "mean_digis": 46912, "distinct_events": len(evs),
+                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
         "roofline": roofline(ctx, b_mean, "plain"), "events": evs,
     }
     slot.close()
@@ -181,10 +311,10 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_module
     working set larger than the 256 MB Infinity Cache); each copy has its own batch
     object and event slots, so the host only waits when it wraps around."""
     ctx = px.Context(n_modules, 2000)
-    if args.autotune:
-        px.autotune_load(ctx, os.path.join(ROOT, "profiles", "autotune.json"),
-                         int(np.mean([e["module"].size for e in evs])))
-    stream = torch.cuda.Stream()
+    # consecutive launches go to different streams, so that one batch's completion
+    # callback (a device -> host -> device round trip on its stream) overlaps the next
+    # batch's kernels
+    streams = [torch.cuda.Stream() for _ in range(N_STREAMS)]
     cap = max(e["module"].size for e in evs)
     groups = []
     for c in range(n_copies):
@@ -192,12 +322,13 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_module
         slots = [px.Event(ctx, cap) for _ in range(per_batch)]
         groups.append((px.Batch(ctx, per_batch), slots, digis))
     flags = [px.Flag() for _ in range(n_copies)]
+    tuned = tune(px, ctx, args, evs, groups[0][2], slots=groups[0][1], batch=groups[0][0])
 
-    def launch(i):
+    def launch(i, graph):
         b, slots, digis = groups[i % n_copies]
         while px.batch_query(b) == px.E_NOT_READY:     # this copy's previous launch
             time.sleep(0)
-        px.acquire_batch(b, slots, digis, stream, flag=flags[i % n_copies], graph=not args.no_graph)
+        px.acquire_batch(b, slots, digis, streams[i % N_STREAMS], flag=flags[i % n_copies], graph=graph)
 
     def drain():
         torch.cuda.synchronize()
@@ -205,35 +336,42 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_module
             while px.batch_query(g[0]) == px.E_NOT_READY:
                 time.sleep(0)
 
+    graph = not args.no_graph
     for i in range(max(args.warmup, n_copies)):          # also captures every graph
-        launch(i)
+        launch(i, graph)
     drain()
     res = [px.produce(s).n_clusters for s in groups[0][1]]
     b_batch = float(sum(event_bytes(e["module"].size, k) for e, k in zip(evs, res)))
-    ctx.set_timing(True)
-    for i in range(n_copies):                            # re-capture with timing events
-        launch(i)
-    drain()
+    if not graph:
+        ctx.set_timing(True)
     ctx.timing(reset=True)
     t0 = time.perf_counter()
     for i in range(args.steps):
-        launch(i)
+        launch(i, graph)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     drain()
+    if graph:
+        # hipEvents recorded inside a captured graph cannot be timed: the kernel times
+        # come from the same batches launched without a graph
+        ctx.set_timing(True)
+        for i in range(min(args.steps, 8 * n_copies)):
+            launch(i, False)
+        drain()
     for b, slots, _ in groups:
         b.close()
         for s in slots:
             s.close()
     rl = roofline(ctx, b_batch, workload)
+    rl["kernel_times_from"] = "graph-free launches of the same batches" if graph else "the timed launches"
     ctx.set_timing(False)
     n_dg = sum(e["module"].size for e in evs)
     out = {
         "value": per_batch * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
         "digis_per_s": n_dg * args.steps / wall,
         "config": {"workload": desc, "n_modules": n_modules, "events_per_launch": per_batch,
-                   "mean_digis": int(n_dg / len(evs)), "device_copies": n_copies,
-                   "kernel_config": list(ctx.kernel_config())},
+                   "mean_digis": int(n_dg / len(evs)), "device_copies": n_copies, "streams": N_STREAMS,
+                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
         "roofline": rl, "events": evs,
     }
     ctx.close()
@@ -263,26 +401,32 @@ def bench_serve(px, torch, args, synth):
     pinned = torch.empty(n_slots * 64, dtype=torch.uint8, pin_memory=True)
     batches = [px.Batch(ctx, max_batch) for _ in range(n_b)]
     streams = [torch.cuda.Stream() for _ in range(n_b)]
+    tuned = tune(px, ctx, args, evs[:16], pool[:16])      # a typical continuous batch
     common = dict(budget_bytes=16 << 30, n_slots=n_slots, max_batch=max_batch, n_cpu_threads=16,
                   cpu_task_ns=args.cpu_task_ns, graph=True)
     # calibration: saturated throughput (all requests arrive at once)
     cal, _, _ = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=1e9, n_requests=4000, seed=7, **common)
     sat = cal["events"] / cal["wall_s"]
     rate = 0.7 * sat
-    ctx.timing(reset=True)
-    ctx.set_timing(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=rate,
                                n_requests=args.steps, seed=11, **common)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # kernel times: hipEvents cannot be timed inside captured graphs, so a shorter run
+    # of the same request stream launches its batches without a graph
+    n_t = min(args.steps, 2000)
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    st_t, _, ncl_t = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=rate, n_requests=n_t,
+                              seed=11, **dict(common, graph=False))
+    torch.cuda.synchronize()
     for b in batches:
         b.close()
-    b_mean = float(np.mean([event_bytes(evs[r % len(evs)]["module"].size, ncl[r]) for r in range(args.steps)]))
-    n_batches = max(1, st["batches"])
-    rl = roofline(ctx, b_mean * args.steps / n_batches, "serve")
+    b_mean = float(np.mean([event_bytes(evs[r % len(evs)]["module"].size, ncl_t[r]) for r in range(n_t)]))
+    rl = roofline(ctx, b_mean * n_t / max(1, st_t["batches"]), "serve")
+    rl["kernel_times_from"] = f"graph-free launches of the first {n_t} requests"
     ctx.set_timing(False)
+    n_batches = max(1, st["batches"])
     out = {
         "value": st["events"] / st["wall_s"], "ms_per_step": st["wall_s"] * 1e3 / args.steps,
         "digis_per_s": st["digis"] / st["wall_s"],
@@ -293,6 +437,7 @@ def bench_serve(px, torch, args, synth):
                                "16 GB admission budget, continuous batching over 4 streams, 16 CPU threads",
                    "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
                    "requests": args.steps, "mean_events_per_launch": round(args.steps / n_batches, 2),
+                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned,
                    "peak_resident_bytes": st["peak_resident_bytes"]},
         "roofline": rl, "events": evs,
     }
@@ -315,8 +460,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="batched workloads: plain launches, no captured graph")
-    ap.add_argument("--autotune", action="store_true", help="load the kernel shape from profiles/autotune.json")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel shape instead of tuning it on the workload first")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
+                    help="only run REPS device copies of 1 GiB (counter calibration) and exit")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries of the workload from rocprofv3 output in DIR and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.workload, profile_commands(args.workload))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(events shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
@@ -331,9 +484,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    px.lib()
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration)
+        return
+    px.lib()
+    copy_gbs = copy_bandwidth(torch)
     r = fn(px, torch, args, synth)
+    r["roofline"]["copy_GBps"] = copy_gbs
+    r["roofline"]["frac_of_copy"] = round(r["roofline"]["achieved"] / copy_gbs, 5) if copy_gbs else None
     evs = r.pop("events")
     line = {
         "metric": "events/s + digis/s clustered (frac HBM peak); p50/p99 event latency; host block time",

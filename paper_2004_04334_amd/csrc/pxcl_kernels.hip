@@ -790,10 +790,22 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             if (j < n && lin[u] == NOPIX) err |= EB_RANGE;
         }
     };
-    // cluster index of the root of run `run`
+    const u32 wv = tid >> 6, lane = tid & 63u;
+    // cluster index of run `run` (after the flattening below, par[run] is its root)
     auto cluster_of = [&](u32 run) {
-        const u32 root = uf_find(s.par, run);
+        const u32 root = ld_wg(&s.par[run]);
         return u32(s.rootp[root >> 5]) + __popc(s.rootb[root >> 5] & ((1u << (root & 31u)) - 1u));
+    };
+    // s.rootb[] over all KW words: bit r set iff pred(r); a wave forms 64 bits at a time
+    // from 64 consecutive indices (ballot), so lanes touch consecutive words
+    auto set_bits = [&](auto pred) {
+        for (u32 base = wv * 64; base < KW * 32; base += B_WG) {
+            const u64 m = __ballot(pred(base + lane) ? 1 : 0);
+            if (lane == 0) {
+                s.rootb[base >> 5] = u32(m);
+                s.rootb[(base >> 5) + 1] = u32(m >> 32);
+            }
+        }
     };
     for (u32 base = 0; base < n; base += SPAN) {               // pass 1: bitmap
         u32 lin[UNR];
@@ -825,30 +837,38 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     }
     for (u32 r = tid; r < nruns; r += B_WG) s.par[r] = r;
     lds_barrier();
-    // unions, one run at a time, from the bitmap only
-    for (u32 w = tid; w < WORDS; w += B_WG) {
-        u32 sb = run_starts(s.bm, w);
-        u32 r = s.rpre[w];
-        const u32 col = w / WPC;
-        while (sb) {
-            const u32 b = __ffs(sb) - 1;
-            sb &= sb - 1;
-            const u32 r0 = (w % WPC) * 32 + b;                        // first row of the run
-            link_run(s.par, s.bm, s.rpre, r, col, r0, run_end(s.bm, col, r0));
-            ++r;
+    // Unions from the bitmap only.  Wave v links the runs of its block of columns to the
+    // next column, one column at a time from left to right, a lane per run start row.
+    // A run of the next column is then hooked straight under a root found in an earlier
+    // column, so the trees stay shallow even along chains that cross the module (a
+    // serpentine); unordered unions would build paths as long as the chain.
+    {
+        constexpr u32 NWV = B_WG / 64;
+        const u32 c0 = wv * COLS / NWV, c1 = (wv + 1) * COLS / NWV;
+        for (u32 col = c0; col < c1; ++col) {
+            for (u32 r0 = lane; r0 < ROWS; r0 += 64) {
+                const u32 lin = col * ROWS + r0;
+                if ((run_starts(s.bm, lin >> 5) >> (lin & 31u)) & 1u)
+                    link_run(s.par, s.bm, s.rpre, run_of(s.bm, s.rpre, lin), col, r0, run_end(s.bm, col, r0));
+            }
+            gsync<64>();                                        // this column's hooks before the next
         }
     }
     lds_barrier();
-    // roots (parent == self) number the clusters in order of their smallest index
-    for (u32 w = tid; w < KW; w += B_WG) {
-        u32 bits = 0;
-#pragma unroll
-        for (u32 i = 0; i < 32; ++i) {
-            const u32 r = w * 32 + i;
-            if (r < nruns && ld_wg(&s.par[r]) == r) bits |= 1u << i;
+    // flatten: every run points at its root.  Walks only read, and each store writes a
+    // root, so a concurrent walk through a stored entry still ends at the same root.
+    for (u32 r = tid; r < nruns; r += B_WG) {
+        u32 x = ld_wg(&s.par[r]);
+        for (u32 it = 0; it < MAX_RUNS; ++it) {
+            const u32 y = ld_wg(&s.par[x]);
+            if (y == x) break;
+            x = y;
         }
-        s.rootb[w] = bits;
+        st_wg(&s.par[r], x);
     }
+    lds_barrier();
+    // roots (parent == self) number the clusters in order of their smallest index
+    set_bits([&](u32 r) { return r < nruns && ld_wg(&s.par[r]) == r; });
     lds_barrier();
     u32 ncl;
     {
@@ -900,18 +920,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     wait_all_mem();
     lds_barrier();
     // cut; kept clusters -> staging records in cluster (= ascending id) order
-    for (u32 w = tid; w < KW; w += B_WG) {
-        u32 bits = 0;
-        if (w * 32 < ncl) {
-            u32 ch[32];
-#pragma unroll
-            for (u32 i = 0; i < 32; ++i) ch[i] = ld_ag(&cch[min(w * 32 + i, ncl - 1)]);
-#pragma unroll
-            for (u32 i = 0; i < 32; ++i)
-                if (w * 32 + i < ncl && ch[i] >= a.charge_cut) bits |= 1u << i;
-        }
-        s.rootb[w] = bits;                                     // kept clusters (roots rebuilt below)
-    }
+    set_bits([&](u32 c) { return c < ncl && ld_ag(&cch[c]) >= a.charge_cut; });   // kept clusters
     lds_barrier();
     u32 Kc;
     {
@@ -955,15 +964,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     wait_all_mem();
     lds_barrier();
     // the kept bits replaced the root bits: rebuild the roots for the last pass
-    for (u32 w = tid; w < KW; w += B_WG) {
-        u32 bits = 0;
-#pragma unroll
-        for (u32 i = 0; i < 32; ++i) {
-            const u32 r = w * 32 + i;
-            if (r < nruns && ld_wg(&s.par[r]) == r) bits |= 1u << i;
-        }
-        s.rootb[w] = bits;
-    }
+    set_bits([&](u32 r) { return r < nruns && ld_wg(&s.par[r]) == r; });
     lds_barrier();
     {
         u32 sw[KPT], cnt = 0, tot;

@@ -76,3 +76,13 @@ def test_scratch_mode_big_module(emulator):
     ev = synth.from_pixels(m, np.concatenate([tr, sr]), np.concatenate([tc, sc]), n_modules=3, seed=5)
     _check(emulator, [ev], 3, header=True, grids=(2, 2, 2, 2))
     _check(emulator, [ev], 3, header=True, grids=(2, 2, 2, 2), sanitizer="thread")
+
+
+def test_scratch_mode_column_serpentine_and_lattice(emulator):
+    """Scratch mode with a column-wise serpentine (one cluster along 416 columns) and an
+    even lattice (16,640 singleton clusters, about half of them cut)."""
+    sr, sc = synth.serpentine(row_wise=False)
+    lr, lc = np.meshgrid(np.arange(0, 160, 2), np.arange(0, 416, 2), indexing="ij")
+    m = np.concatenate([np.zeros(sr.size, np.int64), np.ones(lr.size, np.int64)])
+    ev = synth.from_pixels(m, np.concatenate([sr, lr.ravel()]), np.concatenate([sc, lc.ravel()]), n_modules=2, seed=6)
+    _check(emulator, [ev], 2, grids=(2, 2, 2, 2))
