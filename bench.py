@@ -68,7 +68,7 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
         "traffic": load_traffic(workload, dom),
         "algorithmic_bytes_per_launch": int(bytes_per_launch),
         "kernel_mean_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
-        "launches": int(max(cnt)),
+        "timed_launches": int(max(cnt)),
         "pipeline_GBps": round(bytes_per_launch / pipe / 1e9, 2) if pipe > 0 else 0.0,
     }
 
@@ -241,7 +241,7 @@ def bench_async(px, torch, args, synth):
         kept.append(px.produce(slots[0]).n_clusters)
     px.run_async(ctx, slots, streams, pool, max(1, args.warmup), cpu_task_ns=args.cpu_task_ns)
     ctx.timing(reset=True)
-    ctx.set_timing(True)
+    ctx.set_timing(True, args.timing_period)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = px.run_async(ctx, slots, streams, pool, args.steps, cpu_task_ns=args.cpu_task_ns)
@@ -284,7 +284,7 @@ def bench_plain(px, torch, args, synth):
         kept.append(px.produce(slot).n_clusters)
     px.run_async(ctx, [slot], [stream], pool, max(1, args.warmup), blocking=True)
     ctx.timing(reset=True)
-    ctx.set_timing(True)
+    ctx.set_timing(True, args.timing_period)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = px.run_async(ctx, [slot], [stream], pool, args.steps, blocking=True)
@@ -320,15 +320,15 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_module
     for c in range(n_copies):
         digis = [px.Digis.from_numpy(e, "cuda") for e in evs]
         slots = [px.Event(ctx, cap) for _ in range(per_batch)]
-        groups.append((px.Batch(ctx, per_batch), slots, digis))
+        groups.append((px.Batch(ctx, per_batch), slots, digis, px.BatchInputs(slots, digis)))
     flags = [px.Flag() for _ in range(n_copies)]
     tuned = tune(px, ctx, args, evs, groups[0][2], slots=groups[0][1], batch=groups[0][0])
 
-    def launch(i, graph):
-        b, slots, digis = groups[i % n_copies]
+    def launch(i, graph, stream=None):
+        b, _, _, prepared = groups[i % n_copies]
         while px.batch_query(b) == px.E_NOT_READY:     # this copy's previous launch
             time.sleep(0)
-        px.acquire_batch(b, slots, digis, streams[i % N_STREAMS], flag=flags[i % n_copies], graph=graph)
+        px.acquire_batch(b, prepared, None, stream or streams[i % N_STREAMS], flag=flags[i % n_copies], graph=graph)
 
     def drain():
         torch.cuda.synchronize()
@@ -343,22 +343,26 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_module
     res = [px.produce(s).n_clusters for s in groups[0][1]]
     b_batch = float(sum(event_bytes(e["module"].size, k) for e, k in zip(evs, res)))
     if not graph:
-        ctx.set_timing(True)
+        ctx.set_timing(True, args.timing_period)
     ctx.timing(reset=True)
     t0 = time.perf_counter()
+    host = 0.0
     for i in range(args.steps):
+        h0 = time.perf_counter()
         launch(i, graph)
+        host += time.perf_counter() - h0
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     drain()
     if graph:
         # hipEvents recorded inside a captured graph cannot be timed: the kernel times
         # come from the same batches launched without a graph
+        # (on one stream, so that concurrent batches do not stretch each other's kernels)
         ctx.set_timing(True)
         for i in range(min(args.steps, 8 * n_copies)):
-            launch(i, False)
+            launch(i, False, streams[0])
         drain()
-    for b, slots, _ in groups:
+    for b, slots, _, _ in groups:
         b.close()
         for s in slots:
             s.close()
@@ -369,6 +373,7 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_module
     out = {
         "value": per_batch * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
         "digis_per_s": n_dg * args.steps / wall,
+        "host_us_per_launch": host * 1e6 / args.steps,
         "config": {"workload": desc, "n_modules": n_modules, "events_per_launch": per_batch,
                    "mean_digis": int(n_dg / len(evs)), "device_copies": n_copies, "streams": N_STREAMS,
                    "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
@@ -462,6 +467,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="batched workloads: plain launches, no captured graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel shape instead of tuning it on the workload first")
+    ap.add_argument("--timing-period", type=int, default=8,
+                    help="time the kernels of every N-th launch of each event object in the timed region")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
                     help="only run REPS device copies of 1 GiB (counter calibration) and exit")
     ap.add_argument("--summarize-profiles", metavar="DIR",

@@ -137,13 +137,14 @@ int pxcl_set_kernel_config(pxcl_ctx* ctx, uint32_t wg, uint32_t mpw);
 int pxcl_get_kernel_config(const pxcl_ctx* ctx, uint32_t* wg, uint32_t* mpw);
 
 /* Per-kernel device timing: hipEvents recorded on the launch stream around each
- * kernel (also inside captured graphs, which are re-captured when this changes).
- * Off by default.  Stats: for each of the 4 kernels (0 segmentation, 1 big-module
+ * kernel of every period-th launch of each event or batch object (period 0: off,
+ * the default; 1: every launch).  Launches that replay a captured graph are never
+ * timed: elapsed times of events recorded inside a captured graph are not
+ * available.  Stats: for each of the 4 kernels (0 segmentation, 1 big-module
  * clustering, 2 small-module clustering, 3 compaction) the summed milliseconds and
- * launch count;
- * a launch is counted once its event is produced (single events) or the batch
- * object is used again or unbound (batches). */
-int pxcl_set_timing(pxcl_ctx* ctx, int enable);
+ * the number of timed launches; a launch is counted once its event is produced
+ * (single events) or the batch object is used again or unbound (batches). */
+int pxcl_set_timing(pxcl_ctx* ctx, int period);
 int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum /*[4]*/, uint64_t* launches /*[4]*/, int reset);
 
 /* ---- event slots ------------------------------------------------------------ */

@@ -281,31 +281,39 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
     }
     wait_all_mem();
     lds_barrier();
-    // pass 2: split into small and big modules.  A module whose start does not
-    // increase (module ids out of order, already flagged) gets no entry.
+    // pass 2: split into small and big modules, IDX_PER consecutive items per thread
+    // (one round for up to IDX_SPAN items).  A module whose start does not increase
+    // (module ids out of order, already flagged) gets no entry.
     u32 ns = 0, nb = 0;
-    for (u32 base = 0; base < items; base += A_WG) {
-        const u32 i = base + tid;
-        u32 cls = 0, s0 = 0, s1 = 0, m = 0;   // cls: 1 small, 2 big
-        if (i < items) {
-            if (one_pass) {
-                s0 = s_st[i];
-                s1 = s_st[i + 1];
-                m = s_cnt[i];
-            } else {
-                s0 = ld_ag(&item_start[i]);
-                s1 = ld_ag(&item_start[i + 1]);
-                m = 0xFFFFFFFFu;
-            }
-            if (s1 > s0) cls = (s1 - s0 <= a.dcap) ? 1u : 2u;
+    for (u32 base = 0; base < items; base += IDX_SPAN) {
+        const u32 i0 = base + tid * IDX_PER;
+        u32 st[IDX_PER + 1], md[IDX_PER];
+#pragma unroll
+        for (u32 j = 0; j <= IDX_PER; ++j) {
+            const u32 i = min(i0 + j, items);
+            st[j] = one_pass ? s_st[i] : ld_ag(&item_start[i]);
+            if (j < IDX_PER) md[j] = (one_pass && i < items) ? s_cnt[i] : 0xFFFFFFFFu;
         }
+        u32 cls = 0, cnt = 0;                  // 2 bits per item: 1 small, 2 big
+#pragma unroll
+        for (u32 j = 0; j < IDX_PER; ++j)
+            if (i0 + j < items && st[j + 1] > st[j]) {
+                const u32 c = (st[j + 1] - st[j] <= a.dcap) ? 1u : 2u;
+                cls |= c << (2 * j);
+                cnt += (c == 1) ? 1u : (1u << 16);
+            }
         u32 tot;
-        const u32 ex = group_excl_scan<A_WG>((cls == 1 ? 1u : 0u) | (cls == 2 ? 1u << 16 : 0u), tid, wsum, tot);
-        if (cls) {
-            if (m == 0xFFFFFFFFu) m = E.module[s0];   // module id from its first digi
-            const ItemEntry ent{i, s0, s1 - s0, m};
-            if (cls == 1) small[ns + (ex & 0xFFFFu)] = ent;
-            else big[nb + (ex >> 16)] = ent;
+        const u32 ex = group_excl_scan<A_WG>(cnt, tid, wsum, tot);
+        u32 ps = ns + (ex & 0xFFFFu), pb = nb + (ex >> 16);
+#pragma unroll
+        for (u32 j = 0; j < IDX_PER; ++j) {
+            const u32 c = (cls >> (2 * j)) & 3u;
+            if (c) {
+                const u32 m = md[j] != 0xFFFFFFFFu ? md[j] : E.module[st[j]];   // else from its first digi
+                const ItemEntry ent{i0 + j, st[j], st[j + 1] - st[j], m};
+                if (c == 1) small[ps++] = ent;
+                else big[pb++] = ent;
+            }
         }
         ns += tot & 0xFFFFu;
         nb += tot >> 16;
@@ -373,10 +381,13 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
 // ---------------------------------------------------------------------------
 constexpr u32 NOPIX = 0xFFFFFFFFu;
 
+constexpr u32 CMW = (COLS + 31) / 32;   // words of a per-module column mask
+
 template <u32 G, u32 K>
 struct RegModuleSmem {
     static constexpr u32 RCAP = G * K, KBW = RCAP / 32;
     u32 bm[WORDS];     // fired-pixel bitmap (clear between modules)
+    u32 cm[CMW];       // columns holding a fired pixel (clear between modules)
     u64 acc[RCAP];     // union-find parents (as u32, first half), then charge | size << 44
     u32 kb[KBW];       // kept-root bits over run index
     u16 rpre[WORDS];   // run starts before each word
@@ -390,17 +401,62 @@ struct Item {
     bool ok;
 };
 
-// Issue the loads of the module's digis j = lt + q*G (raw row, col, adc); the values
-// are only used when the module is clustered, so the loads stay in flight meanwhile.
+// The value of lane 0 in every lane (for values the whole wave holds alike: the
+// compiler then keeps them in scalar registers and branches on them uniformly).
+__device__ __forceinline__ u32 wave_uniform(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* wave_uniform(T* p) {
+    const u64 x = reinterpret_cast<u64>(p);
+    return reinterpret_cast<T*>(u64(wave_uniform(u32(x))) | (u64(wave_uniform(u32(x >> 32))) << 32));
+}
+__device__ __forceinline__ Item wave_uniform(const Item& I) {
+    return Item{wave_uniform(I.e), wave_uniform(I.it), wave_uniform(I.st), wave_uniform(I.n), wave_uniform(I.mod),
+                wave_uniform(I.ok ? 1u : 0u) != 0};
+}
+__device__ __forceinline__ EventDesc wave_uniform(const EventDesc& E) {
+    return EventDesc{wave_uniform(E.module), wave_uniform(E.row), wave_uniform(E.col), wave_uniform(E.adc),
+                     wave_uniform(E.ws), wave_uniform(E.hstat), wave_uniform(E.n), wave_uniform(E.cap),
+                     wave_uniform(E.epoch), 0u};
+}
+
+// Issue the loads of the module's digis j = lt + q*G < n (raw row, col, adc); the
+// values are only used when the module is clustered, so the loads stay in flight
+// meanwhile.  With few slots per thread, slots past the module's end are not
+// loaded; with many (the big-module kernel) every slot loads a digi of the module
+// (unconditional loads keep that kernel's register allocation within bounds).
 template <u32 G, u32 K>
 __device__ __forceinline__ void fetch_digis(const EventDesc& E, const Item& I, u32 lt, u32* R, u32* C, u32* A) {
 #pragma unroll
     for (u32 q = 0; q < K; ++q) {
         const u32 j = lt + q * G;
-        const u32 i = I.st + (j < I.n ? j : 0u);     // always inside the module
-        R[q] = E.row[i];
-        C[q] = E.col[i];
-        A[q] = E.adc[i];
+        if constexpr (K <= 8) {
+            R[q] = C[q] = A[q] = 0u;
+            if (q * G < I.n && j < I.n) {
+                R[q] = E.row[I.st + j];
+                C[q] = E.col[I.st + j];
+                A[q] = E.adc[I.st + j];
+            }
+        } else {
+            const u32 i = I.st + (j < I.n ? j : 0u);     // always inside the module
+            R[q] = E.row[i];
+            C[q] = E.col[i];
+            A[q] = E.adc[i];
+        }
+    }
+}
+
+// f(q) for the digi slots q < nq (nq uniform over the group).  With few slots per
+// thread the loop is not unrolled, so a large body appears once in the code (the
+// register arrays it indexes with the uniform q stay in registers).
+template <u32 K, typename F>
+__device__ __forceinline__ void for_slots(u32 nq, F f) {
+    if constexpr (K <= 8) {
+#pragma unroll 1
+        for (u32 q = 0; q < nq; ++q) f(q);
+    } else {
+#pragma unroll
+        for (u32 q = 0; q < K; ++q)
+            if (q < nq) f(q);
     }
 }
 
@@ -413,9 +469,10 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
                                              const Item& I, RegModuleSmem<G, K>& gp, u32 lt, const u32* R,
                                              const u32* C, const u32* A, Mid mid) {
     static_assert(G * K <= 65536, "run indices are kept in 16 bits");
-    constexpr u32 KBW = G * K / 32, WPT = (WORDS + G - 1) / G;
+    constexpr u32 KBW = G * K / 32, CPT = (COLS + G - 1) / G;
     u32* par = reinterpret_cast<u32*>(gp.acc);
     const bool act = I.ok;
+    const u32 nq = act ? min((I.n + G - 1) / G, K) : 0u;   // slots that may hold a digi
     u32 err = 0;
     // LIN: linear pixel index or NOPIX; AR: adc in the low 16 bits, then run / root
     u32 LIN[K], AR[K];
@@ -425,11 +482,12 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
         const u32 j = lt + q * G;
         LIN[q] = NOPIX;
         AR[q] = A[q] & 0xFFFFu;
-        if (act && j < I.n) {
+        if (q < nq && j < I.n) {
             if (R[q] < ROWS && C[q] < COLS) {
                 const u32 lin = C[q] * ROWS + R[q];
                 const u32 bit = 1u << (lin & 31u);
                 if (atomicOr(&gp.bm[lin >> 5], bit) & bit) err |= EB_DUP;
+                atomicOr(&gp.cm[C[q] >> 5], 1u << (C[q] & 31u));
                 LIN[q] = lin;
             } else {
                 err |= EB_RANGE;
@@ -438,25 +496,41 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
     }
     mid(0);
     gsync<G>();
-    // P2: run starts per word, prefix over words; parents
+    // P2: run starts per word of the columns holding a fired pixel (the only words
+    // whose run index is ever asked for), prefix over them in column order; parents.
+    // A thread takes CPT consecutive columns; per column the five word counts are kept
+    // packed, 6 bits each.
     u32 nruns = 0;
     {
-        u32 sw[WPT];
+        u32 pk[CPT];
         u32 cnt = 0;
-        const u32 w0 = lt * WPT;
+        const u32 c0 = lt * CPT;
 #pragma unroll
-        for (u32 i = 0; i < WPT; ++i) {
-            const u32 w = w0 + i;
-            sw[i] = (act && w < WORDS) ? __popc(run_starts(gp.bm, w)) : 0u;
-            cnt += sw[i];
+        for (u32 i = 0; i < CPT; ++i) {
+            const u32 c = c0 + i;
+            pk[i] = 0u;
+            if (act && c < COLS && ((gp.cm[c >> 5] >> (c & 31u)) & 1u)) {
+#pragma unroll
+                for (u32 k = 0; k < WPC; ++k) {
+                    const u32 v = __popc(run_starts(gp.bm, c * WPC + k));
+                    pk[i] |= v << (6 * k);
+                    cnt += v;
+                }
+                pk[i] |= 1u << 31;                       // column fired
+            }
         }
         const u32 ex = group_excl_scan<G>(cnt, lt, gp.wsum, nruns);
         u32 run = ex;
 #pragma unroll
-        for (u32 i = 0; i < WPT; ++i) {
-            const u32 w = w0 + i;
-            if (act && w < WORDS) gp.rpre[w] = u16(run);
-            run += sw[i];
+        for (u32 i = 0; i < CPT; ++i) {
+            if (pk[i] >> 31) {
+                const u32 c = c0 + i;
+#pragma unroll
+                for (u32 k = 0; k < WPC; ++k) {
+                    gp.rpre[c * WPC + k] = u16(run);
+                    run += (pk[i] >> (6 * k)) & 63u;
+                }
+            }
         }
     }
     if (act)
@@ -464,8 +538,7 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
     gsync<G>();
     mid(1);
     // P3: unions with the next column
-#pragma unroll
-    for (u32 q = 0; q < K; ++q) {
+    for_slots<K>(nq, [&](u32 q) {
         const u32 lin = LIN[q];
         if (lin != NOPIX) {
             const u32 col = lin / ROWS, row = lin - col * ROWS;
@@ -473,12 +546,11 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
             AR[q] |= r << 16;
             link_right(par, gp.bm, gp.rpre, lin, row, col, r);
         }
-    }
+    });
     gsync<G>();
     // P4: roots; the digi that starts its root's run speaks for the cluster
     u32 starts = 0;
-#pragma unroll
-    for (u32 q = 0; q < K; ++q) {
+    for_slots<K>(nq, [&](u32 q) {
         const u32 lin = LIN[q];
         if (lin != NOPIX) {
             const u32 run = AR[q] >> 16;
@@ -486,7 +558,7 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
             if (root == run && !((lin % ROWS) > 0 && fired(gp.bm, lin - 1))) starts |= 1u << q;
             AR[q] = (AR[q] & 0xFFFFu) | (root << 16);
         }
-    }
+    });
     gsync<G>();
     if (act) {
         for (u32 r = lt; r < nruns; r += G) gp.acc[r] = 0ull;
@@ -496,13 +568,13 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
     // P5: charge and size per root
 #pragma unroll
     for (u32 q = 0; q < K; ++q)
-        if (LIN[q] != NOPIX) atomicAdd(&gp.acc[AR[q] >> 16], (1ull << 44) | u64(AR[q] & 0xFFFFu));
+        if (q < nq && LIN[q] != NOPIX) atomicAdd(&gp.acc[AR[q] >> 16], (1ull << 44) | u64(AR[q] & 0xFFFFu));
     mid(2);
     gsync<G>();
     // P6: charge cut, one bit per kept root
 #pragma unroll
     for (u32 q = 0; q < K; ++q)
-        if (starts & (1u << q)) {
+        if (q < nq && (starts & (1u << q))) {
             const u32 r = AR[q] >> 16;
             if (u32(gp.acc[r]) >= a.charge_cut) atomicOr(&gp.kb[r >> 5], 1u << (r & 31u));
         }
@@ -523,7 +595,7 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
         const u32 idbase = I.mod * PIX;
 #pragma unroll
         for (u32 q = 0; q < K; ++q)
-            if (starts & (1u << q)) {
+            if (q < nq && (starts & (1u << q))) {
                 const u32 r = AR[q] >> 16;
                 const u64 v = gp.acc[r];
                 const u32 charge = u32(v), size = u32(v >> 44);
@@ -547,11 +619,12 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
 #pragma unroll
         for (u32 q = 0; q < K; ++q) {
             const u32 j = lt + q * G;
-            if (j < I.n) od[I.st + j] = (LIN[q] != NOPIX) ? int32_t(u32(gp.acc[AR[q] >> 16])) : -1;
+            if (q < nq && j < I.n) od[I.st + j] = (LIN[q] != NOPIX) ? int32_t(u32(gp.acc[AR[q] >> 16])) : -1;
         }
 #pragma unroll
         for (u32 q = 0; q < K; ++q)
-            if (LIN[q] != NOPIX) st_wg(&gp.bm[LIN[q] >> 5], 0u);   // several digis may share a word
+            if (q < nq && LIN[q] != NOPIX) st_wg(&gp.bm[LIN[q] >> 5], 0u);   // several digis may share a word
+        if (lt < CMW) gp.cm[lt] = 0u;
         if (err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, err);
     }
     gsync<G>();
@@ -580,6 +653,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     const u32 gofs = WAVE ? 0u : g;
     RegModuleSmem<G, K>& gp = s.grp[g];
     for (u32 w = lt; w < WORDS; w += G) gp.bm[w] = 0u;
+    if (lt < CMW) gp.cm[lt] = 0u;
     const u32 k = num_events(a);
     u32 total;
     if (k == 1) {                             // one event, alone or in a header
@@ -617,6 +691,8 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
             const ItemEntry ent = *entry_of(t, E, e);
             I = make_item(ent, E, e, true);
         }
+        I = wave_uniform(I);                      // one module per wave (or per group of waves)
+        E = wave_uniform(E);
         if (I.ok) fetch_digis<G, K>(E, I, lt, R, C, A);
     }
     u32 nv = 0;                                   // ticket of the next module (in flight)
@@ -652,7 +728,8 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
                     issue_entry();
                 }
             } else if (stage == 2) {
-                In = make_item(ent, En, ne, pent != nullptr);
+                In = wave_uniform(make_item(ent, En, ne, pent != nullptr));
+                En = wave_uniform(En);
                 if (In.ok) fetch_digis<G, K>(En, In, lt, NR, NC, NA);
             }
         };
@@ -1007,6 +1084,7 @@ __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
     __shared__ u32 s_wsum[B_WG / 64];
     const u32 tid = threadIdx.x;
     for (u32 w = tid; w < WORDS; w += B_WG) s.reg.bm[w] = 0u;   // bm leads both layouts
+    if (tid < CMW) s.reg.cm[tid] = 0u;
     const u32 k = num_events(a);
     const u32 total = event_prefix<B_WG>(a, k, s_pref, s_wsum, CTL_BIG, 1, 0);
     for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
@@ -1030,6 +1108,8 @@ __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
             cluster_regs<B_WG, K_BIG>(a, E, L, I, s.reg, tid, R, C, A, [](int) {});
         } else {
             cluster_scratch(a, E, L, I, s.scr);
+            if (tid < CMW) s.reg.cm[tid] = 0u;                 // the scratch layout overlaps it
+            lds_barrier();
         }
     }
 }

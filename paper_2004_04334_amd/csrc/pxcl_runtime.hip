@@ -99,6 +99,7 @@ struct pxcl_event {
     void* user = nullptr;
     pxcl_batch* batch = nullptr;
     std::atomic<int> cb_pending{0};   // launches whose completion callback has not returned
+    u32 launches = 0;                 // for sampling launches to time
 };
 
 struct pxcl_batch {
@@ -118,7 +119,7 @@ struct pxcl_batch {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     u32 g_wg = 0, g_mpw = 0;
-    bool g_timed = false;
+    u32 launches = 0;
     hipEvent_t tev[5] = {};
     bool timed = false;       // the launch in flight records per-kernel events
 };
@@ -317,9 +318,9 @@ extern "C" int pxcl_get_kernel_config(const pxcl_ctx* ctx, uint32_t* wg, uint32_
     return PXCL_OK;
 }
 
-extern "C" int pxcl_set_timing(pxcl_ctx* ctx, int enable) {
-    if (!ctx) return PXCL_E_INVAL;
-    ctx->timing.store(enable ? 1 : 0);
+extern "C" int pxcl_set_timing(pxcl_ctx* ctx, int period) {
+    if (!ctx || period < 0) return PXCL_E_INVAL;
+    ctx->timing.store(period);
     return PXCL_OK;
 }
 
@@ -416,7 +417,8 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     ev->status = PXCL_OK;
     __atomic_store_n(&ev->hs[HS_EPOCH], 0u, __ATOMIC_RELEASE);
     const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
-    const bool timed = ctx->timing.load() != 0;
+    const int period = ctx->timing.load();
+    const bool timed = period > 0 && (ev->launches++ % u32(period)) == 0;
     int prev = 0;
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
@@ -594,8 +596,8 @@ static LaunchArgs batch_args(pxcl_batch* b, u32 wg, u32 mpw) {
 
 // Capture the per-batch pipeline (header copy + four kernels, full grids) once per
 // kernel configuration; replays read k and the event descriptors from the header.
-static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, bool timed) {
-    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw && b->g_timed == timed) return hipSuccess;
+static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw) {
+    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw) return hipSuccess;
     drop_graph(b);
     pxcl_ctx* ctx = b->ctx;
     const LaunchArgs a = batch_args(b, wg, mpw);
@@ -604,7 +606,7 @@ static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, bool timed) {
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t e2 = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(b->max_events), hipMemcpyHostToDevice, cs);
-    if (e2 == hipSuccess) e2 = launch_all(a, g, wg, mpw, cs, timed ? b->tev : nullptr);
+    if (e2 == hipSuccess) e2 = launch_all(a, g, wg, mpw, cs, nullptr);
     e = hipStreamEndCapture(cs, &b->graph);
     if (e2 != hipSuccess) { if (b->graph) hipGraphDestroy(b->graph); b->graph = nullptr; return e2; }
     if (e != hipSuccess) return e;
@@ -612,7 +614,6 @@ static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, bool timed) {
     if (e != hipSuccess) { drop_graph(b); return e; }
     b->g_wg = wg;
     b->g_mpw = mpw;
-    b->g_timed = timed;
     return hipSuccess;
 }
 
@@ -642,7 +643,10 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     if (prev != ctx->device) hipSetDevice(ctx->device);
     const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
     if (b->timed) { b->timed = false; add_timing(ctx, b->tev); }   // the previous launch is complete
-    const bool timed = ctx->timing.load() != 0;
+    // graph replays are never timed (elapsed times of events recorded inside a captured
+    // graph are not available); plain launches are sampled every `period` launches
+    const int period = ctx->timing.load();
+    const bool timed = !(flags & PXCL_BATCH_GRAPH) && period > 0 && (b->launches++ % u32(period)) == 0;
     b->k = k;
     b->cb = cb;
     b->user = user;
@@ -669,7 +673,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     }
     if (e == hipSuccess) {
         if (flags & PXCL_BATCH_GRAPH) {
-            e = ensure_graph(b, wg, mpw, timed);
+            e = ensure_graph(b, wg, mpw);
             if (e == hipSuccess) e = hipGraphLaunch(b->gexec, s);
         } else {
             const LaunchArgs a = batch_args(b, wg, mpw);

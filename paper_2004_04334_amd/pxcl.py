@@ -246,8 +246,9 @@ class Context:
         _check(lib().pxcl_get_kernel_config(self._h, ctypes.byref(a), ctypes.byref(b)), "get_kernel_config")
         return a.value, b.value
 
-    def set_timing(self, enable: bool):
-        _check(lib().pxcl_set_timing(self._h, 1 if enable else 0), "set_timing")
+    def set_timing(self, enable, period: int = 1):
+        """Time the kernels of every `period`-th launch (enable False: off)."""
+        _check(lib().pxcl_set_timing(self._h, int(period) if enable else 0), "set_timing")
 
     def timing(self, reset: bool = False):
         ms = (ctypes.c_double * 4)()
@@ -367,13 +368,25 @@ def _batch_arrays(events: Sequence[Event], digis: Sequence[Digis]):
     return k, evs, ins
 
 
-def acquire_batch(batch: Batch, events: Sequence[Event], digis: Sequence[Digis], stream=None,
+class BatchInputs:
+    """The argument arrays of one batch (event objects and their digis), marshalled
+    once for repeated launches of the same inputs."""
+
+    def __init__(self, events: Sequence[Event], digis: Sequence[Digis]):
+        if len(events) != len(digis):
+            raise ValueError("one Digis per event")
+        self.k, self.evs, self.ins = _batch_arrays(events, digis)
+        self._keep = (list(events), list(digis))
+
+
+def acquire_batch(batch: Batch, events, digis: Optional[Sequence[Digis]] = None, stream=None,
                   flag: Optional[Flag] = None, graph: bool = False) -> None:
-    if len(events) != len(digis):
-        raise ValueError("one Digis per event")
-    k, evs, ins = _batch_arrays(events, digis)
+    """Launch a batch: `events` and `digis` are sequences of equal length, or `events`
+    is a BatchInputs (and `digis` None)."""
+    prepared = events if isinstance(events, BatchInputs) else BatchInputs(events, digis)
+    k, evs, ins = prepared.k, prepared.evs, prepared.ins
     cb_ptr, user = (flag_cb_ptr(), ctypes.addressof(flag)) if flag is not None else (None, None)
-    batch._keep = (list(digis), evs, ins, flag)
+    batch._keep = (prepared, flag)
     _check(lib().pxcl_acquire_batch(batch.handle, evs, ins, k, _stream_ptr(stream), cb_ptr, user,
                                     BATCH_GRAPH if graph else 0), "acquire_batch")
 
