@@ -67,14 +67,17 @@ extern "C" {
 #define PXCL_E_HIP (-8)         /* a HIP runtime call failed */
 #define PXCL_E_INTERNAL (-10)   /* a bounded device-side wait expired (library bug) */
 #define PXCL_E_NOTFOUND (-11)   /* autotune cache file missing or without this key */
+#define PXCL_E_HINT (-12)       /* async: a module has more digis than pxcl_digis.max_module_digis */
 
 /* Asynchronous error bits (pxcl_clusters.err_bits).  When several are set the
- * status reports, in this order: RANGE, ORDER, DUP.  With RANGE or ORDER set the
- * DUP bit is not reliable (grouping by module is then undefined). */
+ * status reports, in this order: RANGE, ORDER, HINT, DUP.  With RANGE or ORDER set
+ * the DUP bit is not reliable (grouping by module is then undefined); with HINT set
+ * the modules above the hint were not clustered. */
 #define PXCL_ERRBIT_RANGE 1u
 #define PXCL_ERRBIT_ORDER 2u
 #define PXCL_ERRBIT_DUP 4u
 #define PXCL_ERRBIT_INTERNAL 8u
+#define PXCL_ERRBIT_HINT 16u
 
 /* ---- types -------------------------------------------------------------------- */
 typedef struct pxcl_ctx pxcl_ctx;
@@ -91,7 +94,11 @@ typedef struct {
 
 /* Input digis: structure of arrays, grouped by non-decreasing module id, any order
  * within a module.  All four arrays hold n uint16 values and must stay valid and
- * unmodified until the done callback has fired. */
+ * unmodified until the done callback has fired.
+ * max_module_digis: optional upper bound on the digis of any one module (0 =
+ * unknown).  When it is at most the small-module kernel's capacity (workgroup size /
+ * modules per workgroup * 8 digis), the big-module kernel is not launched; a module
+ * above the bound is then not clustered and the event fails with PXCL_E_HINT. */
 typedef struct {
     const uint16_t* module;
     const uint16_t* row;
@@ -99,6 +106,7 @@ typedef struct {
     const uint16_t* adc;
     uint32_t n;
     int32_t where;        /* PXCL_WHERE_HOST or PXCL_WHERE_DEVICE */
+    uint32_t max_module_digis;
 } pxcl_digis;
 
 /* Completion callback.  Runs on a HIP runtime thread once the event's (or batch's)

@@ -51,7 +51,10 @@ enum : u32 { HS_EPOCH = 0, HS_ERR = 1, HS_NCL = 2, HS_ITEMS = 3, HS_BIG = 4, HS_
 constexpr u32 HS_BYTES = HS_WORDS * 4;
 
 // Error bits (same values as PXCL_ERRBIT_*).
-constexpr u32 EB_RANGE = 1, EB_ORDER = 2, EB_DUP = 4, EB_INTERNAL = 8;
+constexpr u32 EB_RANGE = 1, EB_ORDER = 2, EB_DUP = 4, EB_INTERNAL = 8, EB_HINT = 16;
+
+// Launch flags.
+constexpr u32 LF_NO_BIG = 1;   // the big-module kernel is not launched (size hint)
 
 // One event as the kernels see it (64 bytes).
 struct EventDesc {
@@ -83,7 +86,7 @@ struct LaunchArgs {
     u32 n_modules;
     u32 charge_cut;
     u32 dcap;           // largest module (digis) the small-module kernel takes
-    u32 pad;
+    u32 flags;          // LF_*
     EventDesc single;
 };
 

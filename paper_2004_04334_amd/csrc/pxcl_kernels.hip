@@ -242,6 +242,7 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
     const u32 M = a.n_modules, n = E.n;
     const u64* seg = ws_ptr<const u64>(E, L.seg);
     u32* item_start = ws_ptr<u32>(E, L.item_start);
+    u32* item_kept = ws_ptr<u32>(E, L.item_kept);
     u32* ctl = ws_ptr<u32>(E, L.ctl);
     ItemEntry* small = ws_ptr<ItemEntry>(E, L.small);
     ItemEntry* big = ws_ptr<ItemEntry>(E, L.big);
@@ -297,6 +298,9 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
         u32 cls = 0, cnt = 0;                  // 2 bits per item: 1 small, 2 big
 #pragma unroll
         for (u32 j = 0; j < IDX_PER; ++j)
+            if (i0 + j < items) item_kept[i0 + j] = 0u;   // a module left unclustered keeps nothing
+#pragma unroll
+        for (u32 j = 0; j < IDX_PER; ++j)
             if (i0 + j < items && st[j + 1] > st[j]) {
                 const u32 c = (st[j + 1] - st[j] <= a.dcap) ? 1u : 2u;
                 cls |= c << (2 * j);
@@ -322,6 +326,7 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
         ctl[CTL_SMALL] = ns;
         ctl[CTL_BIG] = nb;
         st_ag(&ctl[CTL_SEGDONE], 0u);
+        if (nb && (a.flags & LF_NO_BIG)) atomicOr(&ctl[CTL_ERR], EB_HINT);   // left unclustered
     }
 }
 
@@ -1174,7 +1179,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         for (u32 x = i0 + wv; x < i1; x += C_WG / 64) {
             const u32 off = s_off[x - i0], cnt = s_off[x - i0 + 1] - off;
             const u32 src = s_src[x - i0];
-            if (off + cnt > E.n || src + cnt > E.n) continue;   // inconsistent input (flagged)
+            if (cnt > E.n || off > E.n - cnt || src > E.n - cnt) continue;   // inconsistent (flagged)
             for (u32 j0 = 0; j0 < cnt; j0 += 64 * CP_UNR) {
                 int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
 #pragma unroll
@@ -1197,7 +1202,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             }
         }
         if (i1 >= items && tid == 0) {                     // the event's last chunk: status
-            const u32 ncl = items ? s_off[i1 - i0] : 0u;
+            const u32 ncl = items ? min(s_off[i1 - i0], E.n) : 0u;
             const u32 err = ctl[CTL_ERR];
             ctl[CTL_ERR] = 0u;
             ctl[CTL_NCL] = ncl;

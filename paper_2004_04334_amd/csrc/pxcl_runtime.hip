@@ -59,6 +59,7 @@ u32 next_epoch() {
 int status_from_bits(u32 bits) {
     if (bits & EB_RANGE) return PXCL_E_RANGE;
     if (bits & EB_ORDER) return PXCL_E_ORDER;
+    if (bits & EB_HINT) return PXCL_E_HINT;
     if (bits & EB_DUP) return PXCL_E_DUP_PIXEL;
     if (bits & EB_INTERNAL) return PXCL_E_INTERNAL;
     return PXCL_OK;
@@ -100,6 +101,7 @@ struct pxcl_event {
     pxcl_batch* batch = nullptr;
     std::atomic<int> cb_pending{0};   // launches whose completion callback has not returned
     u32 launches = 0;                 // for sampling launches to time
+    bool timed_big = false;           // the timed launch ran the big-module kernel
 };
 
 struct pxcl_batch {
@@ -118,8 +120,9 @@ struct pxcl_batch {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    u32 g_wg = 0, g_mpw = 0;
+    u32 g_wg = 0, g_mpw = 0, g_flags = 0;
     u32 launches = 0;
+    bool timed_big = false;
     hipEvent_t tev[5] = {};
     bool timed = false;       // the launch in flight records per-kernel events
 };
@@ -160,7 +163,7 @@ hipError_t launch_all(const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipS
     if (tev && (e = hipEventRecord(tev[0], s)) != hipSuccess) return e;
     if ((e = launch_segment(a, g.a, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
-    if ((e = launch_big(a, g.b, s)) != hipSuccess) return e;
+    if (!(a.flags & LF_NO_BIG) && (e = launch_big(a, g.b, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[2], s)) != hipSuccess) return e;
     if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[3], s)) != hipSuccess) return e;
@@ -210,7 +213,8 @@ void finish_event_from_host_status(pxcl_event* ev) {
     u32 bits = hs[HS_ERR];
     if (tag != ev->epoch) bits |= EB_INTERNAL;       // status write-back missing
     ev->err_bits = bits;
-    ev->ncl = hs[HS_NCL];
+    const u32 ncl = hs[HS_NCL];
+    ev->ncl = ncl < ev->n ? ncl : ev->n;              // never more clusters than digis
     ev->status = status_from_bits(bits);
 }
 
@@ -429,6 +433,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.n_modules = ctx->n_modules;
     a.charge_cut = ctx->charge_cut;
     a.dcap = cluster_capacity(wg, mpw);
+    if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
     hipError_t e = make_desc(ev, in, s, &a.single);
     const u64 items = std::min<u64>(in->n, (u64)ctx->n_modules);
     const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, false);
@@ -446,6 +451,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
         return PXCL_E_HIP;
     }
     ev->timed = timed;
+    ev->timed_big = !(a.flags & LF_NO_BIG);
     return PXCL_OK;
 }
 
@@ -457,12 +463,14 @@ extern "C" int pxcl_query(const pxcl_event* ev) {
     return PXCL_E_INVAL;
 }
 
-static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev) {
+// big: whether the big-module kernel was launched (otherwise it is not counted)
+static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev, bool big) {
     float ms[4];
     for (int i = 0; i < 4; ++i)
         if (hipEventElapsedTime(&ms[i], tev[i], tev[i + 1]) != hipSuccess) { (void)hipGetLastError(); return; }
     std::lock_guard<std::mutex> g(ctx->tmu);
     for (int i = 0; i < 4; ++i) {
+        if (i == 1 && !big) continue;
         ctx->tsum[i] += ms[i];
         ctx->tcnt[i] += 1;
     }
@@ -471,7 +479,7 @@ static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev) {
 static void collect_timing(pxcl_event* ev) {
     if (!ev->timed) return;
     ev->timed = false;
-    add_timing(ev->ctx, ev->tev);
+    add_timing(ev->ctx, ev->tev, ev->timed_big);
 }
 
 extern "C" int pxcl_produce(pxcl_event* ev, pxcl_clusters* out) {
@@ -573,7 +581,7 @@ static void drop_graph(pxcl_batch* b) {
 extern "C" int pxcl_batch_unbind(pxcl_batch* b) {
     if (!b) return PXCL_E_INVAL;
     if (b->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
-    if (b->timed) { b->timed = false; add_timing(b->ctx, b->tev); }
+    if (b->timed) { b->timed = false; add_timing(b->ctx, b->tev, b->timed_big); }
     drop_graph(b);
     hipEventDestroy(b->done_ev);
     for (int i = 0; i < 5; ++i) hipEventDestroy(b->tev[i]);
@@ -596,11 +604,12 @@ static LaunchArgs batch_args(pxcl_batch* b, u32 wg, u32 mpw) {
 
 // Capture the per-batch pipeline (header copy + four kernels, full grids) once per
 // kernel configuration; replays read k and the event descriptors from the header.
-static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw) {
-    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw) return hipSuccess;
+static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, u32 flags) {
+    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw && b->g_flags == flags) return hipSuccess;
     drop_graph(b);
     pxcl_ctx* ctx = b->ctx;
-    const LaunchArgs a = batch_args(b, wg, mpw);
+    LaunchArgs a = batch_args(b, wg, mpw);
+    a.flags = flags;
     const Grids g = grids_for(ctx, wg, mpw, 0, 0, 0, true);
     hipStream_t cs = b->cap_stream;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -614,6 +623,7 @@ static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw) {
     if (e != hipSuccess) { drop_graph(b); return e; }
     b->g_wg = wg;
     b->g_mpw = mpw;
+    b->g_flags = flags;
     return hipSuccess;
 }
 
@@ -642,7 +652,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
     const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
-    if (b->timed) { b->timed = false; add_timing(ctx, b->tev); }   // the previous launch is complete
+    if (b->timed) { b->timed = false; add_timing(ctx, b->tev, b->timed_big); }   // the previous launch is complete
     // graph replays are never timed (elapsed times of events recorded inside a captured
     // graph are not available); plain launches are sampled every `period` launches
     const int period = ctx->timing.load();
@@ -655,9 +665,12 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     EventDesc* hd = reinterpret_cast<EventDesc*>(b->hp + HDR_EV_OFFSET);
     hipError_t e = hipSuccess;
     u64 digis = 0, items = 0;
+    const u32 dcap = cluster_capacity(wg, mpw);
+    u32 lflags = LF_NO_BIG;                     // unless an event may hold a big module
     for (u32 i = 0; i < k && e == hipSuccess; ++i) {
         pxcl_event* ev = evs[i];
         b->evs[i] = ev;
+        if (!ins[i].max_module_digis || ins[i].max_module_digis > dcap) lflags = 0;
         ev->epoch = next_epoch();
         ev->n = ins[i].n;
         ev->cb = nullptr;
@@ -673,10 +686,11 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     }
     if (e == hipSuccess) {
         if (flags & PXCL_BATCH_GRAPH) {
-            e = ensure_graph(b, wg, mpw);
+            e = ensure_graph(b, wg, mpw, lflags);
             if (e == hipSuccess) e = hipGraphLaunch(b->gexec, s);
         } else {
-            const LaunchArgs a = batch_args(b, wg, mpw);
+            LaunchArgs a = batch_args(b, wg, mpw);
+            a.flags = lflags;
             e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
             const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), k, false);
             if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? b->tev : nullptr);
@@ -697,6 +711,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         return PXCL_E_HIP;
     }
     b->timed = timed;
+    b->timed_big = !(lflags & LF_NO_BIG);
     return PXCL_OK;
 }
 
@@ -724,6 +739,7 @@ extern "C" const char* pxcl_strerror(int code) {
         case PXCL_E_HIP: return "HIP runtime error";
         case PXCL_E_INTERNAL: return "internal error (device wait expired)";
         case PXCL_E_NOTFOUND: return "not found";
+        case PXCL_E_HINT: return "a module has more digis than the size hint";
         default: return "unknown error";
     }
 }

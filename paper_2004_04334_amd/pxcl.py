@@ -16,13 +16,14 @@ import os
 from dataclasses import dataclass
 from typing import Callable, Optional, Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpxcl.so")
 
 OK, E_INVAL, E_CAPACITY, E_BUSY, E_NOT_READY = 0, -1, -2, -3, -4
-E_DUP_PIXEL, E_RANGE, E_ORDER, E_HIP, E_INTERNAL, E_NOTFOUND = -5, -6, -7, -8, -10, -11
+E_DUP_PIXEL, E_RANGE, E_ORDER, E_HIP, E_INTERNAL, E_NOTFOUND, E_HINT = -5, -6, -7, -8, -10, -11, -12
 WHERE_HOST, WHERE_DEVICE = 0, 1
 BATCH_GRAPH = 1
 MAX_BATCH = 128
@@ -41,7 +42,8 @@ class _Config(ctypes.Structure):
 
 class _Digis(ctypes.Structure):
     _fields_ = [("module", ctypes.c_void_p), ("row", ctypes.c_void_p), ("col", ctypes.c_void_p),
-                ("adc", ctypes.c_void_p), ("n", ctypes.c_uint32), ("where", ctypes.c_int32)]
+                ("adc", ctypes.c_void_p), ("n", ctypes.c_uint32), ("where", ctypes.c_int32),
+                ("max_module_digis", ctypes.c_uint32)]
 
 
 class _Clusters(ctypes.Structure):
@@ -173,11 +175,14 @@ def flag_cb_ptr() -> int:
 @dataclass
 class Digis:
     """Digis of one event as four uint16 tensors (CUDA or pinned CPU), grouped by
-    non-decreasing module.  Keep the object alive until the done callback."""
+    non-decreasing module.  Keep the object alive until the done callback.
+    max_module_digis: an upper bound on the digis of any one module, or 0 (unknown);
+    a small bound lets the library skip its big-module kernel."""
     module: torch.Tensor
     row: torch.Tensor
     col: torch.Tensor
     adc: torch.Tensor
+    max_module_digis: int = 0
 
     @property
     def n(self) -> int:
@@ -194,10 +199,13 @@ class Digis:
                 raise ValueError("digis must be contiguous uint16 tensors of equal length")
             if t.is_cuda != self.module.is_cuda or (not t.is_cuda and not t.is_pinned()):
                 raise ValueError("digis must all be on the device or all in pinned host memory")
-        return _Digis(*(t.data_ptr() if self.n else None for t in ts), self.n, self.where)
+        return _Digis(*(t.data_ptr() if self.n else None for t in ts), self.n, self.where,
+                      int(self.max_module_digis))
 
     @staticmethod
-    def from_numpy(ev, device: str = "cuda") -> "Digis":
+    def from_numpy(ev, device: str = "cuda", hint: bool = True) -> "Digis":
+        """Copy a numpy event; with `hint`, the largest number of digis sharing a
+        module id is passed as max_module_digis."""
         ts = []
         for k in ("module", "row", "col", "adc"):
             t = torch.from_numpy(ev[k].astype("uint16", copy=True))
@@ -206,7 +214,8 @@ class Digis:
             elif device == "pinned":
                 t = t.pin_memory()
             ts.append(t.contiguous())
-        return Digis(*ts)
+        mx = int(np.bincount(ev["module"]).max()) if (hint and ev["module"].size) else 0
+        return Digis(*ts, max_module_digis=mx)
 
 
 @dataclass

@@ -3,11 +3,13 @@
 // any out-of-bounds access of the kernels aborts the run.  Test infrastructure.
 //
 // input:  u32 k, n_modules, cut, wg, mpw, grid_a, grid_b, grid_s, grid_c, header
-//         (1: the events go through a batch header even when k == 1);
+//         (1: the events go through a batch header even when k == 1), launch flags
+//         (LF_NO_BIG: the big-module kernel is not run);
 //         per event: u32 n, u32 cap, u16 module[n], row[n], col[n], adc[n]
 // output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
 #include "../../paper_2004_04334_amd/csrc/pxcl_kernels.hip"
 
+#include <algorithm>
 #include <cstdlib>
 #include <random>
 
@@ -21,7 +23,7 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: run_emu in out\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) return 2;
-    u32 h[10];
+    u32 h[11];
     rd(f, h, sizeof(h));
     const u32 k = h[0], M = h[1];
     std::vector<EventDesc> evs(k);
@@ -63,6 +65,7 @@ int main(int argc, char** argv) {
     a.n_modules = M;
     a.charge_cut = h[2];
     a.dcap = cluster_capacity(h[3], h[4]);
+    a.flags = h[10];
     const bool use_header = h[9] != 0;
     if (k == 1 && !use_header) {
         a.single = evs[0];
@@ -74,7 +77,7 @@ int main(int argc, char** argv) {
         a.ctr = reinterpret_cast<u32*>(aligned_alloc(64, 64));
         memset(a.ctr, 0, 64);
     }
-    if (launch_segment(a, h[5], nullptr) || launch_big(a, h[6], nullptr) ||
+    if (launch_segment(a, h[5], nullptr) || (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], nullptr)) ||
         launch_small(h[3], h[4], a, h[7], nullptr) || launch_compact(a, h[8], nullptr)) {
         fprintf(stderr, "launch failed\n");
         return 3;
@@ -82,7 +85,7 @@ int main(int argc, char** argv) {
     FILE* o = fopen(argv[2], "wb");
     for (u32 e = 0; e < k; ++e) {
         const EvLayout L = ev_layout(evs[e].cap, M);
-        const u32 err = hs[e][HS_ERR], ncl = hs[e][HS_NCL];
+        const u32 err = hs[e][HS_ERR], ncl = std::min(hs[e][HS_NCL], evs[e].n);
         const u32 tag = hs[e][HS_EPOCH];
         const u32 hdr2[2] = {tag == evs[e].epoch ? err : (err | 0x80000000u), ncl};
         fwrite(hdr2, 4, 2, o);

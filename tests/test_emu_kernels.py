@@ -102,3 +102,16 @@ def test_more_modules_than_one_indexing_round(emulator):
     assert emulator.cluster_event(ev, 2000)["status"] == 0
     _check(emulator, [ev], 5000, wg=64, mpw=1, grids=(2, 2, 3, 2))
     _check(emulator, [ev, ev], 5000, wg=256, mpw=2, grids=(3, 2, 2, 3))
+
+
+def test_size_hint_skips_big_kernel(emulator):
+    """Without the big-module kernel (a size hint at most the small kernel's capacity):
+    exact results when every module fits (733 and 700 digis <= 1,024 for 128-thread
+    groups), and the hint error, not silently missing clusters, when modules do not
+    (> 512 for 64-thread groups; the empty event is fine)."""
+    evs = _mixed_events()
+    _check(emulator, evs, 6, wg=128, mpw=1, grids=(2, 2, 3, 2), no_big=True)
+    res = emu.run(evs, 6, wg=64, mpw=1, grids=(2, 2, 3, 2), no_big=True)
+    assert [r["status"] for r in res] == [-12, 0, -12, -12]
+    assert all(r["err_bits"] & 16 for i, r in enumerate(res) if i != 1)
+    assert all(r["n_clusters"] <= e["module"].size for r, e in zip(res, evs))

@@ -199,6 +199,39 @@ def test_errors(px):
     ctx.close()
 
 
+def test_size_hint(px):
+    """max_module_digis: a bound at most the small kernel's capacity (2,048 digis for
+    256-thread groups) skips the big-module kernel.  Results are exact when the bound
+    holds or is absent; a module above a wrong bound fails the event with E_HINT
+    rather than losing clusters silently, and the slot stays usable."""
+    lin = (np.arange(3000) * 37) % (160 * 416)
+    big = synth.from_pixels(np.concatenate([np.zeros(40, np.int64), np.full(3000, 3)]),
+                            np.concatenate([np.arange(40) * 3 % 160, lin % 160]),
+                            np.concatenate([np.arange(40) * 5 % 416, lin // 160]), n_modules=8, seed=4)
+    small = synth.plain_event(3, n_modules=8)
+    ctx = _ctx(px, 8)
+    ctx.set_kernel_config(256, 1)
+    slot = px.Event(ctx, max(big["module"].size, small["module"].size))
+
+    def run(ev, digis):
+        px.acquire(slot, digis)
+        px.wait(slot)
+        return px.produce(slot).numpy()
+
+    d = px.Digis.from_numpy(big, "cuda")
+    assert d.max_module_digis == 3000
+    compare(run(big, d), oracle.cluster_event(big, 2000), "hint above capacity")
+    compare(run(big, px.Digis.from_numpy(big, "cuda", hint=False)), oracle.cluster_event(big, 2000), "no hint")
+    d.max_module_digis = 100
+    r = run(big, d)
+    assert r["status"] == px.E_HINT and r["n_clusters"] <= big["module"].size
+    ds = px.Digis.from_numpy(small, "cuda")
+    assert 0 < ds.max_module_digis <= 2048
+    compare(run(small, ds), oracle.cluster_event(small, 2000), "hint within capacity")
+    slot.close()
+    ctx.close()
+
+
 def test_full_size_async_and_stress(px):
     """Full-size events of the asynchronous and the stress configurations."""
     ctx = _ctx(px, 1856)
