@@ -680,11 +680,12 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         return I;
     };
 
-    // The first MPW modules of every workgroup are assigned statically, later ones
-    // come from a ticket counter offset by the static assignment.  The ticket of the
-    // module after next is drawn while the current one is clustered, the next
-    // module's work-list entry and digis are loaded meanwhile.
-    const u32 nstatic = gridDim.x * MPW;
+    // Modules are assigned statically in rounds (round r: module r*per_round + the
+    // group's index) for about three quarters of the work, the rest comes from a
+    // ticket counter, which every group contends for.  The ticket of the module after
+    // next is drawn while the current one is clustered, and the next module's
+    // work-list entry and digis are loaded meanwhile.
+    const u32 per_round = gridDim.x * MPW;
     u32 base = blockIdx.x * MPW + (WAVE ? g : 0u);
     EventDesc E{};
     Item I{0, 0, 0, 0, 0, false};
@@ -700,8 +701,12 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         E = wave_uniform(E);
         if (I.ok) fetch_digis<G, K>(E, I, lt, R, C, A);
     }
-    u32 nv = 0;                                   // ticket of the next module (in flight)
-    if ((WAVE && lt == 0) || (!WAVE && tid == 0)) nv = atomicAdd(&a.ctr[S_TICK], STEP) + nstatic;
+    const u32 nrounds = per_round < total ? max(1u, u32((3ull * total) / (4ull * per_round))) : 1u;   // static
+    const u32 nstatic = nrounds * per_round;
+    const bool dyn = nstatic < total;             // tickets needed at all
+    u32 round = 0;                                // round of the current module (>= nrounds: dynamic)
+    u32 nv = total;                               // ticket of the next dynamic module (in flight)
+    if (dyn && nrounds == 1 && ((WAVE && lt == 0) || (!WAVE && tid == 0))) nv = atomicAdd(&a.ctr[S_TICK], STEP) + nstatic;
 
     while (base < total) {
         u32 nbase = total, nv2 = 0, ne = 0;
@@ -719,13 +724,17 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         };
         auto mid = [&](int stage) {
             if (stage == 0) {
+                const bool snext = round + 1 < nrounds;            // next module static
+                const bool draw = dyn && round + 2 >= nrounds;     // module after next dynamic
                 if constexpr (WAVE) {
-                    nbase = __builtin_amdgcn_readfirstlane(nv);
-                    if (lt == 0) nv2 = atomicAdd(&a.ctr[S_TICK], 1u) + nstatic;
+                    nbase = snext ? base + per_round : __builtin_amdgcn_readfirstlane(nv);
+                    nv2 = total;
+                    if (draw && lt == 0 && nbase < total) nv2 = atomicAdd(&a.ctr[S_TICK], 1u) + nstatic;
                     issue_entry();
                 } else if (tid == 0) {
-                    s.tick[1] = nv;
-                    nv2 = atomicAdd(&a.ctr[S_TICK], STEP) + nstatic;
+                    const u32 nx = snext ? base + per_round : nv;
+                    s.tick[1] = nx;
+                    nv2 = (draw && nx < total) ? atomicAdd(&a.ctr[S_TICK], STEP) + nstatic : total;
                 }
             } else if (stage == 1) {
                 if constexpr (!WAVE) {
@@ -753,6 +762,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         E = En;
         I = In;
         nv = nv2;
+        ++round;
 #pragma unroll
         for (u32 q = 0; q < K; ++q) { R[q] = NR[q]; C[q] = NC[q]; A[q] = NA[q]; }
     }
