@@ -233,43 +233,47 @@ __device__ __forceinline__ void link_right(u32* par, const u32* bm, const u16* r
 // segment
 // ---------------------------------------------------------------------------
 constexpr u32 IDX_PER = 8, IDX_SPAN = A_WG * IDX_PER;   // modules per thread / per pass
+constexpr u32 NONE = 0xFFFFFFFFu;
 
-// Turn the event's per-module table into the ordered item list and the two work
-// lists.  Run by one whole workgroup of A_WG threads; s_st holds IDX_SPAN + 1 words.
+// Turn the event's per-module first digi (first(m): the first digi of module m, or
+// NONE if absent) into the ordered item list and the two work lists.  Run by one
+// whole workgroup of WGS threads, PER modules per thread and pass; s_st holds
+// WGS*PER + 1 words, s_cnt WGS*PER.
+template <u32 WGS, u32 PER, typename First>
 __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc& E, const EvLayout& L,
-                                            u32* wsum, u32* s_st, u32* s_cnt) {
+                                            u32* wsum, u32* s_st, u32* s_cnt, First first) {
+    constexpr u32 SPAN = WGS * PER;
     const u32 tid = threadIdx.x;
     const u32 M = a.n_modules, n = E.n;
-    const u64* seg = ws_ptr<const u64>(E, L.seg);
     u32* item_start = ws_ptr<u32>(E, L.item_start);
     u32* item_kept = ws_ptr<u32>(E, L.item_kept);
     u32* ctl = ws_ptr<u32>(E, L.ctl);
     ItemEntry* small = ws_ptr<ItemEntry>(E, L.small);
     ItemEntry* big = ws_ptr<ItemEntry>(E, L.big);
-    const bool one_pass = M <= IDX_SPAN;
-    // pass 1: modules present, in module order (one load round per IDX_SPAN modules)
+    const bool one_pass = M <= SPAN;
+    // pass 1: modules present, in module order (one load round per SPAN modules)
     u32 items = 0;
-    for (u32 base = 0; base < M; base += IDX_SPAN) {
-        u64 v[IDX_PER];
+    for (u32 base = 0; base < M; base += SPAN) {
+        u32 v[PER];
 #pragma unroll
-        for (u32 j = 0; j < IDX_PER; ++j) {
-            const u32 m = base + tid * IDX_PER + j;
-            v[j] = m < M ? ld_ag64(&seg[m]) : 0ull;
+        for (u32 j = 0; j < PER; ++j) {
+            const u32 m = base + tid * PER + j;
+            v[j] = m < M ? first(m) : NONE;
         }
         u32 flags = 0;
 #pragma unroll
-        for (u32 j = 0; j < IDX_PER; ++j)
-            if (base + tid * IDX_PER + j < M && u32(v[j] >> 32) == E.epoch) flags |= 1u << j;
+        for (u32 j = 0; j < PER; ++j)
+            if (v[j] != NONE) flags |= 1u << j;
         u32 tot;
-        u32 r = items + group_excl_scan<A_WG>(__popc(flags), tid, wsum, tot);
+        u32 r = items + group_excl_scan<WGS>(__popc(flags), tid, wsum, tot);
 #pragma unroll
-        for (u32 j = 0; j < IDX_PER; ++j)
+        for (u32 j = 0; j < PER; ++j)
             if (flags & (1u << j)) {
-                const u32 st = min(u32(v[j]), n);
+                const u32 st = min(v[j], n);
                 st_ag(&item_start[r], st);
                 if (one_pass) {
                     s_st[r] = st;
-                    s_cnt[r] = base + tid * IDX_PER + j;   // module id
+                    s_cnt[r] = base + tid * PER + j;   // module id
                 }
                 ++r;
             }
@@ -282,38 +286,38 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
     }
     wait_all_mem();
     lds_barrier();
-    // pass 2: split into small and big modules, IDX_PER consecutive items per thread
-    // (one round for up to IDX_SPAN items).  A module whose start does not increase
+    // pass 2: split into small and big modules, PER consecutive items per thread
+    // (one round for up to SPAN items).  A module whose start does not increase
     // (module ids out of order, already flagged) gets no entry.
     u32 ns = 0, nb = 0;
-    for (u32 base = 0; base < items; base += IDX_SPAN) {
-        const u32 i0 = base + tid * IDX_PER;
-        u32 st[IDX_PER + 1], md[IDX_PER];
+    for (u32 base = 0; base < items; base += SPAN) {
+        const u32 i0 = base + tid * PER;
+        u32 st[PER + 1], md[PER];
 #pragma unroll
-        for (u32 j = 0; j <= IDX_PER; ++j) {
+        for (u32 j = 0; j <= PER; ++j) {
             const u32 i = min(i0 + j, items);
             st[j] = one_pass ? s_st[i] : ld_ag(&item_start[i]);
-            if (j < IDX_PER) md[j] = (one_pass && i < items) ? s_cnt[i] : 0xFFFFFFFFu;
+            if (j < PER) md[j] = (one_pass && i < items) ? s_cnt[i] : NONE;
         }
         u32 cls = 0, cnt = 0;                  // 2 bits per item: 1 small, 2 big
 #pragma unroll
-        for (u32 j = 0; j < IDX_PER; ++j)
+        for (u32 j = 0; j < PER; ++j)
             if (i0 + j < items) item_kept[i0 + j] = 0u;   // a module left unclustered keeps nothing
 #pragma unroll
-        for (u32 j = 0; j < IDX_PER; ++j)
+        for (u32 j = 0; j < PER; ++j)
             if (i0 + j < items && st[j + 1] > st[j]) {
                 const u32 c = (st[j + 1] - st[j] <= a.dcap) ? 1u : 2u;
                 cls |= c << (2 * j);
                 cnt += (c == 1) ? 1u : (1u << 16);
             }
         u32 tot;
-        const u32 ex = group_excl_scan<A_WG>(cnt, tid, wsum, tot);
+        const u32 ex = group_excl_scan<WGS>(cnt, tid, wsum, tot);
         u32 ps = ns + (ex & 0xFFFFu), pb = nb + (ex >> 16);
 #pragma unroll
-        for (u32 j = 0; j < IDX_PER; ++j) {
+        for (u32 j = 0; j < PER; ++j) {
             const u32 c = (cls >> (2 * j)) & 3u;
             if (c) {
-                const u32 m = md[j] != 0xFFFFFFFFu ? md[j] : E.module[st[j]];   // else from its first digi
+                const u32 m = md[j] != NONE ? md[j] : E.module[st[j]];   // else from its first digi
                 const ItemEntry ent{i0 + j, st[j], st[j + 1] - st[j], m};
                 if (c == 1) small[ps++] = ent;
                 else big[pb++] = ent;
@@ -325,7 +329,6 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
     if (tid == 0) {
         ctl[CTL_SMALL] = ns;
         ctl[CTL_BIG] = nb;
-        st_ag(&ctl[CTL_SEGDONE], 0u);
         if (nb && (a.flags & LF_NO_BIG)) atomicOr(&ctl[CTL_ERR], EB_HINT);   // left unclustered
     }
 }
@@ -376,8 +379,80 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
             s_last = (atomicAdd(&ctl[CTL_SEGDONE], 1u) == chunks - 1) ? 1u : 0u;
         }
         lds_barrier();
-        if (s_last) index_event(a, E, L, s_wsum, s_st, s_md);
+        if (s_last) {
+            const u64* seg_c = seg;
+            index_event<A_WG, IDX_PER>(a, E, L, s_wsum, s_st, s_md, [&](u32 m) {
+                const u64 v = ld_ag64(&seg_c[m]);
+                return u32(v >> 32) == E.epoch ? u32(v) : NONE;
+            });
+            if (tid == 0) st_ag(ws_ptr<u32>(E, L.ctl) + CTL_SEGDONE, 0u);
+        }
         lds_barrier();
+    }
+}
+
+// Segmentation with one workgroup per event, for events of at most S1_MAX_DIGIS
+// digis and S1_MAX_MODULES modules: the first digi of every module present is kept
+// in LDS, so the event is indexed without waiting for other workgroups.  Module ids
+// are read S1_VEC at a time (one 16-byte load) with S1_UNR loads in flight per thread.
+constexpr u32 S1_WG = 1024, S1_PER = 2, S1_VEC = 8, S1_UNR = 4;
+constexpr u32 S1_TILE = S1_WG * S1_VEC * S1_UNR;   // digis per round
+constexpr u32 S1_MAX_MODULES = S1_WG * S1_PER;
+constexpr u32 S1_MAX_DIGIS = 1u << 18;
+
+__global__ __launch_bounds__(S1_WG) void k_segment1(LaunchArgs a) {
+    __shared__ u32 s_first[S1_MAX_MODULES];
+    __shared__ u32 s_st[S1_MAX_MODULES + 1];
+    __shared__ u32 s_md[S1_MAX_MODULES];
+    __shared__ u32 s_wsum[S1_WG / 64];
+    __shared__ u32 s_err;
+    const u32 tid = threadIdx.x;
+    const u32 k = num_events(a), M = a.n_modules;
+    for (u32 e = blockIdx.x; e < k; e += gridDim.x) {
+        const EventDesc E = get_event(a, e);
+        const EvLayout L = ev_layout(E.cap, M);
+        const u32 n = E.n;
+        for (u32 m = tid; m < M; m += S1_WG) s_first[m] = NONE;
+        if (tid == 0) s_err = 0;
+        lds_barrier();
+        u32 err = 0;
+        const bool vec = (reinterpret_cast<uintptr_t>(E.module) & 15u) == 0;
+        for (u32 base = 0; base < n; base += S1_TILE) {
+            u32 id[S1_UNR][S1_VEC], prev[S1_UNR];
+#pragma unroll
+            for (u32 u = 0; u < S1_UNR; ++u) {
+                const u32 i0 = base + (u * S1_WG + tid) * S1_VEC;
+                if (vec && i0 + S1_VEC <= n) {
+                    const uint4 q = *reinterpret_cast<const uint4*>(E.module + i0);
+                    const u32 w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (u32 j = 0; j < S1_VEC; ++j) id[u][j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                } else {
+#pragma unroll
+                    for (u32 j = 0; j < S1_VEC; ++j) id[u][j] = (i0 + j < n) ? E.module[i0 + j] : 0u;
+                }
+                prev[u] = (i0 > 0 && i0 < n) ? E.module[i0 - 1] : 0u;
+            }
+#pragma unroll
+            for (u32 u = 0; u < S1_UNR; ++u) {
+                const u32 i0 = base + (u * S1_WG + tid) * S1_VEC;
+#pragma unroll
+                for (u32 j = 0; j < S1_VEC; ++j) {
+                    const u32 i = i0 + j;
+                    if (i < n) {
+                        const u32 m = id[u][j], pm = j ? id[u][j - 1] : prev[u];
+                        if (i > 0 && m < pm) err |= EB_ORDER;
+                        if (m >= M) err |= EB_RANGE;
+                        else if (i == 0 || m != pm) s_first[m] = i;   // one writer per module when ordered
+                    }
+                }
+            }
+        }
+        if (err) atomicOr(&s_err, err);
+        lds_barrier();
+        if (tid == 0 && s_err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, s_err);
+        index_event<S1_WG, S1_PER>(a, E, L, s_wsum, s_st, s_md, [&](u32 m) { return s_first[m]; });
+        lds_barrier();                                   // before the next event reuses the tables
     }
 }
 
@@ -1264,10 +1339,13 @@ int occupancy_cluster(u32 wg, u32 mpw) {
 int occupancy_big() { return occ(reinterpret_cast<const void*>(k_big), B_WG); }
 int occupancy_compact() { return occ(reinterpret_cast<const void*>(k_compact), C_WG); }
 
+// With LF_SEG1, `grid` workgroups each take whole events (grid >= 1).
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_segment, dim3(grid), dim3(A_WG), 0, s, a);
+    if (a.flags & LF_SEG1) hipLaunchKernelGGL(k_segment1, dim3(grid), dim3(S1_WG), 0, s, a);
+    else hipLaunchKernelGGL(k_segment, dim3(grid), dim3(A_WG), 0, s, a);
     return hipGetLastError();
 }
+bool segment1_fits(u32 n_modules, u32 n_digis) { return n_modules <= S1_MAX_MODULES && n_digis <= S1_MAX_DIGIS; }
 hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s) {
     SmallKernel f = small_kernel(wg, mpw);
     if (!f) return hipErrorInvalidValue;
