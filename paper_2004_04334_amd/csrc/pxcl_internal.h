@@ -55,7 +55,6 @@ constexpr u32 EB_RANGE = 1, EB_ORDER = 2, EB_DUP = 4, EB_INTERNAL = 8, EB_HINT =
 
 // Launch flags.
 constexpr u32 LF_NO_BIG = 1;   // the big-module kernel is not launched (size hint)
-constexpr u32 LF_SEG1 = 2;     // segmentation with one workgroup per event
 
 // One event as the kernels see it (64 bytes).
 struct EventDesc {

@@ -391,71 +391,6 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
     }
 }
 
-// Segmentation with one workgroup per event, for events of at most S1_MAX_DIGIS
-// digis and S1_MAX_MODULES modules: the first digi of every module present is kept
-// in LDS, so the event is indexed without waiting for other workgroups.  Module ids
-// are read S1_VEC at a time (one 16-byte load) with S1_UNR loads in flight per thread.
-constexpr u32 S1_WG = 1024, S1_PER = 2, S1_VEC = 8, S1_UNR = 4;
-constexpr u32 S1_TILE = S1_WG * S1_VEC * S1_UNR;   // digis per round
-constexpr u32 S1_MAX_MODULES = S1_WG * S1_PER;
-constexpr u32 S1_MAX_DIGIS = 1u << 18;
-
-__global__ __launch_bounds__(S1_WG) void k_segment1(LaunchArgs a) {
-    __shared__ u32 s_first[S1_MAX_MODULES];
-    __shared__ u32 s_st[S1_MAX_MODULES + 1];
-    __shared__ u32 s_md[S1_MAX_MODULES];
-    __shared__ u32 s_wsum[S1_WG / 64];
-    __shared__ u32 s_err;
-    const u32 tid = threadIdx.x;
-    const u32 k = num_events(a), M = a.n_modules;
-    for (u32 e = blockIdx.x; e < k; e += gridDim.x) {
-        const EventDesc E = get_event(a, e);
-        const EvLayout L = ev_layout(E.cap, M);
-        const u32 n = E.n;
-        for (u32 m = tid; m < M; m += S1_WG) s_first[m] = NONE;
-        if (tid == 0) s_err = 0;
-        lds_barrier();
-        u32 err = 0;
-        const bool vec = (reinterpret_cast<uintptr_t>(E.module) & 15u) == 0;
-        for (u32 base = 0; base < n; base += S1_TILE) {
-            u32 id[S1_UNR][S1_VEC], prev[S1_UNR];
-#pragma unroll
-            for (u32 u = 0; u < S1_UNR; ++u) {
-                const u32 i0 = base + (u * S1_WG + tid) * S1_VEC;
-                if (vec && i0 + S1_VEC <= n) {
-                    const uint4 q = *reinterpret_cast<const uint4*>(E.module + i0);
-                    const u32 w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                    for (u32 j = 0; j < S1_VEC; ++j) id[u][j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-                } else {
-#pragma unroll
-                    for (u32 j = 0; j < S1_VEC; ++j) id[u][j] = (i0 + j < n) ? E.module[i0 + j] : 0u;
-                }
-                prev[u] = (i0 > 0 && i0 < n) ? E.module[i0 - 1] : 0u;
-            }
-#pragma unroll
-            for (u32 u = 0; u < S1_UNR; ++u) {
-                const u32 i0 = base + (u * S1_WG + tid) * S1_VEC;
-#pragma unroll
-                for (u32 j = 0; j < S1_VEC; ++j) {
-                    const u32 i = i0 + j;
-                    if (i < n) {
-                        const u32 m = id[u][j], pm = j ? id[u][j - 1] : prev[u];
-                        if (i > 0 && m < pm) err |= EB_ORDER;
-                        if (m >= M) err |= EB_RANGE;
-                        else if (i == 0 || m != pm) s_first[m] = i;   // one writer per module when ordered
-                    }
-                }
-            }
-        }
-        if (err) atomicOr(&s_err, err);
-        lds_barrier();
-        if (tid == 0 && s_err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, s_err);
-        index_event<S1_WG, S1_PER>(a, E, L, s_wsum, s_st, s_md, [&](u32 m) { return s_first[m]; });
-        lds_barrier();                                   // before the next event reuses the tables
-    }
-}
-
 // ---------------------------------------------------------------------------
 // clustering of one module with its digis in registers (K per thread, group of G)
 // ---------------------------------------------------------------------------
@@ -1339,13 +1274,10 @@ int occupancy_cluster(u32 wg, u32 mpw) {
 int occupancy_big() { return occ(reinterpret_cast<const void*>(k_big), B_WG); }
 int occupancy_compact() { return occ(reinterpret_cast<const void*>(k_compact), C_WG); }
 
-// With LF_SEG1, `grid` workgroups each take whole events (grid >= 1).
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s) {
-    if (a.flags & LF_SEG1) hipLaunchKernelGGL(k_segment1, dim3(grid), dim3(S1_WG), 0, s, a);
-    else hipLaunchKernelGGL(k_segment, dim3(grid), dim3(A_WG), 0, s, a);
+    hipLaunchKernelGGL(k_segment, dim3(grid), dim3(A_WG), 0, s, a);
     return hipGetLastError();
 }
-bool segment1_fits(u32 n_modules, u32 n_digis) { return n_modules <= S1_MAX_MODULES && n_digis <= S1_MAX_DIGIS; }
 hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s) {
     SmallKernel f = small_kernel(wg, mpw);
     if (!f) return hipErrorInvalidValue;

@@ -29,7 +29,6 @@ int occupancy_cluster(u32 wg, u32 mpw);
 int occupancy_big();
 int occupancy_compact();
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s);
-bool segment1_fits(u32 n_modules, u32 n_digis);
 hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_big(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
@@ -435,11 +434,9 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.charge_cut = ctx->charge_cut;
     a.dcap = cluster_capacity(wg, mpw);
     if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
-    if (segment1_fits(ctx->n_modules, in->n)) a.flags |= LF_SEG1;
     hipError_t e = make_desc(ev, in, s, &a.single);
     const u64 items = std::min<u64>(in->n, (u64)ctx->n_modules);
-    Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, false);
-    if (a.flags & LF_SEG1) g.a = 1;
+    const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, false);
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) {
@@ -613,8 +610,7 @@ static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, u32 flags) {
     pxcl_ctx* ctx = b->ctx;
     LaunchArgs a = batch_args(b, wg, mpw);
     a.flags = flags;
-    Grids g = grids_for(ctx, wg, mpw, 0, 0, 0, true);
-    if (flags & LF_SEG1) g.a = b->max_events;           // a replay has at most this many events
+    const Grids g = grids_for(ctx, wg, mpw, 0, 0, 0, true);
     hipStream_t cs = b->cap_stream;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
@@ -670,12 +666,11 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     hipError_t e = hipSuccess;
     u64 digis = 0, items = 0;
     const u32 dcap = cluster_capacity(wg, mpw);
-    u32 lflags = LF_NO_BIG | LF_SEG1;           // unless an event rules them out
+    u32 lflags = LF_NO_BIG;                     // unless an event may hold a big module
     for (u32 i = 0; i < k && e == hipSuccess; ++i) {
         pxcl_event* ev = evs[i];
         b->evs[i] = ev;
-        if (!ins[i].max_module_digis || ins[i].max_module_digis > dcap) lflags &= ~LF_NO_BIG;
-        if (!segment1_fits(ctx->n_modules, ins[i].n)) lflags &= ~LF_SEG1;
+        if (!ins[i].max_module_digis || ins[i].max_module_digis > dcap) lflags = 0;
         ev->epoch = next_epoch();
         ev->n = ins[i].n;
         ev->cb = nullptr;
@@ -697,8 +692,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
             LaunchArgs a = batch_args(b, wg, mpw);
             a.flags = lflags;
             e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
-            Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), k, false);
-            if (lflags & LF_SEG1) g.a = k;
+            const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), k, false);
             if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? b->tev : nullptr);
         }
     }

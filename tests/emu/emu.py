@@ -34,17 +34,16 @@ def build(force: bool = False, sanitizer: str = "address") -> str:
 
 
 def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, grids=(2, 2, 2, 2), caps=None,
-        header: bool = False, sanitizer: str = "address", no_big: bool = False, seg1: bool = False):
+        header: bool = False, sanitizer: str = "address", no_big: bool = False):
     """Cluster `events` (list of dicts of uint16 arrays) as one launch; returns a list
     of result dicts like the oracle's (status from the error bits).  With `header` the
     events are passed through a batch header even when there is only one; with
-    `no_big` the big-module kernel is not run (the launch of a small size hint); with
-    `seg1` segmentation runs one workgroup per event (grid_a workgroups)."""
+    `no_big` the big-module kernel is not run (the launch of a small size hint)."""
     exe = build(sanitizer=sanitizer)
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
         with open(fin, "wb") as f:
-            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), int(no_big) | (2 if seg1 else 0)],
+            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), int(no_big)],
                      dtype=np.uint32).tofile(f)
             for i, ev in enumerate(events):
                 n = ev["module"].size

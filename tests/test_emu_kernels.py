@@ -116,30 +116,3 @@ def test_size_hint_skips_big_kernel(emulator):
     assert all(r["err_bits"] & 16 for i, r in enumerate(res) if i != 1)
     assert all(r["n_clusters"] <= e["module"].size for r, e in zip(res, evs))
 
-
-@pytest.mark.parametrize("wg,mpw", [(64, 1), (256, 2)])
-def test_one_workgroup_segmentation(emulator, wg, mpw):
-    """Segmentation with one workgroup per event (module starts found in LDS): the
-    mixed events with fewer workgroups than events, one event alone through a header,
-    and an event whose length is not a multiple of the vector width."""
-    evs = _mixed_events()
-    _check(emulator, evs, 6, wg=wg, mpw=mpw, grids=(3, 2, 3, 2), seg1=True)
-    ev = synth.plain_event(4, n_modules=6)
-    odd = {k: (v[:-3] if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
-    _check(emulator, [odd], 6, wg=wg, mpw=mpw, grids=(1, 2, 3, 2), header=True, seg1=True)
-
-
-def test_one_workgroup_segmentation_errors_and_races(emulator):
-    """Error detection (module range, order) and no unsynchronised shared access in the
-    one-workgroup segmentation."""
-    ev = synth.plain_event(5, n_modules=6)
-    bad_order = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
-    bad_order["module"][10] = 5
-    bad_range = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
-    bad_range["module"][-1] = 6
-    res = emu.run([bad_order, bad_range, ev], 6, grids=(2, 2, 3, 2), seg1=True)
-    assert [r["status"] for r in res[:2]] == [emulator.cluster_event(bad_order, 2000)["status"],
-                                             emulator.cluster_event(bad_range, 2000)["status"]]
-    assert res[0]["status"] == -7 and res[1]["status"] == -6
-    compare(res[2], emulator.cluster_event(ev, 2000), "valid event beside errors")
-    _check(emulator, [ev], 6, grids=(1, 2, 3, 2), seg1=True, sanitizer="thread")
