@@ -48,6 +48,9 @@ def _load():
         lib.pxo_cluster_event.restype = ctypes.c_int
         lib.pxo_cluster_event.argtypes = [u16p, u16p, u16p, u16p, ctypes.c_uint32, ctypes.c_uint32,
                                           ctypes.c_uint32, i32p, i32p, i32p, i32p, u32p, u32p]
+        f32p = ctypes.POINTER(ctypes.c_float)
+        lib.pxo_cluster_event_hits.restype = ctypes.c_int
+        lib.pxo_cluster_event_hits.argtypes = lib.pxo_cluster_event.argtypes + [f32p, f32p]
         _lib = lib
     return _lib
 
@@ -86,6 +89,35 @@ def cluster_event(ev, charge_cut: int = 2000):
     return {"status": int(st), "err_bits": int(bits[0]), "n_clusters": k,
             "id": cid[:k].copy(), "charge": chg[:k].copy(), "size": siz[:k].copy(),
             "digi": digi[:n].copy()}
+
+
+def hits(ev, charge_cut: int = 2000):
+    """The clustering result plus, per kept cluster, its hit: the charge-weighted
+    centroid x = sum(adc*col)/charge, y = sum(adc*row)/charge (exact 64-bit sums,
+    divided in double, rounded to float32; NaN for zero charge)."""
+    lib = _load()
+    mod = np.ascontiguousarray(ev["module"], dtype=np.uint16)
+    row = np.ascontiguousarray(ev["row"], dtype=np.uint16)
+    col = np.ascontiguousarray(ev["col"], dtype=np.uint16)
+    adc = np.ascontiguousarray(ev["adc"], dtype=np.uint16)
+    n = mod.size
+    cap = max(n, 1)
+    digi = np.full(cap, -1, dtype=np.int32)
+    cid, chg, siz = (np.zeros(cap, dtype=np.int32) for _ in range(3))
+    hx, hy = np.zeros(cap, dtype=np.float32), np.zeros(cap, dtype=np.float32)
+    ncl = np.zeros(1, dtype=np.uint32)
+    bits = np.zeros(1, dtype=np.uint32)
+    st = lib.pxo_cluster_event_hits(_p(mod, ctypes.c_uint16), _p(row, ctypes.c_uint16),
+                                    _p(col, ctypes.c_uint16), _p(adc, ctypes.c_uint16),
+                                    n, int(ev["n_modules"]), int(charge_cut) & 0xFFFFFFFF,
+                                    _p(digi, ctypes.c_int32), _p(cid, ctypes.c_int32),
+                                    _p(chg, ctypes.c_int32), _p(siz, ctypes.c_int32),
+                                    _p(ncl, ctypes.c_uint32), _p(bits, ctypes.c_uint32),
+                                    _p(hx, ctypes.c_float), _p(hy, ctypes.c_float))
+    k = int(ncl[0])
+    return {"status": int(st), "err_bits": int(bits[0]), "n_clusters": k,
+            "id": cid[:k].copy(), "charge": chg[:k].copy(), "size": siz[:k].copy(),
+            "digi": digi[:n].copy(), "x": hx[:k].copy(), "y": hy[:k].copy()}
 
 
 def components(ev):

@@ -21,6 +21,10 @@
  *   4. a cluster is kept iff charge >= charge_cut;
  *   5. outputs: kept clusters sorted by ascending id; per digi the id of its
  *      cluster if kept, else -1; the number of kept clusters.
+ *   6. hits (the product the figure derives from clusters): per kept cluster its
+ *      charge-weighted centroid in pixel units, x = sum(adc*col)/charge and
+ *      y = sum(adc*row)/charge, from exact 64-bit sums divided in double precision
+ *      and rounded to float; NaN for a cluster of zero charge.
  *
  * Components are found by breadth-first search over a dense 160x416 grid of digi
  * indices, one module at a time: slow, single-threaded and easy to check.
@@ -29,6 +33,7 @@
  *   out-of-range module/row/col -> -6, module ids decreasing -> -7,
  *   the same pixel fired twice  -> -5.  Outputs are unspecified on error.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -47,6 +52,8 @@ typedef struct {
     int64_t id;
     uint32_t charge;
     uint32_t size;
+    uint64_t sum_col;   /* sum of adc*col */
+    uint64_t sum_row;   /* sum of adc*row */
 } o_cluster;
 
 static int cmp_cluster(const void* a, const void* b)
@@ -57,11 +64,12 @@ static int cmp_cluster(const void* a, const void* b)
 
 /* Returns 0 on success or a negative error code; err_bits gets 1 (range), 2 (order),
  * 4 (duplicate pixel) for every class detected. */
-int pxo_cluster_event(const uint16_t* module, const uint16_t* row, const uint16_t* col,
-                      const uint16_t* adc, uint32_t n, uint32_t n_modules,
-                      uint32_t charge_cut, int32_t* digi_cluster, int32_t* cl_id,
-                      int32_t* cl_charge, int32_t* cl_size, uint32_t* n_clusters,
-                      uint32_t* err_bits)
+/* As pxo_cluster_event, and per kept cluster its hit (hit_x, hit_y may be NULL). */
+int pxo_cluster_event_hits(const uint16_t* module, const uint16_t* row, const uint16_t* col,
+                           const uint16_t* adc, uint32_t n, uint32_t n_modules,
+                           uint32_t charge_cut, int32_t* digi_cluster, int32_t* cl_id,
+                           int32_t* cl_charge, int32_t* cl_size, uint32_t* n_clusters,
+                           uint32_t* err_bits, float* hit_x, float* hit_y)
 {
     uint32_t bits = 0;
     *n_clusters = 0;
@@ -114,12 +122,15 @@ int pxo_cluster_event(const uint16_t* module, const uint16_t* row, const uint16_
             comp[i] = (int32_t)n_comp;
             int64_t min_lin = INT64_MAX;
             uint32_t charge = 0, size = 0;
+            uint64_t sum_col = 0, sum_row = 0;
             while (head < tail) {
                 uint32_t d = queue[head++];
                 int64_t lin = (int64_t)module[d] * (O_ROWS * O_COLS) + (int64_t)col[d] * O_ROWS + row[d];
                 if (lin < min_lin) min_lin = lin;
                 charge += adc[d];
                 size += 1;
+                sum_col += (uint64_t)adc[d] * col[d];
+                sum_row += (uint64_t)adc[d] * row[d];
                 for (int dr = -1; dr <= 1; ++dr) {
                     for (int dc = -1; dc <= 1; ++dc) {
                         int r2 = (int)row[d] + dr, c2 = (int)col[d] + dc;
@@ -136,6 +147,8 @@ int pxo_cluster_event(const uint16_t* module, const uint16_t* row, const uint16_
             cls[n_comp].id = min_lin;
             cls[n_comp].charge = charge;
             cls[n_comp].size = size;
+            cls[n_comp].sum_col = sum_col;
+            cls[n_comp].sum_row = sum_row;
             ++n_comp;
         }
         /* reset the grid cells this module used */
@@ -161,12 +174,24 @@ int pxo_cluster_event(const uint16_t* module, const uint16_t* row, const uint16_
         if (cl_id) cl_id[k] = (int32_t)cls[j].id;
         if (cl_charge) cl_charge[k] = (int32_t)cls[j].charge;
         if (cl_size) cl_size[k] = (int32_t)cls[j].size;
+        if (hit_x) hit_x[k] = cls[j].charge ? (float)((double)cls[j].sum_col / (double)cls[j].charge) : NAN;
+        if (hit_y) hit_y[k] = cls[j].charge ? (float)((double)cls[j].sum_row / (double)cls[j].charge) : NAN;
         ++k;
     }
     *n_clusters = k;
     if (err_bits) *err_bits = 0;
     free(grid); free(comp); free(queue); free(cls);
     return O_OK;
+}
+
+int pxo_cluster_event(const uint16_t* module, const uint16_t* row, const uint16_t* col,
+                      const uint16_t* adc, uint32_t n, uint32_t n_modules,
+                      uint32_t charge_cut, int32_t* digi_cluster, int32_t* cl_id,
+                      int32_t* cl_charge, int32_t* cl_size, uint32_t* n_clusters,
+                      uint32_t* err_bits)
+{
+    return pxo_cluster_event_hits(module, row, col, adc, n, n_modules, charge_cut, digi_cluster, cl_id,
+                                  cl_charge, cl_size, n_clusters, err_bits, NULL, NULL);
 }
 
 /* All clusters before the cut, sorted by id (for invariant tests): returns the count. */

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import test_oracle_hits as hpins
 from tests import test_oracle_pins as pins
 
 MUTANTS = {
@@ -20,6 +21,11 @@ MUTANTS = {
     "modules_not_separated": ("for (uint32_t i = s; i < e; ++i) grid[row[i] * O_COLS + col[i]] = -1;", ""),
     "descending_order": ("return (x > y) - (x < y);", "return (x < y) - (x > y);"),
     "max_instead_of_min_id": ("if (lin < min_lin) min_lin = lin;", "if (min_lin == INT64_MAX || lin > min_lin) min_lin = lin;"),
+    # hits
+    "unweighted_hit": ("sum_col += (uint64_t)adc[d] * col[d];", "sum_col += (uint64_t)col[d] * 3000u;"),
+    "hit_axes_swapped": ("sum_row += (uint64_t)adc[d] * row[d];", "sum_row += (uint64_t)adc[d] * col[d];"),
+    "hit_in_float": ("(float)((double)cls[j].sum_col / (double)cls[j].charge)",
+                     "((float)cls[j].sum_col / (float)cls[j].charge)"),
 }
 
 
@@ -41,6 +47,14 @@ class _Fake:
     def components(self, ev):
         return self.cluster_event(ev, 0)
 
+    def hits(self, ev, charge_cut=2000):
+        saved = oracle._lib
+        oracle._lib = self._lib
+        try:
+            return oracle.hits(ev, charge_cut)
+        finally:
+            oracle._lib = saved
+
 
 def _build_mutant(tmp_path, name, old, new):
     src = open(oracle._SRC).read()
@@ -54,6 +68,8 @@ def _build_mutant(tmp_path, name, old, new):
     lib.pxo_cluster_event.restype = ctypes.c_int
     lib.pxo_cluster_event.argtypes = [u16p, u16p, u16p, u16p, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_uint32, i32p, i32p, i32p, i32p, u32p, u32p]
+    lib.pxo_cluster_event_hits.restype = ctypes.c_int
+    lib.pxo_cluster_event_hits.argtypes = lib.pxo_cluster_event.argtypes + [ctypes.POINTER(ctypes.c_float)] * 2
     return lib
 
 
@@ -65,6 +81,10 @@ def _caught(fake):
         lambda: pins.test_closed_form_no_wraparound(fake),
         lambda: pins.test_closed_form_column_track(fake, 207),
         lambda: pins.test_random_small_vs_pairwise(fake),
+        lambda: hpins.test_two_pixels_weighted(fake),
+        lambda: hpins.test_against_scipy_label(fake, 0.05),
+        lambda: hpins.test_against_scipy_label(fake, 0.5),
+        lambda: hpins.test_large_clusters_exact(fake),          # sums above 2**24
     ]
     for chk in checks:
         try:
