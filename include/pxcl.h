@@ -202,6 +202,40 @@ typedef struct {
 } pxcl_flag;
 void pxcl_flag_cb(void* user, int32_t status);
 
+/* ---- hits: a consumer of an event's clusters ----------------------------------- */
+/* The paper's Figure 1 (Sec. 3) derives hits from clusters.  Here a hit is the
+ * charge-weighted centroid of a kept cluster's pixels, in pixel units:
+ * x = sum(adc*col) / charge, y = sum(adc*row) / charge, from exact 64-bit sums
+ * divided in double precision and rounded to float (NaN for zero charge), one per
+ * kept cluster in the clusters' order.
+ * pxcl_hits_enqueue queues the hits of the event's last acquire on `stream`
+ * (hipStream_t) as a consumer of its clusters in the way Sec. 4.2 describes: when
+ * `stream` is not the stream the event's work went to and that work may still be
+ * running, `stream` first waits for the event's completion event; on the same
+ * stream the order of the stream suffices.  The event must have been acquired and
+ * its input digis must stay valid until `cb` fires (exactly once, with the event's
+ * status).  PXCL_E_BUSY if hits of the event are in flight; an acquire of the event
+ * returns PXCL_E_BUSY while they are.  Non-blocking. */
+typedef struct {
+    int32_t status;            /* the event's status */
+    uint32_t n_hits;           /* = the event's kept clusters */
+    const float* x;            /* [n_hits] column centroid (device) */
+    const float* y;            /* [n_hits] row centroid (device) */
+    void* stream;              /* hipStream_t the hits were queued on */
+    void* done_event;          /* hipEvent_t recorded after them */
+    int32_t device;
+} pxcl_hits;
+int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, void* user);
+/* PXCL_OK once the hits are complete, PXCL_E_NOT_READY while in flight,
+ * PXCL_E_INVAL if none were queued.  Non-blocking. */
+int pxcl_hits_query(const pxcl_event* ev);
+/* Non-blocking.  PXCL_E_NOT_READY before completion; otherwise fills *out (device
+ * pointers into the event's workspace, valid until its next acquire or unbind) and
+ * returns the status. */
+int pxcl_hits_produce(pxcl_event* ev, pxcl_hits* out);
+/* Blocking wait for the hits (tests and simple callers), like pxcl_wait. */
+int pxcl_hits_wait(pxcl_event* ev);
+
 /* ---- batches: many events in one launch --------------------------------------- */
 size_t pxcl_batch_workspace_bytes(const pxcl_ctx* ctx, uint32_t max_events);
 size_t pxcl_batch_pinned_bytes(const pxcl_ctx* ctx, uint32_t max_events);

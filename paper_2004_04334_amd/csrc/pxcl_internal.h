@@ -101,6 +101,8 @@ struct EvLayout {
     size_t seg;                              // per module: launch tag << 32 | first digi
     size_t item_start, item_kept;            // modules present (work items), in module order
     size_t small, big;                       // work lists of the two clustering kernels (ItemEntry)
+    size_t item_off;                         // per item: its first cluster in the outputs
+    size_t hit_x, hit_y;                     // hits (per kept cluster), when asked for
     size_t total;
 };
 
@@ -125,6 +127,9 @@ PXCL_HD inline EvLayout ev_layout(u32 N, u32 M) {
     L.item_kept = o;  o = al256(o + 4 * m);
     L.small = o;      o = al256(o + 16 * m);
     L.big = o;        o = al256(o + 16 * m);
+    L.item_off = o;   o = al256(o + 4 * m);
+    L.hit_x = o;      o = al256(o + 4 * n);
+    L.hit_y = o;      o = al256(o + 4 * n);
     L.total = o;
     return L;
 }

@@ -1196,9 +1196,11 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         int32_t* oid = ws_ptr<int32_t>(E, L.id);
         int32_t* och = ws_ptr<int32_t>(E, L.charge);
         int32_t* osz = ws_ptr<int32_t>(E, L.size);
+        u32* item_off = ws_ptr<u32>(E, L.item_off);
         for (u32 x = i0 + wv; x < i1; x += C_WG / 64) {
             const u32 off = s_off[x - i0], cnt = s_off[x - i0 + 1] - off;
             const u32 src = s_src[x - i0];
+            if (lane == 0) item_off[x] = off;
             if (cnt > E.n || off > E.n - cnt || src > E.n - cnt) continue;   // inconsistent (flagged)
             for (u32 j0 = 0; j0 < cnt; j0 += 64 * CP_UNR) {
                 int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
@@ -1234,6 +1236,72 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             st_sys(&hs[HS_EPOCH], E.epoch);
         }
         lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// hits: per kept cluster the charge-weighted centroid of its pixels, x = sum(adc*col)
+// / charge and y = sum(adc*row) / charge, from exact 64-bit sums, divided in double
+// and rounded to float (NaN for zero charge).  One workgroup per module with kept
+// clusters: the module's cluster ids (ascending) go to LDS, H_CAP at a time; every
+// digi of the module whose id falls in the held range finds its cluster by binary
+// search and adds its weighted coordinates with LDS atomics.
+// ---------------------------------------------------------------------------
+constexpr u32 H_WG = 256, H_CAP = 2048;
+
+__global__ __launch_bounds__(H_WG) void k_hits(LaunchArgs a) {
+    __shared__ u32 s_pref[MAXB + 1];
+    __shared__ u32 s_wsum[H_WG / 64];
+    __shared__ int32_t s_id[H_CAP];
+    __shared__ u64 s_sx[H_CAP], s_sy[H_CAP];
+    const u32 tid = threadIdx.x;
+    const u32 k = num_events(a);
+    const u32 total = event_prefix<H_WG>(a, k, s_pref, s_wsum, CTL_ITEMS, 1, 0);
+    for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
+        const u32 e = find_slot(s_pref, k, t);
+        const u32 it = t - s_pref[e];
+        const EventDesc E = get_event(a, e);
+        const EvLayout L = ev_layout(E.cap, a.n_modules);
+        const u32 st = ws_ptr<const u32>(E, L.item_start)[it];
+        const u32 nd = ws_ptr<const u32>(E, L.item_start)[it + 1] - st;
+        const u32 cnt = ws_ptr<const u32>(E, L.item_kept)[it];
+        const u32 off = ws_ptr<const u32>(E, L.item_off)[it];
+        if (cnt == 0 || cnt > E.n || off > E.n - cnt || st > E.n || nd > E.n - st) continue;
+        const int32_t* ids = ws_ptr<const int32_t>(E, L.id) + off;
+        const int32_t* chg = ws_ptr<const int32_t>(E, L.charge) + off;
+        const int32_t* dcl = ws_ptr<const int32_t>(E, L.digi) + st;
+        float* hx = ws_ptr<float>(E, L.hit_x) + off;
+        float* hy = ws_ptr<float>(E, L.hit_y) + off;
+        for (u32 c0 = 0; c0 < cnt; c0 += H_CAP) {
+            const u32 len = min(H_CAP, cnt - c0);
+            for (u32 c = tid; c < len; c += H_WG) {
+                s_id[c] = ids[c0 + c];
+                s_sx[c] = 0ull;
+                s_sy[c] = 0ull;
+            }
+            lds_barrier();
+            const int32_t lo = s_id[0], hi = s_id[len - 1];
+            for (u32 j = tid; j < nd; j += H_WG) {
+                const int32_t id = dcl[j];
+                if (id < lo || id > hi) continue;          // cut (-1) or held by another chunk
+                u32 l = 0, h = len;
+                while (h - l > 1) {
+                    const u32 m = (l + h) >> 1;
+                    if (s_id[m] <= id) l = m; else h = m;
+                }
+                if (s_id[l] != id) continue;
+                const u64 w = E.adc[st + j];
+                atomicAdd(&s_sx[l], w * E.col[st + j]);
+                atomicAdd(&s_sy[l], w * E.row[st + j]);
+            }
+            lds_barrier();
+            for (u32 c = tid; c < len; c += H_WG) {
+                const u32 q = u32(chg[c0 + c]);
+                hx[c0 + c] = q ? float(double(s_sx[c]) / double(q)) : __int_as_float(0x7FC00000);
+                hy[c0 + c] = q ? float(double(s_sy[c]) / double(q)) : __int_as_float(0x7FC00000);
+            }
+            lds_barrier();
+        }
     }
 }
 
@@ -1290,6 +1358,11 @@ hipError_t launch_big(const LaunchArgs& a, u32 grid, hipStream_t s) {
 }
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(grid), dim3(C_WG), 0, s, a);
+    return hipGetLastError();
+}
+int occupancy_hits() { return occ(reinterpret_cast<const void*>(k_hits), H_WG); }
+hipError_t launch_hits(const LaunchArgs& a, u32 grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_hits, dim3(grid), dim3(H_WG), 0, s, a);
     return hipGetLastError();
 }
 

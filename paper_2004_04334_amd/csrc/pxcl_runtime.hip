@@ -32,6 +32,8 @@ hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_big(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
+int occupancy_hits();
+hipError_t launch_hits(const LaunchArgs& a, u32 grid, hipStream_t s);
 }  // namespace pxcl
 
 using namespace pxcl;
@@ -73,7 +75,7 @@ struct pxcl_ctx {
     u32 n_cu = 0;
     std::string arch;
     std::atomic<u32> wg{256}, mpw{1};
-    int occ_a = 1, occ_l = 1, occ_c = 1;
+    int occ_a = 1, occ_l = 1, occ_c = 1, occ_h = 1;
     std::atomic<int> bound{0};
     std::atomic<int> timing{0};
     std::mutex tmu;
@@ -102,6 +104,16 @@ struct pxcl_event {
     std::atomic<int> cb_pending{0};   // launches whose completion callback has not returned
     u32 launches = 0;                 // for sampling launches to time
     bool timed_big = false;           // the timed launch ran the big-module kernel
+    EventDesc desc{};                 // the event as the kernels saw it (for the hits)
+    // hits of the last acquired event
+    std::atomic<int> hstate{ST_IDLE};
+    std::atomic<int> hits_pending{0};
+    hipEvent_t hits_ev = nullptr;
+    hipStream_t hits_stream = nullptr;
+    pxcl_done_cb hits_cb = nullptr;
+    void* hits_user = nullptr;
+    int32_t hits_status = PXCL_OK;
+    u32 hits_n = 0;
 };
 
 struct pxcl_batch {
@@ -296,6 +308,7 @@ extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** ou
     c->occ_a = occupancy_segment();
     c->occ_l = occupancy_big();
     c->occ_c = occupancy_compact();
+    c->occ_h = occupancy_hits();
     hipSetDevice(prev);
     *out = c;
     return PXCL_OK;
@@ -375,12 +388,14 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     hipSetDevice(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipEventCreateWithFlags(&ev->done_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev->hits_ev, hipEventDisableTiming);
     for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev->tev[i]);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.seg, 0, L.item_start - L.seg, s);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (ev->done_ev) hipEventDestroy(ev->done_ev);
+        if (ev->hits_ev) hipEventDestroy(ev->hits_ev);
         for (int i = 0; i < 5; ++i) if (ev->tev[i]) hipEventDestroy(ev->tev[i]);
         delete ev;
         return PXCL_E_HIP;
@@ -393,11 +408,15 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
 extern "C" int pxcl_event_unbind(pxcl_event* ev) {
     if (!ev) return PXCL_E_INVAL;
     if (ev->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
-    if (ev->cb_pending.load(std::memory_order_acquire) > 0) {     // its callback is still running
-        if (t_in_callback) return PXCL_E_BUSY;
-        while (ev->cb_pending.load(std::memory_order_acquire) > 0) std::this_thread::yield();
+    if (ev->hstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+    if (ev->cb_pending.load(std::memory_order_acquire) > 0 || ev->hits_pending.load(std::memory_order_acquire) > 0) {
+        if (t_in_callback) return PXCL_E_BUSY;                    // a callback of it is still running
+        while (ev->cb_pending.load(std::memory_order_acquire) > 0 ||
+               ev->hits_pending.load(std::memory_order_acquire) > 0)
+            std::this_thread::yield();
     }
     hipEventDestroy(ev->done_ev);
+    hipEventDestroy(ev->hits_ev);
     for (int i = 0; i < 5; ++i) hipEventDestroy(ev->tev[i]);
     ev->ctx->bound.fetch_sub(1);
     delete ev;
@@ -409,7 +428,9 @@ extern "C" uint32_t pxcl_event_capacity(const pxcl_event* ev) { return ev ? ev->
 extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, pxcl_done_cb cb, void* user) {
     if (!ev || !digis_ok(in)) return PXCL_E_INVAL;
     if (in->n > ev->cap) return PXCL_E_CAPACITY;
+    if (ev->hstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;   // hits read the slot
     if (!claim(ev->state)) return PXCL_E_BUSY;
+    ev->hstate.store(ST_IDLE, std::memory_order_release);
     pxcl_ctx* ctx = ev->ctx;
     hipStream_t s = static_cast<hipStream_t>(stream);
     ev->epoch = next_epoch();
@@ -435,6 +456,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.dcap = cluster_capacity(wg, mpw);
     if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
     hipError_t e = make_desc(ev, in, s, &a.single);
+    ev->desc = a.single;
     const u64 items = std::min<u64>(in->n, (u64)ctx->n_modules);
     const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, false);
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
@@ -523,6 +545,114 @@ extern "C" void pxcl_flag_cb(void* user, int32_t status) {
     if (!f) return;
     f->status = status;
     __atomic_fetch_add(&f->fired, 1u, __ATOMIC_RELEASE);
+}
+
+// ---------------------------------------------------------------------------
+// hits: a consumer of an event's clusters
+// ---------------------------------------------------------------------------
+namespace {
+void hits_done_hostfn(void* p) {
+    pxcl_event* ev = static_cast<pxcl_event*>(p);
+    // the event's work completed before the hits (stream order or the wait on its
+    // completion event), so its status block is final, whether or not the event's
+    // own callback has run yet
+    volatile u32* hs = ev->hs;
+    const u32 tag = __atomic_load_n(&ev->hs[HS_EPOCH], __ATOMIC_ACQUIRE);
+    u32 bits = hs[HS_ERR];
+    if (tag != ev->epoch) bits |= EB_INTERNAL;
+    const u32 ncl = hs[HS_NCL];
+    ev->hits_n = ncl < ev->n ? ncl : ev->n;
+    ev->hits_status = status_from_bits(bits);
+    pxcl_done_cb cb = ev->hits_cb;
+    void* user = ev->hits_user;
+    const int32_t st = ev->hits_status;
+    ev->hstate.store(ST_DONE, std::memory_order_release);
+    if (cb) {
+        ++t_in_callback;
+        cb(user, st);
+        --t_in_callback;
+    }
+    ev->hits_pending.fetch_sub(1, std::memory_order_acq_rel);
+}
+}  // namespace
+
+extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, void* user) {
+    if (!ev) return PXCL_E_INVAL;
+    const int st = ev->state.load(std::memory_order_acquire);
+    if (st == ST_IDLE) return PXCL_E_INVAL;                     // no event acquired
+    if (!claim(ev->hstate)) return PXCL_E_BUSY;
+    pxcl_ctx* ctx = ev->ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    hipError_t e = hipSuccess;
+    // a consumer on another stream waits for the clusters if they may not be ready
+    if (st == ST_INFLIGHT && s != ev->stream)
+        e = hipStreamWaitEvent(s, ev->batch ? ev->batch->done_ev : ev->done_ev, 0);
+    ev->hits_cb = cb;
+    ev->hits_user = user;
+    ev->hits_stream = s;
+    ev->hits_status = PXCL_OK;
+    ev->hits_n = 0;
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.single = ev->desc;
+    a.n_modules = ctx->n_modules;
+    a.charge_cut = ctx->charge_cut;
+    const u64 items = std::min<u64>(std::max<u32>(ev->n, 1u), (u64)ctx->n_modules);
+    const u32 grid = u32(std::max<u64>(1, std::min<u64>((u64)ctx->n_cu * ctx->occ_h, items)));
+    if (e == hipSuccess) e = launch_hits(a, grid, s);
+    if (e == hipSuccess) e = hipEventRecord(ev->hits_ev, s);
+    if (e == hipSuccess) {
+        ev->hits_pending.fetch_add(1, std::memory_order_acq_rel);
+        e = hipLaunchHostFunc(s, hits_done_hostfn, ev);
+        if (e != hipSuccess) ev->hits_pending.fetch_sub(1, std::memory_order_acq_rel);
+    }
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ev->hstate.store(ST_IDLE, std::memory_order_release);
+        return PXCL_E_HIP;
+    }
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_hits_query(const pxcl_event* ev) {
+    if (!ev) return PXCL_E_INVAL;
+    const int st = ev->hstate.load(std::memory_order_acquire);
+    if (st == ST_DONE) return PXCL_OK;
+    if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
+    return PXCL_E_INVAL;
+}
+
+extern "C" int pxcl_hits_produce(pxcl_event* ev, pxcl_hits* out) {
+    if (!ev || !out) return PXCL_E_INVAL;
+    const int st = ev->hstate.load(std::memory_order_acquire);
+    if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
+    if (st != ST_DONE) return PXCL_E_INVAL;
+    const EvLayout L = ev_layout(ev->cap, ev->ctx->n_modules);
+    out->status = ev->hits_status;
+    out->n_hits = ev->hits_status == PXCL_OK ? ev->hits_n : 0u;
+    out->x = reinterpret_cast<const float*>(ev->ws + L.hit_x);
+    out->y = reinterpret_cast<const float*>(ev->ws + L.hit_y);
+    out->stream = ev->hits_stream;
+    out->done_event = ev->hits_ev;
+    out->device = ev->ctx->device;
+    return ev->hits_status;
+}
+
+extern "C" int pxcl_hits_wait(pxcl_event* ev) {
+    if (!ev) return PXCL_E_INVAL;
+    const int st = ev->hstate.load(std::memory_order_acquire);
+    if (st == ST_IDLE) return PXCL_E_INVAL;
+    if (st == ST_INFLIGHT) {
+        if (hipEventSynchronize(ev->hits_ev) != hipSuccess) return PXCL_E_HIP;
+        while (ev->hstate.load(std::memory_order_acquire) != ST_DONE) std::this_thread::yield();
+    }
+    if (!t_in_callback)
+        while (ev->hits_pending.load(std::memory_order_acquire) > 0) std::this_thread::yield();
+    return PXCL_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -634,6 +764,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     for (u32 i = 0; i < k; ++i) {
         if (!evs[i] || evs[i]->ctx != b->ctx || !digis_ok(&ins[i])) return PXCL_E_INVAL;
         if (ins[i].n > evs[i]->cap) return PXCL_E_CAPACITY;
+        if (evs[i]->hstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
         for (u32 j = 0; j < i; ++j)
             if (evs[j] == evs[i]) return PXCL_E_INVAL;
     }
@@ -680,7 +811,9 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         ev->timed = false;
         ev->status = PXCL_OK;
         __atomic_store_n(&ev->hs[HS_EPOCH], 0u, __ATOMIC_RELEASE);
+        ev->hstate.store(ST_IDLE, std::memory_order_release);
         e = make_desc(ev, &ins[i], s, &hd[i]);
+        ev->desc = hd[i];
         digis += ins[i].n;
         items += std::min<u64>(ins[i].n, (u64)ctx->n_modules);
     }

@@ -46,6 +46,12 @@ class _Digis(ctypes.Structure):
                 ("max_module_digis", ctypes.c_uint32)]
 
 
+class _Hits(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_hits", ctypes.c_uint32), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("stream", ctypes.c_void_p), ("done_event", ctypes.c_void_p),
+                ("device", ctypes.c_int32)]
+
+
 class _Clusters(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("err_bits", ctypes.c_uint32), ("n_clusters", ctypes.c_uint32),
                 ("n_digis", ctypes.c_uint32), ("id", ctypes.c_void_p), ("charge", ctypes.c_void_p),
@@ -102,6 +108,10 @@ _SIGS = {
     "pxcl_produce": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Clusters)]),
     "pxcl_wait": (ctypes.c_int, [ctypes.c_void_p]),
     "pxcl_flag_cb": (None, [ctypes.c_void_p, ctypes.c_int32]),
+    "pxcl_hits_enqueue": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pxcl_hits_query": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_hits_produce": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Hits)]),
+    "pxcl_hits_wait": (ctypes.c_int, [ctypes.c_void_p]),
     "pxcl_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
     "pxcl_batch_pinned_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
     "pxcl_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -342,6 +352,52 @@ def produce(event: Event) -> ClusterResult:
     return ClusterResult(st, int(c.err_bits), int(c.n_clusters), event._view(c.id, c.n_clusters),
                          event._view(c.charge, c.n_clusters), event._view(c.size, c.n_clusters),
                          event._view(c.digi_cluster, c.n_digis), c.stream or 0, c.done_event or 0)
+
+
+@dataclass
+class HitsResult:
+    status: int
+    n_hits: int
+    x: torch.Tensor      # float32 views into the event's workspace
+    y: torch.Tensor
+    stream: int
+    done_event: int
+
+    def numpy(self):
+        return {"status": self.status, "n_hits": self.n_hits, "x": self.x.cpu().numpy(), "y": self.y.cpu().numpy()}
+
+
+def hits_enqueue(event: Event, stream=None, done_cb: Optional[Callable[[int], None]] = None,
+                 flag: Optional[Flag] = None) -> None:
+    """Queue the hits of the event's last acquire on ``stream`` (a consumer of its
+    clusters; another stream waits for the event's completion event)."""
+    cb_ptr, user = None, None
+    if flag is not None:
+        cb_ptr, user = flag_cb_ptr(), ctypes.addressof(flag)
+    elif done_cb is not None:
+        c = DONE_CB(lambda _u, st: done_cb(int(st)))
+        event._hcb = c
+        cb_ptr = ctypes.cast(c, ctypes.c_void_p).value
+    event._hkeep = flag
+    _check(lib().pxcl_hits_enqueue(event.handle, _stream_ptr(stream), cb_ptr, user), "hits_enqueue")
+
+
+def hits_query(event: Event) -> int:
+    return int(lib().pxcl_hits_query(event.handle))
+
+
+def hits_wait(event: Event) -> None:
+    _check(lib().pxcl_hits_wait(event.handle), "hits_wait")
+
+
+def hits_produce(event: Event) -> HitsResult:
+    h = _Hits()
+    st = int(lib().pxcl_hits_produce(event.handle, ctypes.byref(h)))
+    if st in (E_NOT_READY, E_INVAL):
+        raise PxclError(st, "hits_produce")
+    n = int(h.n_hits)
+    return HitsResult(st, n, event._view(h.x, n).view(torch.float32), event._view(h.y, n).view(torch.float32),
+                      h.stream or 0, h.done_event or 0)
 
 
 class Batch:

@@ -34,16 +34,17 @@ def build(force: bool = False, sanitizer: str = "address") -> str:
 
 
 def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, grids=(2, 2, 2, 2), caps=None,
-        header: bool = False, sanitizer: str = "address", no_big: bool = False):
+        header: bool = False, sanitizer: str = "address", no_big: bool = False, hits: bool = False):
     """Cluster `events` (list of dicts of uint16 arrays) as one launch; returns a list
     of result dicts like the oracle's (status from the error bits).  With `header` the
     events are passed through a batch header even when there is only one; with
-    `no_big` the big-module kernel is not run (the launch of a small size hint)."""
+    `no_big` the big-module kernel is not run (the launch of a small size hint); with
+    `hits` the hits kernel runs after the launch and the results carry "x" and "y"."""
     exe = build(sanitizer=sanitizer)
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
         with open(fin, "wb") as f:
-            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), int(no_big)],
+            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), int(no_big), int(hits)],
                      dtype=np.uint32).tofile(f)
             for i, ev in enumerate(events):
                 n = ev["module"].size
@@ -67,6 +68,10 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
         cid = raw[p:p + ncl]; p += ncl
         chg = raw[p:p + ncl]; p += ncl
         siz = raw[p:p + ncl]; p += ncl
+        hx = hy = None
+        if hits:
+            hx = raw[p:p + ncl].view(np.float32); p += ncl
+            hy = raw[p:p + ncl].view(np.float32); p += ncl
         st = 0
         if err & 0x80000000:
             st = -10
@@ -80,6 +85,9 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
             st = -5
         elif err & 8:
             st = -10
-        out.append({"status": st, "err_bits": err, "n_clusters": ncl, "digi": digi.copy(), "id": cid.copy(),
-                    "charge": chg.copy(), "size": siz.copy()})
+        r = {"status": st, "err_bits": err, "n_clusters": ncl, "digi": digi.copy(), "id": cid.copy(),
+             "charge": chg.copy(), "size": siz.copy()}
+        if hits:
+            r["x"], r["y"] = hx.copy(), hy.copy()
+        out.append(r)
     return out

@@ -82,6 +82,11 @@ inline void __builtin_amdgcn_fence(int, const char*, const char* = nullptr) {
 }
 inline void __builtin_amdgcn_s_waitcnt(int) {}
 inline int __popc(uint32_t x) { return __builtin_popcount(x); }
+inline float __int_as_float(int x) {
+    float f;
+    std::memcpy(&f, &x, sizeof(f));
+    return f;
+}
 inline int __ffs(uint32_t x) { return __builtin_ffs(int(x)); }
 inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
 template <typename T> inline T min(T a, T b) { return a < b ? a : b; }

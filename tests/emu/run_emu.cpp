@@ -4,9 +4,11 @@
 //
 // input:  u32 k, n_modules, cut, wg, mpw, grid_a, grid_b, grid_s, grid_c, header
 //         (1: the events go through a batch header even when k == 1), launch flags
-//         (LF_NO_BIG: the big-module kernel is not run);
+//         (LF_NO_BIG: the big-module kernel is not run), hits (1: run the hits kernel
+//         after the launch);
 //         per event: u32 n, u32 cap, u16 module[n], row[n], col[n], adc[n]
 // output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
+//         (with hits: then f32 x[nc], y[nc])
 #include "../../paper_2004_04334_amd/csrc/pxcl_kernels.hip"
 
 #include <algorithm>
@@ -23,7 +25,7 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: run_emu in out\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) return 2;
-    u32 h[11];
+    u32 h[12];
     rd(f, h, sizeof(h));
     const u32 k = h[0], M = h[1];
     std::vector<EventDesc> evs(k);
@@ -82,6 +84,10 @@ int main(int argc, char** argv) {
         fprintf(stderr, "launch failed\n");
         return 3;
     }
+    if (h[11] && launch_hits(a, h[8], nullptr)) {
+        fprintf(stderr, "hits launch failed\n");
+        return 3;
+    }
     FILE* o = fopen(argv[2], "wb");
     for (u32 e = 0; e < k; ++e) {
         const EvLayout L = ev_layout(evs[e].cap, M);
@@ -93,6 +99,10 @@ int main(int argc, char** argv) {
         fwrite(ws[e] + L.id, 4, ncl, o);
         fwrite(ws[e] + L.charge, 4, ncl, o);
         fwrite(ws[e] + L.size, 4, ncl, o);
+        if (h[11]) {
+            fwrite(ws[e] + L.hit_x, 4, ncl, o);
+            fwrite(ws[e] + L.hit_y, 4, ncl, o);
+        }
     }
     fclose(o);
     for (u32 e = 0; e < k; ++e) { free(ws[e]); free(hs[e]); }

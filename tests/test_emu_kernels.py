@@ -116,3 +116,27 @@ def test_size_hint_skips_big_kernel(emulator):
     assert all(r["err_bits"] & 16 for i, r in enumerate(res) if i != 1)
     assert all(r["n_clusters"] <= e["module"].size for r, e in zip(res, evs))
 
+
+
+@pytest.mark.parametrize("sanitizer", ["address", "thread"])
+def test_hits_kernel(emulator, sanitizer):
+    """The hits kernel after a launch of several events (one with a module above the
+    small kernel's capacity), bit-exact against the oracle's hits."""
+    evs = _mixed_events()
+    res = emu.run(evs, 6, wg=64, mpw=1, grids=(2, 2, 3, 2), hits=True, sanitizer=sanitizer)
+    for i, (r, e) in enumerate(zip(res, evs)):
+        ref = emulator.hits(e, 2000)
+        compare(r, ref, f"event {i}")
+        assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"]), f"hits of event {i}"
+
+
+def test_hits_kernel_many_clusters_per_module(emulator):
+    """A module with more kept clusters than the hits kernel holds at once (2,048):
+    the even lattice, 16,640 singletons of which about half pass the cut."""
+    lr, lc = np.meshgrid(np.arange(0, 160, 2), np.arange(0, 416, 2), indexing="ij")
+    ev = synth.from_pixels(np.zeros(lr.size, np.int64), lr.ravel(), lc.ravel(), n_modules=1, seed=9)
+    (r,) = emu.run([ev], 1, grids=(2, 2, 2, 2), hits=True)
+    ref = emulator.hits(ev, 2000)
+    assert ref["n_clusters"] > 2 * 2048
+    compare(r, ref, "lattice")
+    assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])

@@ -1,0 +1,128 @@
+"""Hits (the charge-weighted centroid of every kept cluster) as a consumer of an
+event's clusters: on the event's own stream, on another stream while the event is
+still in flight (the consumer waits for the event's completion event), after a
+batch launch; bit-exact against the oracle's hits."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_04334_amd import synth
+from tests.gpu_util import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def px():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_04334_amd import pxcl
+    pxcl.lib()
+    oracle.build()
+    return pxcl
+
+
+def _check_hits(px, slot, ev, what):
+    ref = oracle.hits(ev, 2000)
+    compare(px.produce(slot).numpy(), ref, what)
+    h = px.hits_produce(slot)
+    assert h.status == 0 and h.n_hits == ref["n_clusters"], what
+    hn = h.numpy()
+    assert np.array_equal(hn["x"], ref["x"]) and np.array_equal(hn["y"], ref["y"]), f"{what}: hits differ"
+
+
+def test_hits_same_stream(px):
+    import torch
+    evs = [synth.plain_event(0), synth.async_event(7), synth.stress_event(3)]
+    for i, ev in enumerate(evs):
+        print(f"hits same stream, event {i}", flush=True)
+        ctx = px.Context(ev["n_modules"], 2000)
+        slot = px.Event(ctx, ev["module"].size)
+        s = torch.cuda.Stream()
+        d = px.Digis.from_numpy(ev, "cuda")
+        px.acquire(slot, d, s)
+        px.hits_enqueue(slot, s)                   # queued behind the clusters, no wait needed
+        px.hits_wait(slot)
+        px.wait(slot)
+        _check_hits(px, slot, ev, f"event {i}")
+        slot.close()
+        ctx.close()
+
+
+def test_hits_on_another_stream_while_in_flight(px):
+    import torch
+    ev = synth.async_event(8)
+    ctx = px.Context(1856, 2000)
+    slot = px.Event(ctx, ev["module"].size)
+    d = px.Digis.from_numpy(ev, "cuda")
+    s_ev, s_hits = torch.cuda.Stream(), torch.cuda.Stream()
+    calls = []
+    with torch.cuda.stream(s_ev):
+        torch.cuda._sleep(100_000_000)             # keep the event's stream busy (~50 ms)
+    px.acquire(slot, d, s_ev)
+    assert px.query(slot) == px.E_NOT_READY
+    px.hits_enqueue(slot, s_hits, done_cb=lambda st: calls.append(st))
+    assert px.hits_query(slot) == px.E_NOT_READY
+    with pytest.raises(px.PxclError) as ei:
+        px.hits_enqueue(slot, s_hits)              # one hits launch in flight per event
+    assert ei.value.code == px.E_BUSY
+    with pytest.raises(px.PxclError) as ei:
+        px.acquire(slot, d, s_ev)                  # the slot is still read by the hits
+    assert ei.value.code == px.E_BUSY
+    px.hits_wait(slot)
+    px.wait(slot)
+    time.sleep(0.01)
+    assert calls == [0]
+    _check_hits(px, slot, ev, "chained")
+    slot.close()
+    ctx.close()
+
+
+def test_hits_after_batch(px):
+    import torch
+    evs = [synth.batch_event(40 + i) for i in range(6)]
+    ctx = px.Context(1856, 2000)
+    b = px.Batch(ctx, 8)
+    slots = [px.Event(ctx, max(e["module"].size for e in evs)) for _ in evs]
+    digis = [px.Digis.from_numpy(e, "cuda") for e in evs]
+    s = torch.cuda.Stream()
+    f = px.Flag()
+    px.acquire_batch(b, slots, digis, s, flag=f, graph=True)
+    other = torch.cuda.Stream()
+    for sl in slots:
+        px.hits_enqueue(sl, other)                 # some may still be in flight
+    for i, (sl, e) in enumerate(zip(slots, evs)):
+        px.hits_wait(sl)
+        px.wait(sl)
+        _check_hits(px, sl, e, f"batch event {i}")
+    for sl in slots:
+        sl.close()
+    b.close()
+    ctx.close()
+
+
+def test_hits_errors(px):
+    ctx = px.Context(4, 2000)
+    ev = synth.plain_event(1, n_modules=4)
+    slot = px.Event(ctx, ev["module"].size)
+    with pytest.raises(px.PxclError) as ei:
+        px.hits_enqueue(slot)                      # nothing acquired
+    assert ei.value.code == px.E_INVAL
+    bad = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
+    bad["row"][3] = 200
+    px.acquire(slot, px.Digis.from_numpy(bad, "cuda"))
+    px.hits_enqueue(slot)
+    px.hits_wait(slot)
+    assert px.hits_produce(slot).status == px.E_RANGE
+    px.acquire(slot, px.Digis.from_numpy(ev, "cuda"))   # the slot is reusable
+    px.hits_enqueue(slot)
+    px.hits_wait(slot)
+    px.wait(slot)
+    _check_hits(px, slot, ev, "after error")
+    slot.close()
+    ctx.close()
