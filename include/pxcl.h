@@ -236,6 +236,33 @@ int pxcl_hits_produce(pxcl_event* ev, pxcl_hits* out);
 /* Blocking wait for the hits (tests and simple callers), like pxcl_wait. */
 int pxcl_hits_wait(pxcl_event* ev);
 
+/* ---- transfer to the host on demand ----------------------------------------------- */
+/* Sec. 4.3: device results go to the host only when a CPU consumer asks.
+ * pxcl_copy_to_host queues asynchronous device-to-host copies of the event's kept
+ * clusters (and, if digi_cluster is set, its per-digi ids; if x and y are set, its
+ * hits, which must have been queued) into caller-owned pinned buffers, on `stream`,
+ * waiting for the event (and the hits) across streams like pxcl_hits_enqueue.  The
+ * cluster arrays must hold `capacity` >= the event's kept clusters once it is
+ * complete, or >= its digis while it may be in flight (PXCL_E_CAPACITY otherwise).
+ * When `cb` fires (exactly once, with the event's status) the buffers hold the data
+ * and n_clusters and status are set.  PXCL_E_BUSY while a copy of the event is in
+ * flight; an acquire of the event returns PXCL_E_BUSY while it is.  Non-blocking. */
+typedef struct {
+    int32_t* id;               /* pinned host [capacity] */
+    int32_t* charge;           /* pinned host [capacity] */
+    int32_t* size;             /* pinned host [capacity] */
+    int32_t* digi_cluster;     /* pinned host [n_digis], or NULL */
+    float* x;                  /* pinned host [capacity] hits, or NULL (with y) */
+    float* y;
+    uint32_t capacity;
+    uint32_t n_clusters;       /* out, when the callback fires */
+    int32_t status;            /* out, when the callback fires */
+} pxcl_host_clusters;
+int pxcl_copy_to_host(pxcl_event* ev, void* stream, pxcl_host_clusters* dst, pxcl_done_cb cb, void* user);
+/* PXCL_OK once the copy is complete, PXCL_E_NOT_READY while in flight, PXCL_E_INVAL
+ * if none was queued.  Non-blocking. */
+int pxcl_copy_query(const pxcl_event* ev);
+
 /* ---- batches: many events in one launch --------------------------------------- */
 size_t pxcl_batch_workspace_bytes(const pxcl_ctx* ctx, uint32_t max_events);
 size_t pxcl_batch_pinned_bytes(const pxcl_ctx* ctx, uint32_t max_events);

@@ -114,6 +114,13 @@ struct pxcl_event {
     void* hits_user = nullptr;
     int32_t hits_status = PXCL_OK;
     u32 hits_n = 0;
+    // copy to host of the last acquired event
+    std::atomic<int> cstate{ST_IDLE};
+    std::atomic<int> copy_pending{0};
+    hipEvent_t copy_ev = nullptr;
+    pxcl_host_clusters* copy_dst = nullptr;
+    pxcl_done_cb copy_cb = nullptr;
+    void* copy_user = nullptr;
 };
 
 struct pxcl_batch {
@@ -389,6 +396,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipEventCreateWithFlags(&ev->done_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev->hits_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev->copy_ev, hipEventDisableTiming);
     for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev->tev[i]);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.seg, 0, L.item_start - L.seg, s);
@@ -396,6 +404,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     if (e != hipSuccess) {
         if (ev->done_ev) hipEventDestroy(ev->done_ev);
         if (ev->hits_ev) hipEventDestroy(ev->hits_ev);
+        if (ev->copy_ev) hipEventDestroy(ev->copy_ev);
         for (int i = 0; i < 5; ++i) if (ev->tev[i]) hipEventDestroy(ev->tev[i]);
         delete ev;
         return PXCL_E_HIP;
@@ -409,14 +418,19 @@ extern "C" int pxcl_event_unbind(pxcl_event* ev) {
     if (!ev) return PXCL_E_INVAL;
     if (ev->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
     if (ev->hstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
-    if (ev->cb_pending.load(std::memory_order_acquire) > 0 || ev->hits_pending.load(std::memory_order_acquire) > 0) {
+    if (ev->cstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+    auto pending = [ev]() {
+        return ev->cb_pending.load(std::memory_order_acquire) > 0 ||
+               ev->hits_pending.load(std::memory_order_acquire) > 0 ||
+               ev->copy_pending.load(std::memory_order_acquire) > 0;
+    };
+    if (pending()) {
         if (t_in_callback) return PXCL_E_BUSY;                    // a callback of it is still running
-        while (ev->cb_pending.load(std::memory_order_acquire) > 0 ||
-               ev->hits_pending.load(std::memory_order_acquire) > 0)
-            std::this_thread::yield();
+        while (pending()) std::this_thread::yield();
     }
     hipEventDestroy(ev->done_ev);
     hipEventDestroy(ev->hits_ev);
+    hipEventDestroy(ev->copy_ev);
     for (int i = 0; i < 5; ++i) hipEventDestroy(ev->tev[i]);
     ev->ctx->bound.fetch_sub(1);
     delete ev;
@@ -429,6 +443,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     if (!ev || !digis_ok(in)) return PXCL_E_INVAL;
     if (in->n > ev->cap) return PXCL_E_CAPACITY;
     if (ev->hstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;   // hits read the slot
+    if (ev->cstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;   // so does a copy
     if (!claim(ev->state)) return PXCL_E_BUSY;
     ev->hstate.store(ST_IDLE, std::memory_order_release);
     pxcl_ctx* ctx = ev->ctx;
@@ -642,6 +657,95 @@ extern "C" int pxcl_hits_produce(pxcl_event* ev, pxcl_hits* out) {
     return ev->hits_status;
 }
 
+// ---------------------------------------------------------------------------
+// copy to host on demand
+// ---------------------------------------------------------------------------
+namespace {
+void copy_done_hostfn(void* p) {
+    pxcl_event* ev = static_cast<pxcl_event*>(p);
+    volatile u32* hs = ev->hs;
+    const u32 tag = __atomic_load_n(&ev->hs[HS_EPOCH], __ATOMIC_ACQUIRE);
+    u32 bits = hs[HS_ERR];
+    if (tag != ev->epoch) bits |= EB_INTERNAL;
+    const u32 ncl = hs[HS_NCL];
+    pxcl_host_clusters* d = ev->copy_dst;
+    d->status = status_from_bits(bits);
+    d->n_clusters = d->status == PXCL_OK ? (ncl < ev->n ? ncl : ev->n) : 0u;
+    pxcl_done_cb cb = ev->copy_cb;
+    void* user = ev->copy_user;
+    const int32_t st = d->status;
+    ev->cstate.store(ST_DONE, std::memory_order_release);
+    if (cb) {
+        ++t_in_callback;
+        cb(user, st);
+        --t_in_callback;
+    }
+    ev->copy_pending.fetch_sub(1, std::memory_order_acq_rel);
+}
+}  // namespace
+
+extern "C" int pxcl_copy_to_host(pxcl_event* ev, void* stream, pxcl_host_clusters* dst, pxcl_done_cb cb,
+                                 void* user) {
+    if (!ev || !dst || !dst->id || !dst->charge || !dst->size) return PXCL_E_INVAL;
+    const int st = ev->state.load(std::memory_order_acquire);
+    if (st == ST_IDLE) return PXCL_E_INVAL;
+    const bool want_hits = dst->x || dst->y;
+    const int hst = ev->hstate.load(std::memory_order_acquire);
+    if (want_hits && (!dst->x || !dst->y || hst == ST_IDLE)) return PXCL_E_INVAL;   // no hits queued
+    // clusters to copy: exact once the event is complete, else the bound n
+    const u32 ncl = (st == ST_DONE) ? ev->ncl : ev->n;
+    if (dst->capacity < ncl) return PXCL_E_CAPACITY;
+    if (!claim(ev->cstate)) return PXCL_E_BUSY;
+    pxcl_ctx* ctx = ev->ctx;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    hipError_t e = hipSuccess;
+    if (st == ST_INFLIGHT && s != ev->stream)
+        e = hipStreamWaitEvent(s, ev->batch ? ev->batch->done_ev : ev->done_ev, 0);
+    if (e == hipSuccess && want_hits && hst == ST_INFLIGHT && s != ev->hits_stream)
+        e = hipStreamWaitEvent(s, ev->hits_ev, 0);
+    ev->copy_dst = dst;
+    ev->copy_cb = cb;
+    ev->copy_user = user;
+    dst->n_clusters = 0;
+    dst->status = PXCL_E_NOT_READY;
+    const EvLayout L = ev_layout(ev->cap, ctx->n_modules);
+    auto d2h = [&](void* to, size_t off, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(to, ev->ws + off, bytes, hipMemcpyDeviceToHost, s);
+    };
+    d2h(dst->id, L.id, size_t(ncl) * 4);
+    d2h(dst->charge, L.charge, size_t(ncl) * 4);
+    d2h(dst->size, L.size, size_t(ncl) * 4);
+    if (dst->digi_cluster) d2h(dst->digi_cluster, L.digi, size_t(ev->n) * 4);
+    if (want_hits) {
+        d2h(dst->x, L.hit_x, size_t(ncl) * 4);
+        d2h(dst->y, L.hit_y, size_t(ncl) * 4);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev->copy_ev, s);
+    if (e == hipSuccess) {
+        ev->copy_pending.fetch_add(1, std::memory_order_acq_rel);
+        e = hipLaunchHostFunc(s, copy_done_hostfn, ev);
+        if (e != hipSuccess) ev->copy_pending.fetch_sub(1, std::memory_order_acq_rel);
+    }
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ev->cstate.store(ST_IDLE, std::memory_order_release);
+        return PXCL_E_HIP;
+    }
+    return PXCL_OK;
+}
+
+extern "C" int pxcl_copy_query(const pxcl_event* ev) {
+    if (!ev) return PXCL_E_INVAL;
+    const int st = ev->cstate.load(std::memory_order_acquire);
+    if (st == ST_DONE) return PXCL_OK;
+    if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
+    return PXCL_E_INVAL;
+}
+
 extern "C" int pxcl_hits_wait(pxcl_event* ev) {
     if (!ev) return PXCL_E_INVAL;
     const int st = ev->hstate.load(std::memory_order_acquire);
@@ -765,6 +869,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         if (!evs[i] || evs[i]->ctx != b->ctx || !digis_ok(&ins[i])) return PXCL_E_INVAL;
         if (ins[i].n > evs[i]->cap) return PXCL_E_CAPACITY;
         if (evs[i]->hstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
+        if (evs[i]->cstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
         for (u32 j = 0; j < i; ++j)
             if (evs[j] == evs[i]) return PXCL_E_INVAL;
     }

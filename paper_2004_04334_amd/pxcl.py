@@ -52,6 +52,12 @@ class _Hits(ctypes.Structure):
                 ("device", ctypes.c_int32)]
 
 
+class _HostClusters(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_void_p), ("charge", ctypes.c_void_p), ("size", ctypes.c_void_p),
+                ("digi_cluster", ctypes.c_void_p), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("capacity", ctypes.c_uint32), ("n_clusters", ctypes.c_uint32), ("status", ctypes.c_int32)]
+
+
 class _Clusters(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("err_bits", ctypes.c_uint32), ("n_clusters", ctypes.c_uint32),
                 ("n_digis", ctypes.c_uint32), ("id", ctypes.c_void_p), ("charge", ctypes.c_void_p),
@@ -112,6 +118,9 @@ _SIGS = {
     "pxcl_hits_query": (ctypes.c_int, [ctypes.c_void_p]),
     "pxcl_hits_produce": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Hits)]),
     "pxcl_hits_wait": (ctypes.c_int, [ctypes.c_void_p]),
+    "pxcl_copy_to_host": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_HostClusters),
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "pxcl_copy_query": (ctypes.c_int, [ctypes.c_void_p]),
     "pxcl_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
     "pxcl_batch_pinned_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
     "pxcl_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -398,6 +407,46 @@ def hits_produce(event: Event) -> HitsResult:
     n = int(h.n_hits)
     return HitsResult(st, n, event._view(h.x, n).view(torch.float32), event._view(h.y, n).view(torch.float32),
                       h.stream or 0, h.done_event or 0)
+
+
+class HostCopy:
+    """Pinned host buffers a copy to the host fills (cluster arrays of `capacity`,
+    optionally per-digi ids and hits)."""
+
+    def __init__(self, capacity: int, n_digis: int = 0, hits: bool = False):
+        pin = dict(dtype=torch.int32, pin_memory=True)
+        self.id, self.charge, self.size = (torch.zeros(max(1, capacity), **pin) for _ in range(3))
+        self.digi = torch.zeros(max(1, n_digis), **pin) if n_digis else None
+        fpin = dict(dtype=torch.float32, pin_memory=True)
+        self.x = torch.zeros(max(1, capacity), **fpin) if hits else None
+        self.y = torch.zeros(max(1, capacity), **fpin) if hits else None
+        self.s = _HostClusters(self.id.data_ptr(), self.charge.data_ptr(), self.size.data_ptr(),
+                               self.digi.data_ptr() if self.digi is not None else None,
+                               self.x.data_ptr() if hits else None, self.y.data_ptr() if hits else None,
+                               int(capacity), 0, E_NOT_READY)
+
+    def numpy(self, n_digis: int = 0) -> dict:
+        k = int(self.s.n_clusters)
+        out = {"status": int(self.s.status), "n_clusters": k, "id": self.id[:k].numpy().copy(),
+               "charge": self.charge[:k].numpy().copy(), "size": self.size[:k].numpy().copy()}
+        if self.digi is not None:
+            out["digi"] = self.digi[:n_digis].numpy().copy()
+        if self.x is not None:
+            out["x"], out["y"] = self.x[:k].numpy().copy(), self.y[:k].numpy().copy()
+        return out
+
+
+def copy_to_host(event: Event, dst: HostCopy, stream=None, flag: Optional[Flag] = None) -> None:
+    """Queue the copy of the event's results (and hits, if `dst` has room for them)
+    to pinned host memory; `flag` fires when the data is there."""
+    cb_ptr, user = (flag_cb_ptr(), ctypes.addressof(flag)) if flag is not None else (None, None)
+    event._ckeep = (dst, flag)
+    _check(lib().pxcl_copy_to_host(event.handle, _stream_ptr(stream), ctypes.byref(dst.s), cb_ptr, user),
+           "copy_to_host")
+
+
+def copy_query(event: Event) -> int:
+    return int(lib().pxcl_copy_query(event.handle))
 
 
 class Batch:

@@ -126,3 +126,61 @@ def test_hits_errors(px):
     _check_hits(px, slot, ev, "after error")
     slot.close()
     ctx.close()
+
+
+def _wait_flag(f, timeout=30.0):
+    t0 = time.time()
+    while f.fired == 0:
+        assert time.time() - t0 < timeout, "callback did not fire"
+        time.sleep(0.0005)
+
+
+def test_copy_to_host_on_demand(px):
+    """Results and hits reach pinned host memory only when asked: after completion
+    (exact sizes), and while the event is still in flight on another stream (a bound
+    on the sizes, the count filled in by the callback)."""
+    import torch
+    ev = synth.async_event(9)
+    n = ev["module"].size
+    ref = oracle.hits(ev, 2000)
+    ctx = px.Context(1856, 2000)
+    slot = px.Event(ctx, n)
+    d = px.Digis.from_numpy(ev, "cuda")
+    # 1. after completion, same stream
+    px.acquire(slot, d)
+    px.wait(slot)
+    px.hits_enqueue(slot)
+    px.hits_wait(slot)
+    dst = px.HostCopy(ref["n_clusters"], n_digis=n, hits=True)
+    f = px.Flag()
+    px.copy_to_host(slot, dst, flag=f)
+    _wait_flag(f)
+    got = dst.numpy(n)
+    assert f.status == 0 and got["status"] == 0
+    compare(got, ref, "copy after completion")
+    assert np.array_equal(got["x"], ref["x"]) and np.array_equal(got["y"], ref["y"])
+    small = px.HostCopy(ref["n_clusters"] - 1)
+    with pytest.raises(px.PxclError) as ei:
+        px.copy_to_host(slot, small)
+    assert ei.value.code == px.E_CAPACITY
+    # 2. while in flight, on another stream
+    s_ev, s_cp = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s_ev):
+        torch.cuda._sleep(100_000_000)
+    px.acquire(slot, d, s_ev)
+    px.hits_enqueue(slot, s_ev)
+    dst2 = px.HostCopy(n, n_digis=n, hits=True)
+    f2 = px.Flag()
+    px.copy_to_host(slot, dst2, s_cp, flag=f2)
+    assert px.copy_query(slot) == px.E_NOT_READY
+    with pytest.raises(px.PxclError) as ei:
+        px.acquire(slot, d, s_ev)
+    assert ei.value.code == px.E_BUSY
+    _wait_flag(f2)
+    got2 = dst2.numpy(n)
+    compare(got2, ref, "copy while in flight")
+    assert np.array_equal(got2["x"], ref["x"]) and np.array_equal(got2["y"], ref["y"])
+    px.wait(slot)
+    px.hits_wait(slot)
+    slot.close()
+    ctx.close()
