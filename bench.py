@@ -27,8 +27,8 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["segment", "big", "small", "compact"]
-KERNEL_SYMBOLS = {"segment": "k_segment", "big": "k_big", "small": "k_small", "compact": "k_compact"}
+KERNELS = ["segment", "big", "small", "compact", "hits"]
+KERNEL_SYMBOLS = {"segment": "k_segment", "big": "k_big", "small": "k_small", "compact": "k_compact", "hits": "k_hits"}
 
 
 def event_bytes(n_digis: int, n_kept: int) -> int:
@@ -57,6 +57,8 @@ def load_traffic(workload: str, kernel: str):
 def roofline(ctx, bytes_per_launch: float, workload: str):
     ms, cnt = ctx.timing(reset=True)
     avg = {k: (ms[i] / cnt[i] if cnt[i] else 0.0) for i, k in enumerate(KERNELS)}
+    if not cnt[KERNELS.index("hits")]:
+        del avg["hits"]
     tot = {k: ms[i] for i, k in enumerate(KERNELS)}
     dom = max(tot, key=tot.get)
     t = avg[dom] * 1e-3
@@ -225,7 +227,7 @@ def gen_events(maker, count, **kw):
 
 
 # ---------------------------------------------------------------------------
-def bench_async(px, torch, args, synth):
+def bench_async(px, torch, args, synth, hits: bool = False):
     n_threads = 4
     evs = gen_events(synth.async_event, 32)
     ctx = px.Context(1856, 2000)
@@ -239,18 +241,25 @@ def bench_async(px, torch, args, synth):
         px.acquire(slots[0], d)
         px.wait(slots[0])
         kept.append(px.produce(slots[0]).n_clusters)
-    px.run_async(ctx, slots, streams, pool, max(1, args.warmup), cpu_task_ns=args.cpu_task_ns)
+    px.run_async(ctx, slots, streams, pool, max(1, args.warmup), cpu_task_ns=args.cpu_task_ns, hits=hits)
     ctx.timing(reset=True)
     ctx.set_timing(True, args.timing_period)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = px.run_async(ctx, slots, streams, pool, args.steps, cpu_task_ns=args.cpu_task_ns)
+    st = px.run_async(ctx, slots, streams, pool, args.steps, cpu_task_ns=args.cpu_task_ns, hits=hits)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.set_timing(False)
     n_ev = st["events"]
     b_mean = float(np.mean([event_bytes(e["module"].size, k) for e, k in zip(evs, kept)]))
-    rl = roofline(ctx, b_mean, "async")
+    rl = roofline(ctx, b_mean, "hits" if hits else "async")
+    if hits and rl["kernel_mean_us"].get("hits"):
+        # hits kernel: reads row, col, adc and the per-digi id (10 B/digi), the kept ids
+        # and charges (8 B/cluster), writes x and y (8 B/cluster)
+        hb = float(np.mean([10 * e["module"].size + 16 * k for e, k in zip(evs, kept)]))
+        gbs = hb / (rl["kernel_mean_us"]["hits"] * 1e-6) / 1e9
+        rl["hits_kernel"] = {"algorithmic_bytes_per_launch": int(hb), "achieved": round(gbs, 2),
+                             "frac": round(gbs / HBM_PEAK_GBS, 5)}
     out = {
         "value": n_ev / wall, "ms_per_step": wall * 1e3 / args.steps,
         "digis_per_s": st["digis"] / wall,
@@ -258,7 +267,8 @@ def bench_async(px, torch, args, synth):
         "host_blocked_us_per_event": st["blocked_us_per_event"],
         "cpu_tasks_per_s": st["cpu_tasks_per_s"], "errors": st["errors"],
         "config": {"workload": "async: 1856 modules x 160x416, ~50k digis/event, 4 host threads x 1 event "
-                               "in flight, synthetic CPU tasks while waiting",
+                               "in flight, synthetic CPU tasks while waiting" +
+                               (", hits queued behind every event" if hits else ""),
                    "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
                    "host_threads": n_threads, "cpu_task_ns": args.cpu_task_ns, "distinct_events": len(evs),
                    "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
@@ -268,6 +278,12 @@ def bench_async(px, torch, args, synth):
         s.close()
     ctx.close()
     return out
+
+
+def bench_hits(px, torch, args, synth):
+    """The asynchronous workload with every event's hits queued behind it on the
+    same stream (a consumer of the clusters) and produced with it."""
+    return bench_async(px, torch, args, synth, hits=True)
 
 
 def bench_plain(px, torch, args, synth):
@@ -450,7 +466,7 @@ def bench_serve(px, torch, args, synth):
     return out
 
 
-WORKLOADS = {"async": (bench_async, 2000, 100), "plain": (bench_plain, 2000, 100),
+WORKLOADS = {"async": (bench_async, 2000, 100), "hits": (bench_hits, 2000, 100), "plain": (bench_plain, 2000, 100),
              "batch": (bench_batch, 200, 10), "stress": (bench_stress, 100, 5),
              "serve": (bench_serve, 20000, 0)}
 

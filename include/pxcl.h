@@ -148,12 +148,12 @@ int pxcl_get_kernel_config(const pxcl_ctx* ctx, uint32_t* wg, uint32_t* mpw);
  * kernel of every period-th launch of each event or batch object (period 0: off,
  * the default; 1: every launch).  Launches that replay a captured graph are never
  * timed: elapsed times of events recorded inside a captured graph are not
- * available.  Stats: for each of the 4 kernels (0 segmentation, 1 big-module
- * clustering, 2 small-module clustering, 3 compaction) the summed milliseconds and
- * the number of timed launches; a launch is counted once its event is produced
- * (single events) or the batch object is used again or unbound (batches). */
+ * available.  Stats: for each of the 5 kernels (0 segmentation, 1 big-module
+ * clustering, 2 small-module clustering, 3 compaction, 4 hits) the summed
+ * milliseconds and the number of timed launches; a launch is counted once its event
+ * (or its hits) is produced, or the event or batch object is used again or unbound. */
 int pxcl_set_timing(pxcl_ctx* ctx, int period);
-int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum /*[4]*/, uint64_t* launches /*[4]*/, int reset);
+int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum /*[5]*/, uint64_t* launches /*[5]*/, int reset);
 
 /* ---- event slots ------------------------------------------------------------ */
 /* Device workspace bytes for an event slot of capacity max_digis (inputs staged for
@@ -313,11 +313,15 @@ typedef struct {
  * streams[t], keep one event in flight each; while it is in flight the thread runs
  * synthetic CPU tasks of cpu_task_ns nanoseconds (0 = none) and picks the event's
  * produce as soon as its callback has fired.  Thread t processes pool entries
- * t, t+n_threads, ... (mod pool_size), events_per_thread of them.  If blocking is
- * non-zero the thread instead waits with hipStreamSynchronize (the contrast). */
+ * t, t+n_threads, ... (mod pool_size), events_per_thread of them.  flags:
+ * PXCL_RUN_BLOCKING: the thread instead waits with hipStreamSynchronize (the
+ * contrast); PXCL_RUN_HITS: every event's hits are queued right behind it on the
+ * same stream and produced with it. */
+#define PXCL_RUN_BLOCKING 1
+#define PXCL_RUN_HITS 2
 int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
                    uint32_t n_threads, const pxcl_digis* pool, uint32_t pool_size,
-                   uint32_t events_per_thread, uint32_t cpu_task_ns, int blocking,
+                   uint32_t events_per_thread, uint32_t cpu_task_ns, int flags,
                    pxcl_run_stats* out);
 
 /* Serving form: requests arrive as a Poisson process (rate_hz, seeded) and draw

@@ -77,7 +77,8 @@ std::atomic<u64> g_sink{0};   // keeps the CPU tasks' results alive
 // ---------------------------------------------------------------------------
 extern "C" int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams, uint32_t n_threads,
                               const pxcl_digis* pool, uint32_t pool_size, uint32_t events_per_thread,
-                              uint32_t cpu_task_ns, int blocking, pxcl_run_stats* out) {
+                              uint32_t cpu_task_ns, int flags, pxcl_run_stats* out) {
+    const bool blocking = (flags & PXCL_RUN_BLOCKING) != 0, with_hits = (flags & PXCL_RUN_HITS) != 0;
     if (!ctx || !evs || !streams || !pool || !out || n_threads == 0 || pool_size == 0) return PXCL_E_INVAL;
     std::vector<std::vector<double>> lat(n_threads);
     std::vector<double> blocked(n_threads, 0.0);
@@ -96,24 +97,29 @@ extern "C" int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const
         while (!go.load(std::memory_order_acquire)) std::this_thread::yield();
         for (u32 i = 0; i < events_per_thread && rc.load() == PXCL_OK; ++i) {
             const pxcl_digis& in = pool[(t + u64(i) * n_threads) % pool_size];
-            pxcl_flag flag;
+            pxcl_flag flag, hflag;
             flag.status = 0;
             flag.fired = 0;
+            hflag.status = 0;
+            hflag.fired = 0;
             const auto t0 = clk::now();
             int r = pxcl_acquire(evs[t], &in, streams[t], pxcl_flag_cb, &flag);
+            if (r == PXCL_OK && with_hits) r = pxcl_hits_enqueue(evs[t], streams[t], pxcl_flag_cb, &hflag);
             const auto t1 = clk::now();
             blocked[t] += us_since(t0, t1);
             if (r != PXCL_OK) { rc.store(r); break; }
+            // the hits' callback comes after the event's (stream order)
+            pxcl_flag& last = with_hits ? hflag : flag;
             const u32 now_in = inflight.fetch_add(1) + 1;
             u32 m = max_inflight.load();
             while (now_in > m && !max_inflight.compare_exchange_weak(m, now_in)) {}
             if (blocking) {
                 const auto w0 = clk::now();
                 hipStreamSynchronize(static_cast<hipStream_t>(streams[t]));
-                while (__atomic_load_n(&flag.fired, __ATOMIC_ACQUIRE) == 0) std::this_thread::yield();
+                while (__atomic_load_n(&last.fired, __ATOMIC_ACQUIRE) == 0) std::this_thread::yield();
                 blocked[t] += us_since(w0, clk::now());
             } else {
-                while (__atomic_load_n(&flag.fired, __ATOMIC_ACQUIRE) == 0) {
+                while (__atomic_load_n(&last.fired, __ATOMIC_ACQUIRE) == 0) {
                     if (cpu_task_ns) {
                         g_sink.fetch_add(cpu_task(cpu_task_ns, tasks[t] + t), std::memory_order_relaxed);
                         ++tasks[t];
@@ -126,6 +132,10 @@ extern "C" int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const
             pxcl_clusters res;
             const auto p0 = clk::now();
             r = pxcl_produce(evs[t], &res);
+            if (r == PXCL_OK && with_hits) {
+                pxcl_hits hits;
+                r = pxcl_hits_produce(evs[t], &hits);
+            }
             const auto p1 = clk::now();
             blocked[t] += us_since(p0, p1);
             if (r != PXCL_OK) ++errors[t];

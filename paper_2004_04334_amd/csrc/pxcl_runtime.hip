@@ -79,8 +79,8 @@ struct pxcl_ctx {
     std::atomic<int> bound{0};
     std::atomic<int> timing{0};
     std::mutex tmu;
-    double tsum[4] = {0, 0, 0, 0};
-    u64 tcnt[4] = {0, 0, 0, 0};
+    double tsum[5] = {0, 0, 0, 0, 0};   // segment, big, small, compact, hits
+    u64 tcnt[5] = {0, 0, 0, 0, 0};
 };
 
 struct pxcl_event {
@@ -109,6 +109,9 @@ struct pxcl_event {
     std::atomic<int> hstate{ST_IDLE};
     std::atomic<int> hits_pending{0};
     hipEvent_t hits_ev = nullptr;
+    hipEvent_t hits_tev[2] = {};      // around the hits kernel of a timed launch
+    bool hits_timed = false;
+    u32 hits_launches = 0;
     hipStream_t hits_stream = nullptr;
     pxcl_done_cb hits_cb = nullptr;
     void* hits_user = nullptr;
@@ -351,7 +354,7 @@ extern "C" int pxcl_set_timing(pxcl_ctx* ctx, int period) {
 extern "C" int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum, uint64_t* launches, int reset) {
     if (!ctx) return PXCL_E_INVAL;
     std::lock_guard<std::mutex> g(ctx->tmu);
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 5; ++i) {
         if (ms_sum) ms_sum[i] = ctx->tsum[i];
         if (launches) launches[i] = ctx->tcnt[i];
         if (reset) { ctx->tsum[i] = 0; ctx->tcnt[i] = 0; }
@@ -397,6 +400,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     hipError_t e = hipEventCreateWithFlags(&ev->done_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev->hits_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev->copy_ev, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreate(&ev->hits_tev[i]);
     for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev->tev[i]);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.seg, 0, L.item_start - L.seg, s);
@@ -405,6 +409,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
         if (ev->done_ev) hipEventDestroy(ev->done_ev);
         if (ev->hits_ev) hipEventDestroy(ev->hits_ev);
         if (ev->copy_ev) hipEventDestroy(ev->copy_ev);
+        for (int i = 0; i < 2; ++i) if (ev->hits_tev[i]) hipEventDestroy(ev->hits_tev[i]);
         for (int i = 0; i < 5; ++i) if (ev->tev[i]) hipEventDestroy(ev->tev[i]);
         delete ev;
         return PXCL_E_HIP;
@@ -431,6 +436,7 @@ extern "C" int pxcl_event_unbind(pxcl_event* ev) {
     hipEventDestroy(ev->done_ev);
     hipEventDestroy(ev->hits_ev);
     hipEventDestroy(ev->copy_ev);
+    for (int i = 0; i < 2; ++i) hipEventDestroy(ev->hits_tev[i]);
     for (int i = 0; i < 5; ++i) hipEventDestroy(ev->tev[i]);
     ev->ctx->bound.fetch_sub(1);
     delete ev;
@@ -591,12 +597,26 @@ void hits_done_hostfn(void* p) {
 }
 }  // namespace
 
+// add the hits kernel time of the last timed hits launch (complete by now)
+static void collect_hits_timing(pxcl_event* ev) {
+    if (!ev->hits_timed) return;
+    ev->hits_timed = false;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, ev->hits_tev[0], ev->hits_tev[1]) != hipSuccess) { (void)hipGetLastError(); return; }
+    std::lock_guard<std::mutex> g(ev->ctx->tmu);
+    ev->ctx->tsum[4] += ms;
+    ev->ctx->tcnt[4] += 1;
+}
+
 extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, void* user) {
     if (!ev) return PXCL_E_INVAL;
     const int st = ev->state.load(std::memory_order_acquire);
     if (st == ST_IDLE) return PXCL_E_INVAL;                     // no event acquired
     if (!claim(ev->hstate)) return PXCL_E_BUSY;
     pxcl_ctx* ctx = ev->ctx;
+    collect_hits_timing(ev);                                    // the previous hits are complete
+    const int period = ctx->timing.load();
+    const bool timed = period > 0 && (ev->hits_launches++ % u32(period)) == 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int prev = 0;
     hipGetDevice(&prev);
@@ -617,7 +637,9 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
     a.charge_cut = ctx->charge_cut;
     const u64 items = std::min<u64>(std::max<u32>(ev->n, 1u), (u64)ctx->n_modules);
     const u32 grid = u32(std::max<u64>(1, std::min<u64>((u64)ctx->n_cu * ctx->occ_h, items)));
+    if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[0], s);
     if (e == hipSuccess) e = launch_hits(a, grid, s);
+    if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[1], s);
     if (e == hipSuccess) e = hipEventRecord(ev->hits_ev, s);
     if (e == hipSuccess) {
         ev->hits_pending.fetch_add(1, std::memory_order_acq_rel);
@@ -630,6 +652,7 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
         ev->hstate.store(ST_IDLE, std::memory_order_release);
         return PXCL_E_HIP;
     }
+    ev->hits_timed = timed;
     return PXCL_OK;
 }
 
@@ -646,6 +669,7 @@ extern "C" int pxcl_hits_produce(pxcl_event* ev, pxcl_hits* out) {
     const int st = ev->hstate.load(std::memory_order_acquire);
     if (st == ST_INFLIGHT) return PXCL_E_NOT_READY;
     if (st != ST_DONE) return PXCL_E_INVAL;
+    collect_hits_timing(ev);
     const EvLayout L = ev_layout(ev->cap, ev->ctx->n_modules);
     out->status = ev->hits_status;
     out->n_hits = ev->hits_status == PXCL_OK ? ev->hits_n : 0u;

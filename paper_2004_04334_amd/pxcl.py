@@ -279,8 +279,10 @@ class Context:
         _check(lib().pxcl_set_timing(self._h, int(period) if enable else 0), "set_timing")
 
     def timing(self, reset: bool = False):
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_uint64 * 4)()
+        """Summed milliseconds and timed launches of the kernels: segment, big,
+        small, compact, hits."""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_uint64 * 5)()
         _check(lib().pxcl_get_timing(self._h, ms, cnt, 1 if reset else 0), "get_timing")
         return list(ms), list(cnt)
 
@@ -534,14 +536,15 @@ def autotune_load(ctx: Context, cache_path: str, mean_digis: int) -> bool:
 
 
 def run_async(ctx: Context, events: Sequence[Event], streams, pool: Sequence[Digis], events_per_thread: int,
-              cpu_task_ns: int = 0, blocking: bool = False) -> dict:
+              cpu_task_ns: int = 0, blocking: bool = False, hits: bool = False) -> dict:
     n = len(events)
     evs = (ctypes.c_void_p * n)(*[e.handle.value for e in events])
     sts = (ctypes.c_void_p * n)(*[int(s.cuda_stream) for s in streams])
     ins = (_Digis * len(pool))(*[d.struct() for d in pool])
     st = RunStats()
     _check(lib().pxcl_run_async(ctx.handle, evs, sts, n, ins, len(pool), int(events_per_thread),
-                                int(cpu_task_ns), 1 if blocking else 0, ctypes.byref(st)), "run_async")
+                                int(cpu_task_ns), (1 if blocking else 0) | (2 if hits else 0), ctypes.byref(st)),
+           "run_async")
     return st.as_dict()
 
 
