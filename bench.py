@@ -82,8 +82,8 @@ N_STREAMS = 4              # streams the batched workloads spread their launches
 def profile_commands(workload: str) -> dict:
     """The rocprofv3 commands whose output --summarize-profiles reads (run from the
     repository root with the output directory DIR)."""
-    extra = "" if workload == "async" else " --no-graph"
-    steps = {"async": 100, "batch": 20, "stress": 10}.get(workload, 20)
+    extra = "" if workload in ("async", "hits") else " --no-graph"
+    steps = {"async": 100, "hits": 100, "batch": 20, "stress": 10}.get(workload, 20)
     b = f"python3 bench.py --workload {workload}{extra} --no-cpu-baseline"
     pmc = f"{b} --steps {steps} --warmup 2"
     return {
