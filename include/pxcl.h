@@ -305,7 +305,7 @@ typedef struct {
     uint64_t cpu_tasks;
     uint32_t errors;             /* events whose status was not PXCL_OK */
     uint32_t max_inflight;       /* largest number of events in flight at once */
-    uint64_t peak_resident_bytes;/* largest sum of admitted workspace bytes */
+    uint64_t peak_resident_bytes;/* largest sum of the workspace bytes of occupied slots */
     uint64_t batches;            /* device launches (pxcl_acquire_batch calls) */
 } pxcl_run_stats;
 
@@ -325,11 +325,14 @@ int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
                    pxcl_run_stats* out);
 
 /* Serving form: requests arrive as a Poisson process (rate_hz, seeded) and draw
- * their digis round-robin from `pool`.  A request is admitted when its workspace
- * fits in the device arena (first-fit sub-allocation of [d_arena, d_arena+arena_bytes),
- * capped at budget_bytes) and an event object is free; every tick the admitted
- * requests not yet launched go to the device as one batch on a free batch object
- * (continuous batching: batches on different streams overlap).  n_cpu_threads
+ * their digis round-robin from `pool`.  At set-up the device arena
+ * [d_arena, d_arena + arena_bytes) is carved into at most n_slots event slots of
+ * min(budget_bytes, arena_bytes) bytes in total, bound once, in size classes (powers
+ * of two from 16,384 digis up to the largest request) shared out in proportion to the
+ * requests that need each class; a request is admitted, in arrival order, when a slot
+ * of its class is free, so admission neither allocates nor clears memory.  Every tick
+ * the admitted requests not yet launched go to the device as one batch on a free batch
+ * object (continuous batching: batches on different streams overlap).  n_cpu_threads
  * threads run synthetic CPU tasks (cpu_task_ns each) and the produce work.
  * Latency = arrival -> produce returned.  h_pinned must hold n_slots event status
  * blocks (pxcl_event_pinned_bytes each).
@@ -341,7 +344,7 @@ typedef struct {
     double rate_hz;
     uint32_t n_requests;
     uint64_t budget_bytes;
-    uint32_t n_slots;            /* event objects (max requests resident at once) */
+    uint32_t n_slots;            /* event slots at most (max requests resident at once) */
     uint32_t max_batch;          /* events per launch (<= each batch's capacity) */
     uint32_t n_cpu_threads;
     uint32_t cpu_task_ns;

@@ -176,61 +176,33 @@ extern "C" int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const
 // ---------------------------------------------------------------------------
 // serving form
 // ---------------------------------------------------------------------------
-namespace pxcl {
-int event_rebind(pxcl_event* ev, void* d_ws, size_t ws_bytes, uint32_t max_digis, hipStream_t s);
-}
-
 namespace {
-
-// First-fit sub-allocator over the arena, 256-byte granules, coalescing on free.
-class Arena {
-  public:
-    Arena(size_t size, size_t budget) : budget_(budget) { free_[0] = size & ~size_t(255); }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = al256(bytes);
-        if (used_ + bytes > budget_) return false;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                peak_ = std::max(peak_, used_);
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = al256(bytes);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t peak() const { return peak_; }
-
-  private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0, peak_ = 0, budget_;
-};
 
 struct Request {
     double arrival_us;
     u32 pool_idx;
-    u32 slot;
-    size_t off, bytes;
+    u32 cls;      // size class
+    u32 slot;     // event slot while admitted
+};
+
+// Event slots for the serving form, bound once in size classes: class c holds events
+// of up to cap[c] digis (powers of two from 16,384 up to the largest request).  The
+// slots of a class take a share of the slot count and of the memory budget in
+// proportion to how many requests need that class, at least one each.  Admission then
+// takes a free slot of the request's class: no allocation, binding or clearing happens
+// per request.
+struct SlotPool {
+    std::vector<u32> cap;                     // per class: capacity in digis
+    std::vector<size_t> bytes;                // per class: workspace bytes
+    std::vector<std::vector<u32>> free;       // per class: free slot indices
+    std::vector<u32> slot_cls;                // per slot: its class
+    std::vector<pxcl_event*> ev;              // per slot
+    size_t in_use = 0, peak = 0;
+    u32 class_of(u32 n) const {
+        for (u32 c = 0; c < cap.size(); ++c)
+            if (n <= cap[c]) return c;
+        return u32(cap.size()) - 1;
+    }
 };
 
 struct ServeState;
@@ -280,19 +252,58 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     const size_t min_ws = pxcl_event_workspace_bytes(ctx, std::max<u32>(max_n, 1));
     if (min_ws == 0 || min_ws > arena_bytes || min_ws > o->budget_bytes) return PXCL_E_CAPACITY;
 
-    // event objects: bound once to a placeholder range, rebound per request
-    std::vector<pxcl_event*> slot_ev(o->n_slots, nullptr);
+    SlotPool P;
+    for (u32 c = 16384;; c *= 2) {
+        P.cap.push_back(std::min(c, std::max<u32>(max_n, 1)));
+        if (c >= max_n) break;
+    }
+    const u32 ncls = u32(P.cap.size());
+    for (u32 c = 0; c < ncls; ++c) P.bytes.push_back(al256(pxcl_event_workspace_bytes(ctx, P.cap[c])));
+    std::vector<double> need(ncls, 0.0);
+    for (u32 i = 0; i < o->n_requests; ++i) need[P.class_of(std::max<u32>(pool[i % pool_size].n, 1))] += 1.0;
+    const size_t budget = std::min<size_t>(o->budget_bytes, arena_bytes);
+    std::vector<u32> count(ncls, 0);
+    size_t total = 0;
+    u32 nslots = 0;
+    for (u32 c = 0; c < ncls; ++c)
+        if (need[c] > 0) {
+            count[c] = std::max<u32>(1, u32(double(o->n_slots) * need[c] / double(o->n_requests)));
+            total += count[c] * P.bytes[c];
+            nslots += count[c];
+        }
+    while ((total > budget || nslots > o->n_slots) ) {   // shrink the class with the most bytes
+        u32 w = ncls;
+        for (u32 c = 0; c < ncls; ++c)
+            if (count[c] > 1 && (w == ncls || count[c] * P.bytes[c] > count[w] * P.bytes[w])) w = c;
+        if (w == ncls) break;
+        --count[w];
+        total -= P.bytes[w];
+        --nslots;
+    }
+    if (total > budget || nslots > o->n_slots) return PXCL_E_CAPACITY;
     const size_t hsb = pxcl_event_pinned_bytes(ctx);
     hipStream_t s0 = static_cast<hipStream_t>(streams[0]);
     int rc = PXCL_OK;
-    for (u32 i = 0; i < o->n_slots && rc == PXCL_OK; ++i)
-        rc = pxcl_event_bind(ctx, d_arena, arena_bytes, static_cast<u8*>(h_pinned) + i * hsb, hsb, 1, s0,
-                             &slot_ev[i]);
+    P.free.resize(ncls);
+    size_t off = 0;
+    for (u32 c = 0; c < ncls && rc == PXCL_OK; ++c)
+        for (u32 j = 0; j < count[c] && rc == PXCL_OK; ++j) {
+            const u32 i = u32(P.ev.size());
+            pxcl_event* e = nullptr;
+            rc = pxcl_event_bind(ctx, static_cast<u8*>(d_arena) + off, P.bytes[c], static_cast<u8*>(h_pinned) + i * hsb,
+                                 hsb, P.cap[c], s0, &e);
+            if (rc != PXCL_OK) break;
+            P.ev.push_back(e);
+            P.slot_cls.push_back(c);
+            P.free[c].push_back(i);
+            off += P.bytes[c];
+        }
     if (rc == PXCL_OK && hipStreamSynchronize(s0) != hipSuccess) rc = PXCL_E_HIP;
     if (rc != PXCL_OK) {
-        for (auto* e : slot_ev) if (e) pxcl_event_unbind(e);
+        for (auto* e : P.ev) pxcl_event_unbind(e);
         return rc;
     }
+    std::vector<pxcl_event*>& slot_ev = P.ev;
 
     // arrivals
     std::vector<Request> req(o->n_requests);
@@ -304,13 +315,11 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
             t += gap(rng);
             req[i].arrival_us = t;
             req[i].pool_idx = i % pool_size;
+            req[i].cls = P.class_of(std::max<u32>(pool[req[i].pool_idx].n, 1));
         }
     }
 
-    Arena arena(arena_bytes, std::min<size_t>(o->budget_bytes, arena_bytes));
-    std::mutex amu;                       // arena + free slots
-    std::vector<u32> free_slots;
-    for (u32 i = 0; i < o->n_slots; ++i) free_slots.push_back(o->n_slots - 1 - i);
+    std::mutex amu;                       // free slots
     ServeState S;
     S.batch_free_mask.store((n_batches >= 32 ? 0xFFFFFFFFu : ((1u << n_batches) - 1u)));
     std::vector<BatchCtx> bctx(n_batches);
@@ -361,8 +370,8 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
                 if (request_nclusters) request_nclusters[r] = res.n_clusters;
                 {
                     std::lock_guard<std::mutex> g(amu);
-                    arena.release(q.off, q.bytes);
-                    free_slots.push_back(q.slot);
+                    P.free[P.slot_cls[q.slot]].push_back(q.slot);
+                    P.in_use -= P.bytes[P.slot_cls[q.slot]];
                 }
                 inflight.fetch_sub(1);
                 S.done.fetch_add(1, std::memory_order_acq_rel);
@@ -387,12 +396,14 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         while (next_arrival < o->n_requests && req[next_arrival].arrival_us <= now) arrived.push_back(next_arrival++);
         {
             std::lock_guard<std::mutex> g(amu);
-            while (!arrived.empty() && !free_slots.empty()) {
+            while (!arrived.empty()) {                 // in arrival order
                 Request& q = req[arrived.front()];
-                q.bytes = pxcl_event_workspace_bytes(ctx, std::max<u32>(pool[q.pool_idx].n, 1));
-                if (!arena.alloc(q.bytes, &q.off)) break;
-                q.slot = free_slots.back();
-                free_slots.pop_back();
+                auto& fr = P.free[q.cls];
+                if (fr.empty()) break;
+                q.slot = fr.back();
+                fr.pop_back();
+                P.in_use += P.bytes[q.cls];
+                P.peak = std::max(P.peak, P.in_use);
                 admitted.push_back(arrived.front());
                 arrived.pop_front();
             }
@@ -409,8 +420,6 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
                 const u32 r = admitted.front();
                 admitted.pop_front();
                 Request& q = req[r];
-                pxcl::event_rebind(slot_ev[q.slot], static_cast<u8*>(d_arena) + q.off, q.bytes,
-                                   std::max<u32>(pool[q.pool_idx].n, 1), s);
                 bev[k] = slot_ev[q.slot];
                 bin[k] = pool[q.pool_idx];
                 bc.req[k] = r;
@@ -451,7 +460,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     out->cpu_tasks_per_s = out->wall_s > 0 ? double(out->cpu_tasks) / out->wall_s : 0;
     out->errors = errors.load();
     out->max_inflight = max_inflight.load();
-    out->peak_resident_bytes = arena.peak();
+    out->peak_resident_bytes = P.peak;
     out->batches = batches_launched.load();
     return err_rc.load();
 }

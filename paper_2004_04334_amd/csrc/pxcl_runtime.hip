@@ -1016,20 +1016,4 @@ const std::string& ctx_arch(const pxcl_ctx* c) { return c->arch; }
 int ctx_device(const pxcl_ctx* c) { return c->device; }
 }  // namespace pxcl
 
-// Point an idle event object at another workspace range (serving: per-request
-// workspaces carved out of one arena).  Clears the slot's control words with an
-// async memset on `s`; look-back status words need no clearing because launch tags
-// are unique within the process.
-namespace pxcl {
-int event_rebind(pxcl_event* ev, void* d_ws, size_t ws_bytes, uint32_t max_digis, hipStream_t s) {
-    if (!ev || !d_ws || max_digis == 0 || max_digis > PXCL_MAX_EVENT_DIGIS) return PXCL_E_INVAL;
-    if (ev->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
-    const EvLayout L = ev_layout(max_digis, ev->ctx->n_modules);
-    if (ws_bytes < L.total) return PXCL_E_CAPACITY;
-    ev->ws = static_cast<u8*>(d_ws);
-    ev->ws_bytes = ws_bytes;
-    ev->cap = max_digis;
-    ev->state.store(ST_IDLE, std::memory_order_release);
-    return hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s) == hipSuccess ? PXCL_OK : PXCL_E_HIP;
-}
-}  // namespace pxcl
+
