@@ -27,7 +27,10 @@ constexpr u32 MAX_RUNS = PIX / 2;        // vertical runs in a module (alternati
 constexpr u32 MAXB = 128;                // events per batch
 
 // Kernel shapes.
-constexpr u32 A_WG = 256, A_PER = 8, A_CH = A_WG * A_PER;   // segmentation: digis per chunk
+constexpr u32 A_WG = 256;                                   // segmentation: ids per thread,
+constexpr u32 A_PER_N = 8, A_PER_W = 32;                    // narrow chunks for launches that
+                                                            // cannot fill the device, wide ones
+                                                            // (fewer end-of-chunk atomics) else
 constexpr u32 C_WG = 256, C_ITEMS = 8;                      // compaction: items per workgroup
 constexpr u32 K_SMALL = 8;                                  // digis per thread (small-module kernel)
 constexpr u32 B_WG = 512, K_BIG = 32;                       // big-module kernel
@@ -54,7 +57,9 @@ constexpr u32 HS_BYTES = HS_WORDS * 4;
 constexpr u32 EB_RANGE = 1, EB_ORDER = 2, EB_DUP = 4, EB_INTERNAL = 8, EB_HINT = 16;
 
 // Launch flags.
-constexpr u32 LF_NO_BIG = 1;   // the big-module kernel is not launched (size hint)
+constexpr u32 LF_NO_BIG = 1;     // the big-module kernel is not launched (size hint)
+constexpr u32 LF_SEG_WIDE = 2;   // segmentation in wide chunks
+__host__ __device__ constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
 // One event as the kernels see it (64 bytes).
 struct EventDesc {

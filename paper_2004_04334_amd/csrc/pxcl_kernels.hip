@@ -333,7 +333,9 @@ __device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc
     }
 }
 
+template <u32 PER>
 __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
+    constexpr u32 CH = A_WG * PER;
     __shared__ u32 s_pref[MAXB + 1];
     __shared__ u32 s_wsum[A_WG / 64];
     __shared__ u32 s_st[IDX_SPAN + 1];
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
     __shared__ u32 s_err, s_last;
     const u32 tid = threadIdx.x;
     const u32 k = num_events(a);
-    const u32 total = event_prefix<A_WG>(a, k, s_pref, s_wsum, 0, A_CH, 0);
+    const u32 total = event_prefix<A_WG>(a, k, s_pref, s_wsum, 0, CH, 0);
 
     for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
         if (tid == 0) s_err = 0;
@@ -351,16 +353,28 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
         const EvLayout L = ev_layout(E.cap, a.n_modules);
         u64* seg = ws_ptr<u64>(E, L.seg);
         const u32 n = E.n;
-        const u32 i0 = c * A_CH + tid * A_PER;
-        u32 m[A_PER];
+        const u32 i0 = c * CH + tid * PER;
+        u32 m[PER];
+        if ((reinterpret_cast<uintptr_t>(E.module) & 15u) == 0 && i0 + PER <= n) {
+            uint4 v[PER / 8];                             // 16-byte loads, all in flight together
 #pragma unroll
-        for (u32 j = 0; j < A_PER; ++j) m[j] = E.module[min(i0 + j, n - 1)];
+            for (u32 q = 0; q < PER / 8; ++q) v[q] = reinterpret_cast<const uint4*>(E.module + i0)[q];
+#pragma unroll
+            for (u32 q = 0; q < PER / 8; ++q) {
+                const u32 w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+                for (u32 j = 0; j < 8; ++j) m[8 * q + j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+            }
+        } else {
+#pragma unroll
+            for (u32 j = 0; j < PER; ++j) m[j] = E.module[min(i0 + j, n - 1)];
+        }
         const u32 prev = E.module[i0 > 0 ? min(i0 - 1, n - 1) : 0];
         lds_barrier();                           // s_err cleared
         u32 err = 0;
         const u64 tag = u64(E.epoch) << 32;
 #pragma unroll
-        for (u32 j = 0; j < A_PER; ++j) {
+        for (u32 j = 0; j < PER; ++j) {
             const u32 i = i0 + j;
             if (i < n) {
                 const u32 pm = (j == 0) ? prev : m[j - 1];
@@ -372,7 +386,7 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
         if (err) atomicOr(&s_err, err);
         wait_all_mem();                          // this thread's table entries are visible
         lds_barrier();
-        const u32 chunks = (n + A_CH - 1) / A_CH;
+        const u32 chunks = (n + CH - 1) / CH;
         if (tid == 0) {
             u32* ctl = ws_ptr<u32>(E, L.ctl);
             if (s_err) atomicOr(&ctl[CTL_ERR], s_err);
@@ -1334,7 +1348,10 @@ static int occ(const void* fn, int bs) {
     return n;
 }
 
-int occupancy_segment() { return occ(reinterpret_cast<const void*>(k_segment), A_WG); }
+int occupancy_segment() {
+    return std::min(occ(reinterpret_cast<const void*>(k_segment<A_PER_N>), A_WG),
+                    occ(reinterpret_cast<const void*>(k_segment<A_PER_W>), A_WG));
+}
 int occupancy_cluster(u32 wg, u32 mpw) {
     SmallKernel f = small_kernel(wg, mpw);
     return f ? occ(reinterpret_cast<const void*>(f), int(wg)) : 0;
@@ -1343,7 +1360,8 @@ int occupancy_big() { return occ(reinterpret_cast<const void*>(k_big), B_WG); }
 int occupancy_compact() { return occ(reinterpret_cast<const void*>(k_compact), C_WG); }
 
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_segment, dim3(grid), dim3(A_WG), 0, s, a);
+    if (a.flags & LF_SEG_WIDE) hipLaunchKernelGGL(k_segment<A_PER_W>, dim3(grid), dim3(A_WG), 0, s, a);
+    else hipLaunchKernelGGL(k_segment<A_PER_N>, dim3(grid), dim3(A_WG), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s) {

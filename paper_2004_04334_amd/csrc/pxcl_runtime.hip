@@ -158,10 +158,16 @@ struct Grids {
     u32 a, b, s, c;   // segment, big, small, compact
 };
 
+// Wide segmentation chunks once a launch holds at least one of them per compute
+// unit: the chip is still filled and the end-of-chunk atomics are four times fewer.
+static u32 seg_flag(const pxcl_ctx* ctx, u64 digis) {
+    return digis >= (u64)ctx->n_cu * seg_chunk(LF_SEG_WIDE) ? LF_SEG_WIDE : 0u;
+}
+
 // Grids of the four kernels.  `digis` and `items` bound the launch's digis and work
 // items (modules present); with `full` (a captured graph replays with any input)
 // every kernel gets what fits on the device at once.
-Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 items, u32 k, bool full) {
+Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 items, u32 k, u32 flags, bool full) {
     Grids g;
     const u64 ncu = ctx->n_cu;
     const u64 fa = ncu * (u64)ctx->occ_a;
@@ -173,7 +179,8 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 items, u32 
         return g;
     }
     const u32 dcap = cluster_capacity(wg, mpw);
-    g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + A_CH - 1) / A_CH + k)));
+    const u64 ch = seg_chunk(flags);
+    g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + ch - 1) / ch + k)));
     g.b = u32(std::max<u64>(1, std::min<u64>(fb, digis / (dcap + 1))));
     g.s = u32(std::max<u64>(1, std::min<u64>(fs, (items + mpw - 1) / mpw)));
     g.c = u32(std::max<u64>(1, std::min<u64>(fc, (items + C_ITEMS - 1) / C_ITEMS + k)));
@@ -476,10 +483,11 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.charge_cut = ctx->charge_cut;
     a.dcap = cluster_capacity(wg, mpw);
     if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
+    a.flags |= seg_flag(ctx, in->n);
     hipError_t e = make_desc(ev, in, s, &a.single);
     ev->desc = a.single;
     const u64 items = std::min<u64>(in->n, (u64)ctx->n_modules);
-    const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, false);
+    const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, a.flags, false);
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) {
@@ -868,7 +876,7 @@ static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, u32 flags) {
     pxcl_ctx* ctx = b->ctx;
     LaunchArgs a = batch_args(b, wg, mpw);
     a.flags = flags;
-    const Grids g = grids_for(ctx, wg, mpw, 0, 0, 0, true);
+    const Grids g = grids_for(ctx, wg, mpw, 0, 0, 0, flags, true);
     hipStream_t cs = b->cap_stream;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
@@ -946,6 +954,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         digis += ins[i].n;
         items += std::min<u64>(ins[i].n, (u64)ctx->n_modules);
     }
+    lflags |= seg_flag(ctx, digis);
     if (e == hipSuccess) {
         if (flags & PXCL_BATCH_GRAPH) {
             e = ensure_graph(b, wg, mpw, lflags);
@@ -954,7 +963,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
             LaunchArgs a = batch_args(b, wg, mpw);
             a.flags = lflags;
             e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
-            const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), k, false);
+            const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), k, lflags, false);
             if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? b->tev : nullptr);
         }
     }

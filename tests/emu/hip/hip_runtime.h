@@ -29,6 +29,7 @@ struct dim3 {
     dim3(uint32_t a = 1, uint32_t b = 1, uint32_t c = 1) : x(a), y(b), z(c) {}
 };
 struct emu_idx { uint32_t x, y, z; };
+struct uint4 { uint32_t x, y, z, w; };
 inline thread_local emu_idx threadIdx, blockIdx, blockDim, gridDim;
 
 struct EmuWave {

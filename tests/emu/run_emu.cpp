@@ -4,7 +4,8 @@
 //
 // input:  u32 k, n_modules, cut, wg, mpw, grid_a, grid_b, grid_s, grid_c, header
 //         (1: the events go through a batch header even when k == 1), launch flags
-//         (LF_NO_BIG: the big-module kernel is not run), hits (1: run the hits kernel
+//         (LF_NO_BIG: the big-module kernel is not run; LF_SEG_WIDE: segmentation in
+//         wide chunks), hits (1: run the hits kernel
 //         after the launch);
 //         per event: u32 n, u32 cap, u16 module[n], row[n], col[n], adc[n]
 // output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]

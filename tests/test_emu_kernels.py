@@ -67,6 +67,21 @@ def test_no_unsynchronised_shared_access(emulator, wg, mpw):
            sanitizer="thread")
 
 
+def test_wide_segmentation_chunks(emulator):
+    """Segmentation in wide chunks (the form of launches with many digis): events of
+    one partial chunk, an empty one, and one of 41,679 digis spanning six chunks with
+    a ragged tail, alone and in a batch."""
+    sr, sc = synth.serpentine(row_wise=True)
+    tr, tc = synth.column_track(7)
+    pr, pc = np.divmod(np.arange(8160) * 8 % (160 * 416), 160)[::-1]
+    m = np.concatenate([np.zeros(tr.size, np.int64), np.ones(sr.size, np.int64), np.full(pr.size, 4)])
+    ev = synth.from_pixels(m, np.concatenate([tr, sr, pr]), np.concatenate([tc, sc, pc]), n_modules=6, seed=5)
+    assert ev["module"].size > 5 * 8192
+    _check(emulator, [ev], 6, grids=(2, 2, 2, 2), seg_wide=True)
+    evs = _mixed_events() + [ev]
+    _check(emulator, evs, 6, grids=(3, 2, 3, 2), caps=[max(1, e["module"].size) + 5 for e in evs], seg_wide=True)
+
+
 def test_scratch_mode_big_module(emulator):
     """A module above the register capacity of the big-module kernel (a serpentine
     of 33,359 pixels) next to a full-column track."""
