@@ -10,12 +10,18 @@
  *    after completion.  The continuation is released by a reference-counted holder
  *    that non-framework threads may signal and that can carry an error.
  *    -> pxcl_acquire() enqueues all device work and returns without blocking;
- *       pxcl_done_cb fires exactly once, from a HIP runtime thread, with a status;
+ *       pxcl_done_cb fires exactly once, from the context's completion thread,
+ *       with a status;
  *       pxcl_produce() hands back the results without blocking.
  *  - Sec. 4.1 (asynchronous execution): during event processing only asynchronous
  *    copies, memsets and kernel launches are issued, on the caller's stream; no
  *    allocation and no synchronisation happens on the event path; completion is
  *    signalled by a callback queued into the stream after the work.
+ *    -> here an event is recorded into the stream after the work instead, and one
+ *       thread per context polls the events of the launches in flight and runs the
+ *       callbacks: queuing a host function costs the caller ~30 us per launch on
+ *       this platform and fires ~45-75 us after the work ends; polling an event
+ *       costs ~0.1 us and sees the end ~10 us after it.
  *    -> the library never allocates device or pinned memory: the caller allocates
  *       workspaces once (e.g. from PyTorch's caching allocator, the counterpart of
  *       the memory pool of Sec. 4.1) and binds them; device-side errors are
@@ -109,11 +115,12 @@ typedef struct {
     uint32_t max_module_digis;
 } pxcl_digis;
 
-/* Completion callback.  Runs on a HIP runtime thread once the event's (or batch's)
- * device work and status write-back are complete; status = PXCL_OK or an async
- * error code.  It must not call HIP and must not block: it only releases a waiting
- * task (e.g. enqueues produce()).  It fires exactly once per successful
- * pxcl_acquire / pxcl_acquire_batch and never when they return an error. */
+/* Completion callback.  Runs on the context's completion thread once the event's
+ * (or batch's) device work and status write-back are complete; status = PXCL_OK or
+ * an async error code.  It must not block: the context's other completions wait
+ * while it runs.  It may produce and acquire again; it may not destroy the context
+ * (PXCL_E_BUSY).  It fires exactly once per successful pxcl_acquire /
+ * pxcl_acquire_batch and never when they return an error. */
 typedef void (*pxcl_done_cb)(void* user, int32_t status);
 
 /* Results of one event (device pointers into the event's workspace).  Valid until
@@ -133,10 +140,12 @@ typedef struct {
 } pxcl_clusters;
 
 /* ---- context ---------------------------------------------------------------- */
-/* Create a context on `device`.  Queries the device and sets the default kernel
- * configuration.  Allocates only small host metadata. */
+/* Create a context on `device`.  Queries the device, sets the default kernel
+ * configuration and starts the context's completion thread (asleep while nothing
+ * is in flight).  Allocates only small host metadata. */
 int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** out);
-/* PXCL_E_BUSY while events or batches are still bound. */
+/* Stops the completion thread.  PXCL_E_BUSY while events or batches are still
+ * bound, or when called from a completion callback. */
 int pxcl_ctx_destroy(pxcl_ctx* ctx);
 
 /* Clustering kernel shape: workgroup size wg in {64,128,256,512} and modules per

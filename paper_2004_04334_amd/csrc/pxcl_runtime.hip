@@ -1,15 +1,20 @@
 // Host runtime of the pixel-clustering library: the C ABI of include/pxcl.h.
 //
 // acquire() only validates, stages host inputs with async copies, launches the
-// four kernels on the caller's stream and queues a host callback -- the split of a
-// module's work into acquire/produce with a completion callback that releases the
-// waiting task (paper Sec. 2 and Sec. 4.1).  No device or pinned allocation happens
-// after bind; the callback never calls HIP.
+// four kernels on the caller's stream and records a completion event -- the split
+// of a module's work into acquire/produce with a completion callback that releases
+// the waiting task (paper Sec. 2 and Sec. 4.1).  The callback runs on the context's
+// completion thread, which polls the completion events of the launches in flight:
+// a host function queued into the stream (the mechanism of Sec. 4.1) costs the
+// calling thread tens of microseconds per launch here and fires tens of
+// microseconds after the work ends, while a query of an event is a read of its
+// signal.  No device or pinned allocation happens after bind.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -17,6 +22,7 @@
 #include <string>
 #include <thread>
 #include <unistd.h>
+#include <vector>
 
 #include "../../include/pxcl.h"
 #include "pxcl_internal.h"
@@ -67,7 +73,24 @@ int status_from_bits(u32 bits) {
     return PXCL_OK;
 }
 
+// A launch whose completion event the completion thread polls.
+enum : int { CK_EVENT = 0, CK_BATCH = 1, CK_HITS = 2, CK_COPY = 3 };
+struct Pending {
+    int kind;
+    void* obj;          // pxcl_event* or pxcl_batch*
+    hipEvent_t done;    // recorded after the launch's work
+};
+
 }  // namespace
+
+struct pxcl_completer {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<Pending> in;           // posted, not yet taken by the thread
+    std::atomic<bool> has_in{false};
+    bool stop = false, idle = false;
+    std::thread th;
+};
 
 struct pxcl_ctx {
     int device = 0;
@@ -81,6 +104,7 @@ struct pxcl_ctx {
     std::mutex tmu;
     double tsum[5] = {0, 0, 0, 0, 0};   // segment, big, small, compact, hits
     u64 tcnt[5] = {0, 0, 0, 0, 0};
+    pxcl_completer comp;
 };
 
 struct pxcl_event {
@@ -251,7 +275,7 @@ void finish_event_from_host_status(pxcl_event* ev) {
 // the callback must not wait for the callback itself.
 thread_local int t_in_callback = 0;
 
-void event_done_hostfn(void* p) {
+void event_complete(void* p) {
     pxcl_event* ev = static_cast<pxcl_event*>(p);
     finish_event_from_host_status(ev);
     pxcl_done_cb cb = ev->cb;
@@ -266,7 +290,7 @@ void event_done_hostfn(void* p) {
     ev->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
 }
 
-void batch_done_hostfn(void* p) {
+void batch_complete(void* p) {
     pxcl_batch* b = static_cast<pxcl_batch*>(p);
     int32_t bst = PXCL_OK;
     for (u32 i = 0; i < b->k; ++i) {
@@ -301,6 +325,25 @@ bool claim(std::atomic<int>& st) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// completion thread
+// ---------------------------------------------------------------------------
+static void completer_loop(pxcl_completer* c, int device);
+
+// Hand a launch to the completion thread; its completion step and callback run once
+// `done` has completed.
+static void completer_post(pxcl_ctx* ctx, int kind, void* obj, hipEvent_t done) {
+    pxcl_completer& c = ctx->comp;
+    bool wake;
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        c.in.push_back(Pending{kind, obj, done});
+        c.has_in.store(true, std::memory_order_release);
+        wake = c.idle;
+    }
+    if (wake) c.cv.notify_one();
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** out) {
@@ -327,13 +370,26 @@ extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** ou
     c->occ_c = occupancy_compact();
     c->occ_h = occupancy_hits();
     hipSetDevice(prev);
+    try {
+        c->comp.th = std::thread(completer_loop, &c->comp, device);
+    } catch (...) {
+        delete c;
+        return PXCL_E_INTERNAL;
+    }
     *out = c;
     return PXCL_OK;
 }
 
 extern "C" int pxcl_ctx_destroy(pxcl_ctx* ctx) {
     if (!ctx) return PXCL_E_INVAL;
-    if (ctx->bound.load() != 0) return PXCL_E_BUSY;
+    if (ctx->bound.load() != 0) return PXCL_E_BUSY;   // nothing bound, so nothing in flight
+    if (t_in_callback) return PXCL_E_BUSY;            // the callback runs on the thread to stop
+    {
+        std::lock_guard<std::mutex> g(ctx->comp.mu);
+        ctx->comp.stop = true;
+    }
+    ctx->comp.cv.notify_one();
+    if (ctx->comp.th.joinable()) ctx->comp.th.join();
     delete ctx;
     return PXCL_OK;
 }
@@ -492,8 +548,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) {
         ev->cb_pending.fetch_add(1, std::memory_order_acq_rel);
-        e = hipLaunchHostFunc(s, event_done_hostfn, ev);
-        if (e != hipSuccess) ev->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
+        completer_post(ctx, CK_EVENT, ev, ev->done_ev);
     }
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
@@ -580,7 +635,7 @@ extern "C" void pxcl_flag_cb(void* user, int32_t status) {
 // hits: a consumer of an event's clusters
 // ---------------------------------------------------------------------------
 namespace {
-void hits_done_hostfn(void* p) {
+void hits_complete(void* p) {
     pxcl_event* ev = static_cast<pxcl_event*>(p);
     // the event's work completed before the hits (stream order or the wait on its
     // completion event), so its status block is final, whether or not the event's
@@ -651,8 +706,7 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
     if (e == hipSuccess) e = hipEventRecord(ev->hits_ev, s);
     if (e == hipSuccess) {
         ev->hits_pending.fetch_add(1, std::memory_order_acq_rel);
-        e = hipLaunchHostFunc(s, hits_done_hostfn, ev);
-        if (e != hipSuccess) ev->hits_pending.fetch_sub(1, std::memory_order_acq_rel);
+        completer_post(ctx, CK_HITS, ev, ev->hits_ev);
     }
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
@@ -693,7 +747,7 @@ extern "C" int pxcl_hits_produce(pxcl_event* ev, pxcl_hits* out) {
 // copy to host on demand
 // ---------------------------------------------------------------------------
 namespace {
-void copy_done_hostfn(void* p) {
+void copy_complete(void* p) {
     pxcl_event* ev = static_cast<pxcl_event*>(p);
     volatile u32* hs = ev->hs;
     const u32 tag = __atomic_load_n(&ev->hs[HS_EPOCH], __ATOMIC_ACQUIRE);
@@ -715,6 +769,47 @@ void copy_done_hostfn(void* p) {
     ev->copy_pending.fetch_sub(1, std::memory_order_acq_rel);
 }
 }  // namespace
+
+// The completion thread: takes posted launches, queries their completion events
+// and runs the completion step of each one that has completed (an event that
+// reports an error counts as completed: the status block then shows the missing
+// write-back).  It sleeps while nothing is in flight and yields between passes.
+static void completer_loop(pxcl_completer* c, int device) {
+    hipSetDevice(device);
+    std::vector<Pending> mine;
+    for (;;) {
+        if (mine.empty() || c->has_in.load(std::memory_order_acquire)) {
+            std::unique_lock<std::mutex> lk(c->mu);
+            if (mine.empty() && c->in.empty()) {
+                if (c->stop) return;
+                c->idle = true;
+                c->cv.wait(lk, [c] { return c->stop || !c->in.empty(); });
+                c->idle = false;
+                if (c->in.empty()) return;
+            }
+            mine.insert(mine.end(), c->in.begin(), c->in.end());
+            c->in.clear();
+            c->has_in.store(false, std::memory_order_relaxed);
+        }
+        bool any = false;
+        for (size_t i = 0; i < mine.size();) {
+            const hipError_t q = hipEventQuery(mine[i].done);
+            if (q == hipErrorNotReady) { ++i; continue; }
+            if (q != hipSuccess) (void)hipGetLastError();
+            const Pending p = mine[i];
+            mine[i] = mine.back();
+            mine.pop_back();
+            switch (p.kind) {
+                case CK_EVENT: event_complete(p.obj); break;
+                case CK_BATCH: batch_complete(p.obj); break;
+                case CK_HITS: hits_complete(p.obj); break;
+                default: copy_complete(p.obj); break;
+            }
+            any = true;
+        }
+        if (!any) std::this_thread::yield();
+    }
+}
 
 extern "C" int pxcl_copy_to_host(pxcl_event* ev, void* stream, pxcl_host_clusters* dst, pxcl_done_cb cb,
                                  void* user) {
@@ -758,8 +853,7 @@ extern "C" int pxcl_copy_to_host(pxcl_event* ev, void* stream, pxcl_host_cluster
     if (e == hipSuccess) e = hipEventRecord(ev->copy_ev, s);
     if (e == hipSuccess) {
         ev->copy_pending.fetch_add(1, std::memory_order_acq_rel);
-        e = hipLaunchHostFunc(s, copy_done_hostfn, ev);
-        if (e != hipSuccess) ev->copy_pending.fetch_sub(1, std::memory_order_acq_rel);
+        completer_post(ctx, CK_COPY, ev, ev->copy_ev);
     }
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
@@ -970,9 +1064,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     if (e == hipSuccess) e = hipEventRecord(b->done_ev, s);
     if (e == hipSuccess) {
         for (u32 i = 0; i < k; ++i) evs[i]->cb_pending.fetch_add(1, std::memory_order_acq_rel);
-        e = hipLaunchHostFunc(s, batch_done_hostfn, b);
-        if (e != hipSuccess)
-            for (u32 i = 0; i < k; ++i) evs[i]->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
+        completer_post(ctx, CK_BATCH, b, b->done_ev);
     }
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
