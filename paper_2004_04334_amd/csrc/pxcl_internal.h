@@ -31,7 +31,7 @@ constexpr u32 A_WG = 256;                                   // segmentation: ids
 constexpr u32 A_PER_N = 8, A_PER_W = 32;                    // narrow chunks for launches that
                                                             // cannot fill the device, wide ones
                                                             // (fewer end-of-chunk atomics) else
-constexpr u32 C_WG = 256, C_ITEMS = 8;                      // compaction: items per workgroup
+constexpr u32 C_WG = 256;                                   // compaction: a wave per module
 constexpr u32 K_SMALL = 8;                                  // digis per thread (small-module kernel)
 constexpr u32 B_WG = 512, K_BIG = 32;                       // big-module kernel
 constexpr u32 BIG_RCAP = B_WG * K_BIG;                      // 16384: larger modules use scratch mode
@@ -39,18 +39,17 @@ constexpr u32 BIG_RCAP = B_WG * K_BIG;                      // 16384: larger mod
 // Per-event control words (u32) at the start of an event workspace.
 enum : u32 {
     CTL_ERR = 0,      // accumulated PXCL_ERRBIT_* of the launch in progress
-    CTL_ITEMS = 1,    // number of modules present (work items)
     CTL_NCL = 2,      // kept clusters
-    CTL_SMALL = 3,    // items for the small-module kernel
-    CTL_BIG = 4,      // items for the big-module kernel
-    CTL_SEGDONE = 5,  // segmentation chunks finished (the last one indexes the event)
+    CTL_BIG = 4,      // modules on the big-module list
+    CTL_PRESENT = 5,  // words 5-6: modules on the present-module list, one count per
+                      // launch parity (EventDesc::slot); a launch clears the other one
     CTL_CTR = 8,      // launch counters when the event is launched on its own
     CTL_WORDS = 64
 };
 // Launch counters: the small-module kernel's ticket.
 enum : u32 { S_TICK = 0, N_CTR = 8 };
 // Host status block (pinned) written by the compaction kernel.
-enum : u32 { HS_EPOCH = 0, HS_ERR = 1, HS_NCL = 2, HS_ITEMS = 3, HS_BIG = 4, HS_WORDS = 16 };
+enum : u32 { HS_EPOCH = 0, HS_ERR = 1, HS_NCL = 2, HS_WORDS = 16 };
 constexpr u32 HS_BYTES = HS_WORDS * 4;
 
 // Error bits (same values as PXCL_ERRBIT_*).
@@ -71,14 +70,16 @@ struct EventDesc {
     u32* hstat;      // host status block (pinned, device-accessible)
     u32 n;           // digis
     u32 cap;         // workspace capacity in digis
-    u32 epoch;       // launch tag of the segment words
-    u32 pad;
+    u32 epoch;       // launch tag of the module-table words
+    u32 slot;        // launch parity: which present-module count this launch uses
 };
 static_assert(sizeof(EventDesc) == 64, "EventDesc is 64 bytes");
 
-// A work-list entry: item index (module order), first digi, digis, module id.
-struct ItemEntry {
-    u32 it, st, n, mod;
+// A module's digis [first, end), each word tagged with the launch (epoch << 32):
+// written by the digis at the module's boundaries, so an entry whose tags are not
+// the current launch's belongs to an absent module and needs no clearing.
+struct ModRange {
+    u64 first, end;
 };
 
 // Batch header in device memory: u32 k, padding to 64 bytes, then EventDesc[k].
@@ -103,10 +104,11 @@ struct EvLayout {
     size_t ctl, in_mod, in_row, in_col, in_adc;
     size_t digi, id, charge, size;           // outputs
     size_t tid, tcharge, tsize;              // cluster records before compaction
-    size_t seg;                              // per module: launch tag << 32 | first digi
-    size_t item_start, item_kept;            // modules present (work items), in module order
-    size_t small, big;                       // work lists of the two clustering kernels (ItemEntry)
-    size_t item_off;                         // per item: its first cluster in the outputs
+    size_t mtab;                             // per module: ModRange
+    size_t kept;                             // per module: kept clusters
+    size_t big;                              // module ids for the big-module kernel
+    size_t present;                          // module ids of the modules present (any order)
+    size_t off;                              // per module: its first cluster in the outputs
     size_t hit_x, hit_y;                     // hits (per kept cluster), when asked for
     size_t total;
 };
@@ -127,12 +129,11 @@ PXCL_HD inline EvLayout ev_layout(u32 N, u32 M) {
     L.tid = o;        o = al256(o + 4 * n);
     L.tcharge = o;    o = al256(o + 4 * n);
     L.tsize = o;      o = al256(o + 4 * n);
-    L.seg = o;        o = al256(o + 8 * m);
-    L.item_start = o; o = al256(o + 4 * (m + 1));
-    L.item_kept = o;  o = al256(o + 4 * m);
-    L.small = o;      o = al256(o + 16 * m);
-    L.big = o;        o = al256(o + 16 * m);
-    L.item_off = o;   o = al256(o + 4 * m);
+    L.mtab = o;       o = al256(o + 16 * m);
+    L.kept = o;       o = al256(o + 4 * m);
+    L.big = o;        o = al256(o + 4 * m);
+    L.present = o;    o = al256(o + 4 * m);
+    L.off = o;        o = al256(o + 4 * m);
     L.hit_x = o;      o = al256(o + 4 * n);
     L.hit_y = o;      o = al256(o + 4 * n);
     L.total = o;

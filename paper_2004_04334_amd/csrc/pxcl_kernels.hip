@@ -138,12 +138,37 @@ __device__ __forceinline__ u32 find_slot(const u32* pref, u32 k, u32 t) {
     return lo;
 }
 
-// Prefix over the events of a launch of max(ceil(count / div), at_least), where
-// count is the event's digis (which = 0) or one of its control words (which =
-// CTL_*; 0 for an empty event).  pref[k] = total.  Every thread of the workgroup
-// calls it; any k <= MAXB with any BS.
+// What event_prefix counts per event.
+constexpr u32 CNT_DIGIS = 0, CNT_MODULES = 0xFFFFFFFFu, CNT_UNITS = 0xFFFFFFFEu;
+
+// Modules on the event's present-module list.
+__device__ __forceinline__ u32 present_count(const LaunchArgs& a, const EventDesc& E) {
+    return min(ld_ag(ws_ptr<const u32>(E, ev_layout(E.cap, a.n_modules).ctl) + CTL_PRESENT + (E.slot & 1u)), a.n_modules);
+}
+
+// Work units of the kernels after segmentation: when most modules are present, every
+// module (unit j is module j; an absent one is recognised by its table entry), else
+// the present-module list (unit j is its entry j, one more load away).
+__device__ __forceinline__ bool dense_units(const LaunchArgs& a, u32 present) { return 2 * present > a.n_modules; }
+__device__ __forceinline__ u32 unit_count(const LaunchArgs& a, const EventDesc& E) {
+    if (!E.n) return 0u;
+    const u32 p = present_count(a, E);
+    return dense_units(a, p) ? a.n_modules : p;
+}
+__device__ __forceinline__ u32 unit_module(const LaunchArgs& a, const EventDesc& E, const EvLayout& L, u32 units,
+                                           u32 j) {
+    if (units == a.n_modules) return j;         // dense (a list as long as the module count is all of them)
+    return min(ws_ptr<const u32>(E, L.present)[j], a.n_modules - 1);
+}
+
+// Prefix over the events of a launch of max(ceil(count / div), at_least) + plus,
+// where count is the event's digis (CNT_DIGIS), the modules per event
+// (CNT_MODULES), its work units (CNT_UNITS) or one of its control words (CTL_*, at
+// most the modules per event); 0 for an empty event.  pref[k] = total.
+// Every thread of the workgroup calls it; any k <= MAXB with any BS.
 template <u32 BS>
-__device__ __forceinline__ u32 event_prefix(const LaunchArgs& a, u32 k, u32* pref, u32* wsum, u32 which, u32 div, u32 at_least) {
+__device__ __forceinline__ u32 event_prefix(const LaunchArgs& a, u32 k, u32* pref, u32* wsum, u32 which, u32 div,
+                                            u32 at_least, u32 plus = 0) {
     u32 carry = 0;
     for (u32 base = 0; base < k; base += BS) {
         const u32 e = base + threadIdx.x;
@@ -151,8 +176,12 @@ __device__ __forceinline__ u32 event_prefix(const LaunchArgs& a, u32 k, u32* pre
         if (e < k) {
             const EventDesc E = get_event(a, e);
             u32 cnt = 0;
-            if (E.n) cnt = which ? ld_ag(ws_ptr<u32>(E, ev_layout(E.cap, a.n_modules).ctl) + which) : E.n;
-            v = max((cnt + div - 1) / div, at_least);
+            if (E.n)
+                cnt = which == CNT_DIGIS     ? E.n
+                      : which == CNT_MODULES ? a.n_modules
+                      : which == CNT_UNITS   ? unit_count(a, E)
+                                             : min(ld_ag(ws_ptr<u32>(E, ev_layout(E.cap, a.n_modules).ctl) + which), a.n_modules);
+            v = max((cnt + div - 1) / div, at_least) + plus;
         }
         u32 tot;
         const u32 ex = group_excl_scan<BS>(v, threadIdx.x, wsum, tot);
@@ -230,120 +259,22 @@ __device__ __forceinline__ void link_right(u32* par, const u32* bm, const u16* r
 }
 
 // ---------------------------------------------------------------------------
-// segment
+// segment: every digi at a module boundary writes the module's entry of the module
+// table (first digi, one past the last), tagged with the launch, and the digi that
+// starts a module appends it to the present-module list (one atomic per chunk for
+// the chunk's place in it); module ids must be non-decreasing (else EB_ORDER) and
+// below the module count (else EB_RANGE).  The first chunk of an event also clears
+// its kept counts (an absent module keeps nothing) and empties its big-module list.
 // ---------------------------------------------------------------------------
-constexpr u32 IDX_PER = 8, IDX_SPAN = A_WG * IDX_PER;   // modules per thread / per pass
-constexpr u32 NONE = 0xFFFFFFFFu;
-
-// Turn the event's per-module first digi (first(m): the first digi of module m, or
-// NONE if absent) into the ordered item list and the two work lists.  Run by one
-// whole workgroup of WGS threads, PER modules per thread and pass; s_st holds
-// WGS*PER + 1 words, s_cnt WGS*PER.
-template <u32 WGS, u32 PER, typename First>
-__device__ __forceinline__ void index_event(const LaunchArgs& a, const EventDesc& E, const EvLayout& L,
-                                            u32* wsum, u32* s_st, u32* s_cnt, First first) {
-    constexpr u32 SPAN = WGS * PER;
-    const u32 tid = threadIdx.x;
-    const u32 M = a.n_modules, n = E.n;
-    u32* item_start = ws_ptr<u32>(E, L.item_start);
-    u32* item_kept = ws_ptr<u32>(E, L.item_kept);
-    u32* ctl = ws_ptr<u32>(E, L.ctl);
-    ItemEntry* small = ws_ptr<ItemEntry>(E, L.small);
-    ItemEntry* big = ws_ptr<ItemEntry>(E, L.big);
-    const bool one_pass = M <= SPAN;
-    // pass 1: modules present, in module order (one load round per SPAN modules)
-    u32 items = 0;
-    for (u32 base = 0; base < M; base += SPAN) {
-        u32 v[PER];
-#pragma unroll
-        for (u32 j = 0; j < PER; ++j) {
-            const u32 m = base + tid * PER + j;
-            v[j] = m < M ? first(m) : NONE;
-        }
-        u32 flags = 0;
-#pragma unroll
-        for (u32 j = 0; j < PER; ++j)
-            if (v[j] != NONE) flags |= 1u << j;
-        u32 tot;
-        u32 r = items + group_excl_scan<WGS>(__popc(flags), tid, wsum, tot);
-#pragma unroll
-        for (u32 j = 0; j < PER; ++j)
-            if (flags & (1u << j)) {
-                const u32 st = min(v[j], n);
-                st_ag(&item_start[r], st);
-                if (one_pass) {
-                    s_st[r] = st;
-                    s_cnt[r] = base + tid * PER + j;   // module id
-                }
-                ++r;
-            }
-        items += tot;
-    }
-    if (tid == 0) {
-        st_ag(&item_start[items], n);
-        st_ag(&ctl[CTL_ITEMS], items);
-        if (one_pass) s_st[items] = n;
-    }
-    wait_all_mem();
-    lds_barrier();
-    // pass 2: split into small and big modules, PER consecutive items per thread
-    // (one round for up to SPAN items).  A module whose start does not increase
-    // (module ids out of order, already flagged) gets no entry.
-    u32 ns = 0, nb = 0;
-    for (u32 base = 0; base < items; base += SPAN) {
-        const u32 i0 = base + tid * PER;
-        u32 st[PER + 1], md[PER];
-#pragma unroll
-        for (u32 j = 0; j <= PER; ++j) {
-            const u32 i = min(i0 + j, items);
-            st[j] = one_pass ? s_st[i] : ld_ag(&item_start[i]);
-            if (j < PER) md[j] = (one_pass && i < items) ? s_cnt[i] : NONE;
-        }
-        u32 cls = 0, cnt = 0;                  // 2 bits per item: 1 small, 2 big
-#pragma unroll
-        for (u32 j = 0; j < PER; ++j)
-            if (i0 + j < items) item_kept[i0 + j] = 0u;   // a module left unclustered keeps nothing
-#pragma unroll
-        for (u32 j = 0; j < PER; ++j)
-            if (i0 + j < items && st[j + 1] > st[j]) {
-                const u32 c = (st[j + 1] - st[j] <= a.dcap) ? 1u : 2u;
-                cls |= c << (2 * j);
-                cnt += (c == 1) ? 1u : (1u << 16);
-            }
-        u32 tot;
-        const u32 ex = group_excl_scan<WGS>(cnt, tid, wsum, tot);
-        u32 ps = ns + (ex & 0xFFFFu), pb = nb + (ex >> 16);
-#pragma unroll
-        for (u32 j = 0; j < PER; ++j) {
-            const u32 c = (cls >> (2 * j)) & 3u;
-            if (c) {
-                const u32 m = md[j] != NONE ? md[j] : E.module[st[j]];   // else from its first digi
-                const ItemEntry ent{i0 + j, st[j], st[j + 1] - st[j], m};
-                if (c == 1) small[ps++] = ent;
-                else big[pb++] = ent;
-            }
-        }
-        ns += tot & 0xFFFFu;
-        nb += tot >> 16;
-    }
-    if (tid == 0) {
-        ctl[CTL_SMALL] = ns;
-        ctl[CTL_BIG] = nb;
-        if (nb && (a.flags & LF_NO_BIG)) atomicOr(&ctl[CTL_ERR], EB_HINT);   // left unclustered
-    }
-}
-
 template <u32 PER>
 __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
     constexpr u32 CH = A_WG * PER;
     __shared__ u32 s_pref[MAXB + 1];
     __shared__ u32 s_wsum[A_WG / 64];
-    __shared__ u32 s_st[IDX_SPAN + 1];
-    __shared__ u32 s_md[IDX_SPAN];
-    __shared__ u32 s_err, s_last;
+    __shared__ u32 s_err, s_base;
     const u32 tid = threadIdx.x;
     const u32 k = num_events(a);
-    const u32 total = event_prefix<A_WG>(a, k, s_pref, s_wsum, 0, CH, 0);
+    const u32 total = event_prefix<A_WG>(a, k, s_pref, s_wsum, CNT_DIGIS, CH, 0);
 
     for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
         if (tid == 0) s_err = 0;
@@ -351,7 +282,7 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
         const u32 c = t - s_pref[e];
         const EventDesc E = get_event(a, e);
         const EvLayout L = ev_layout(E.cap, a.n_modules);
-        u64* seg = ws_ptr<u64>(E, L.seg);
+        ModRange* mt = ws_ptr<ModRange>(E, L.mtab);
         const u32 n = E.n;
         const u32 i0 = c * CH + tid * PER;
         u32 m[PER];
@@ -370,38 +301,54 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
             for (u32 j = 0; j < PER; ++j) m[j] = E.module[min(i0 + j, n - 1)];
         }
         const u32 prev = E.module[i0 > 0 ? min(i0 - 1, n - 1) : 0];
-        lds_barrier();                           // s_err cleared
-        u32 err = 0;
+        const u32 next = E.module[min(i0 + PER, n - 1)];
+        u32* ctl = ws_ptr<u32>(E, L.ctl);
+        const u32 slot = E.slot & 1u;
+        if (c == 0) {                            // read by the kernels after this one
+            if (tid == 0) {
+                ctl[CTL_BIG] = 0u;
+                ctl[CTL_PRESENT + (slot ^ 1u)] = 0u;   // for the next launch (the last one's is done)
+            }
+            u32* kept = ws_ptr<u32>(E, L.kept);
+            for (u32 q = tid; q < a.n_modules; q += A_WG) kept[q] = 0u;
+        }
+        u32 err = 0, starts = 0;
         const u64 tag = u64(E.epoch) << 32;
 #pragma unroll
         for (u32 j = 0; j < PER; ++j) {
             const u32 i = i0 + j;
             if (i < n) {
                 const u32 pm = (j == 0) ? prev : m[j - 1];
+                const u32 nm = (j + 1 == PER) ? next : m[j + 1];
                 if (i > 0 && m[j] < pm) err |= EB_ORDER;
-                if (m[j] >= a.n_modules) err |= EB_RANGE;
-                else if (i == 0 || m[j] != pm) st_ag64(&seg[m[j]], tag | i);
+                if (m[j] >= a.n_modules) {
+                    err |= EB_RANGE;
+                } else {
+                    if (i == 0 || m[j] != pm) {
+                        mt[m[j]].first = tag | i;
+                        starts |= 1u << j;
+                    }
+                    if (i + 1 == n || m[j] != nm) mt[m[j]].end = tag | (i + 1);
+                }
             }
         }
+        u32 nstart;
+        const u32 ex = group_excl_scan<A_WG>(__popc(starts), tid, s_wsum, nstart);   // also orders s_err
+        if (tid == 0) s_base = nstart ? atomicAdd(&ctl[CTL_PRESENT + slot], nstart) : 0u;
+        lds_barrier();
+        u32* present = ws_ptr<u32>(E, L.present);
+        u32 r = s_base + ex;
+#pragma unroll
+        for (u32 j = 0; j < PER; ++j)
+            if (starts & (1u << j)) {
+                if (r < a.n_modules) present[r] = m[j];
+                else err |= EB_INTERNAL;         // a count left by a launch that did not finish
+                ++r;
+            }
         if (err) atomicOr(&s_err, err);
-        wait_all_mem();                          // this thread's table entries are visible
         lds_barrier();
-        const u32 chunks = (n + CH - 1) / CH;
-        if (tid == 0) {
-            u32* ctl = ws_ptr<u32>(E, L.ctl);
-            if (s_err) atomicOr(&ctl[CTL_ERR], s_err);
-            s_last = (atomicAdd(&ctl[CTL_SEGDONE], 1u) == chunks - 1) ? 1u : 0u;
-        }
-        lds_barrier();
-        if (s_last) {
-            const u64* seg_c = seg;
-            index_event<A_WG, IDX_PER>(a, E, L, s_wsum, s_st, s_md, [&](u32 m) {
-                const u64 v = ld_ag64(&seg_c[m]);
-                return u32(v >> 32) == E.epoch ? u32(v) : NONE;
-            });
-            if (tid == 0) st_ag(ws_ptr<u32>(E, L.ctl) + CTL_SEGDONE, 0u);
-        }
-        lds_barrier();
+        if (tid == 0 && s_err) atomicOr(&ctl[CTL_ERR], s_err);
+        lds_barrier();                           // before s_err is cleared for the next chunk
     }
 }
 
@@ -638,7 +585,7 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
                 }
                 gp.acc[r] = u64(id);
             }
-        if (lt == 0) ws_ptr<u32>(E, L.item_kept)[I.it] = Kc;
+        if (lt == 0) ws_ptr<u32>(E, L.kept)[I.it] = Kc;
     }
     mid(3);
     gsync<G>();
@@ -687,21 +634,52 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     u32 total;
     if (k == 1) {                             // one event, alone or in a header
         const EventDesc E0 = get_event(a, 0);
-        total = E0.n ? ld_ag(ws_ptr<u32>(E0, ev_layout(E0.cap, a.n_modules).ctl) + CTL_SMALL) : 0u;
-        if (tid == 0) s.pref[0] = 0;
+        total = unit_count(a, E0);
+        if (tid == 0) {
+            s.pref[0] = 0;
+            s.pref[1] = total;
+        }
         lds_barrier();
     } else {
-        total = event_prefix<WG>(a, k, s.pref, s.wsum, CTL_SMALL, 1, 0);
+        total = event_prefix<WG>(a, k, s.pref, s.wsum, CNT_UNITS, 1, 0);
     }
-    auto entry_of = [&](u32 t, EventDesc& Ev, u32& e) -> const ItemEntry* {
+    // Work unit t: unit t - pref[e] of event e.
+    auto entry_of = [&](u32 t, EventDesc& Ev, u32& e, u32& mod) -> const ModRange* {
         e = k == 1 ? 0u : find_slot(s.pref, k, t);
         Ev = get_event(a, e);
-        return ws_ptr<const ItemEntry>(Ev, ev_layout(Ev.cap, a.n_modules).small) + (t - s.pref[e]);
+        const EvLayout L = ev_layout(Ev.cap, a.n_modules);
+        mod = unit_module(a, Ev, L, s.pref[e + 1] - s.pref[e], t - s.pref[e]);
+        return ws_ptr<const ModRange>(Ev, L.mtab) + mod;
     };
-    auto make_item = [&](const ItemEntry& ent, const EventDesc& Ev, u32 e, bool valid) {
-        Item I{e, ent.it, ent.st, ent.n, ent.mod, false};
-        I.ok = valid && I.n > 0 && I.st + I.n <= Ev.n && I.n <= G * K && I.mod < a.n_modules;
+    // I.n = 0 for an entry that is not this launch's (or inconsistent after an
+    // ordering error); ok only for a present module the group can hold.
+    auto make_item = [&](const ModRange& r, const EventDesc& Ev, u32 e, u32 mod, bool valid) {
+        Item I{e, mod, 0, 0, mod, false};
+        if (valid && u32(r.first >> 32) == Ev.epoch && u32(r.end >> 32) == Ev.epoch) {
+            const u32 st = u32(r.first), en = u32(r.end);
+            if (st < en && en <= Ev.n) {
+                I.st = st;
+                I.n = en - st;
+            }
+        }
+        I.ok = I.n > 0 && I.n <= G * K;
         return I;
+    };
+    // A module larger than the group goes to the big-module list (or, when that
+    // kernel is not launched, keeps nothing and flags the size hint).  Other units
+    // not clustered (entries not of this launch) need nothing: segmentation cleared
+    // the kept counts.
+    auto skip = [&](const EventDesc& Ev, const Item& Is) {
+        if (Is.n <= G * K) return;
+        const EvLayout L = ev_layout(Ev.cap, a.n_modules);
+        u32* ctl = ws_ptr<u32>(Ev, L.ctl);
+        if (!(a.flags & LF_NO_BIG)) {
+            const u32 r = atomicAdd(&ctl[CTL_BIG], 1u);
+            if (r < a.n_modules) ws_ptr<u32>(Ev, L.big)[r] = Is.mod;
+            else atomicOr(&ctl[CTL_ERR], EB_INTERNAL);
+        } else {
+            atomicOr(&ctl[CTL_ERR], EB_HINT);
+        }
     };
 
     // Modules are assigned statically in rounds (round r: module r*per_round + the
@@ -717,9 +695,9 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     {
         const u32 t = base + gofs;
         if (t < total) {
-            u32 e;
-            const ItemEntry ent = *entry_of(t, E, e);
-            I = make_item(ent, E, e, true);
+            u32 e, mod;
+            const ModRange r = *entry_of(t, E, e, mod);
+            I = make_item(r, E, e, mod, true);
         }
         I = wave_uniform(I);                      // one module per wave (or per group of waves)
         E = wave_uniform(E);
@@ -733,16 +711,16 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     if (dyn && nrounds == 1 && ((WAVE && lt == 0) || (!WAVE && tid == 0))) nv = atomicAdd(&a.ctr[S_TICK], STEP) + nstatic;
 
     while (base < total) {
-        u32 nbase = total, nv2 = 0, ne = 0;
+        u32 nbase = total, nv2 = 0, ne = 0, nmod = 0;
         EventDesc En{};
-        const ItemEntry* pent = nullptr;
-        ItemEntry ent{0, 0, 0, 0};
+        const ModRange* pent = nullptr;
+        ModRange ent{0, 0};
         Item In{0, 0, 0, 0, 0, false};
         u32 NR[K], NC[K], NA[K];
         auto issue_entry = [&]() {
             const u32 t = nbase + gofs;
             if (t < total) {
-                pent = entry_of(t, En, ne);
+                pent = entry_of(t, En, ne, nmod);
                 ent = *pent;                      // load issued; used at stage 2
             }
         };
@@ -766,13 +744,12 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
                     issue_entry();
                 }
             } else if (stage == 2) {
-                In = wave_uniform(make_item(ent, En, ne, pent != nullptr));
+                In = wave_uniform(make_item(ent, En, ne, nmod, pent != nullptr));
                 En = wave_uniform(En);
                 if (In.ok) fetch_digis<G, K>(En, In, lt, NR, NC, NA);
             }
         };
-        if (base + gofs < total && !I.ok && lt == 0)
-            atomicOr(ws_ptr<u32>(E, ev_layout(E.cap, a.n_modules).ctl) + CTL_ERR, EB_INTERNAL);
+        if (base + gofs < total && !I.ok && lt == 0) skip(E, I);
         if (!WAVE || I.ok) {
             const EvLayout L = ev_layout(E.cap, a.n_modules);
             cluster_regs<G, K>(a, E, L, I, gp, lt, R, C, A, mid);
@@ -1075,7 +1052,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
                 }
             }
         }
-        if (tid == 0) ws_ptr<u32>(E, L.item_kept)[I.it] = Kc;
+        if (tid == 0) ws_ptr<u32>(E, L.kept)[I.it] = Kc;
     }
     wait_all_mem();
     lds_barrier();
@@ -1131,12 +1108,16 @@ __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
         I.e = find_slot(s_pref, k, t);
         const EventDesc E = get_event(a, I.e);
         const EvLayout L = ev_layout(E.cap, a.n_modules);
-        const ItemEntry ent = ws_ptr<const ItemEntry>(E, L.big)[t - s_pref[I.e]];
-        I.it = ent.it;
-        I.st = ent.st;
-        I.n = ent.n;
-        I.mod = ent.mod;
-        I.ok = I.n > 0 && I.st + I.n <= E.n && I.mod < a.n_modules;
+        I.mod = I.it = ws_ptr<const u32>(E, L.big)[t - s_pref[I.e]];
+        if (I.mod < a.n_modules) {
+            const ModRange r = ws_ptr<const ModRange>(E, L.mtab)[I.mod];
+            const u32 st = u32(r.first), en = u32(r.end);
+            if (u32(r.first >> 32) == E.epoch && u32(r.end >> 32) == E.epoch && st < en && en <= E.n) {
+                I.st = st;
+                I.n = en - st;
+                I.ok = I.n > a.dcap;                   // listed by the small kernel as too large for it
+            }
+        }
         if (!I.ok) {
             if (tid == 0) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, EB_INTERNAL);
             continue;
@@ -1154,102 +1135,89 @@ __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// compact: per event, chunks of C_ITEMS modules; a chunk's offset is the sum of the
-// kept counts of all earlier modules; each wave copies the records of C_ITEMS/4
-// modules, CP_UNR records per lane at a time
+// compact: one wave per work unit (module) and one per event for its status.  A
+// module's first output position is the sum of the kept counts of all modules before
+// it (PS_UNR loads per lane in flight); the wave copies the module's records, CP_UNR
+// per lane at a time.
 // ---------------------------------------------------------------------------
-constexpr u32 CP_UNR = 4, SUM_UNR = 8;
+constexpr u32 CP_UNR = 4, PS_UNR = 32, C_WAVES = C_WG / 64;
+
+// Sum of kept[0, end) over the wave.
+__device__ __forceinline__ u32 kept_before(const u32* kept, u32 end, u32 lane) {
+    u32 part = 0;
+    for (u32 b = 0; b < end; b += 64 * PS_UNR) {
+        u32 v[PS_UNR];
+#pragma unroll
+        for (u32 q = 0; q < PS_UNR; ++q) {
+            const u32 i = b + q * 64 + lane;
+            v[q] = i < end ? kept[i] : 0u;
+        }
+#pragma unroll
+        for (u32 q = 0; q < PS_UNR; ++q) part += v[q];
+    }
+    return __shfl(wave_incl_scan(part), 63, 64);
+}
 
 __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
     __shared__ u32 s_pref[MAXB + 1];
     __shared__ u32 s_wsum[C_WG / 64];
-    __shared__ u32 s_off[C_ITEMS + 1];
-    __shared__ u32 s_src[C_ITEMS];
-    __shared__ u32 s_red[C_WG / 64];
     const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const u32 k = num_events(a);
+    const u32 k = num_events(a), M = a.n_modules;
     if (blockIdx.x == 0 && tid == 0) st_ag(&a.ctr[S_TICK], 0u);   // the small kernel has finished
-    const u32 total = event_prefix<C_WG>(a, k, s_pref, s_wsum, CTL_ITEMS, C_ITEMS, 1);
-    for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
-        const u32 e = find_slot(s_pref, k, t);
-        const u32 c = t - s_pref[e];
-        const EventDesc E = get_event(a, e);
-        const EvLayout L = ev_layout(E.cap, a.n_modules);
+    const u32 total = event_prefix<C_WG>(a, k, s_pref, s_wsum, CNT_UNITS, 1, 0, 1);   // + status unit
+    for (u32 u = wave_uniform(blockIdx.x * C_WAVES + wv); u < total; u += gridDim.x * C_WAVES) {
+        const u32 e = wave_uniform(find_slot(s_pref, k, u));
+        const u32 j = u - s_pref[e], np = s_pref[e + 1] - s_pref[e] - 1;
+        const EventDesc E = wave_uniform(get_event(a, e));
+        const EvLayout L = ev_layout(E.cap, M);
         u32* ctl = ws_ptr<u32>(E, L.ctl);
-        const u32 items = E.n ? ctl[CTL_ITEMS] : 0u;
-        const u32* kept = ws_ptr<const u32>(E, L.item_kept);
-        const u32* item_start = ws_ptr<const u32>(E, L.item_start);
-        const u32 i0 = c * C_ITEMS, i1 = min(i0 + C_ITEMS, items);
-        u32 part = 0;                                      // kept clusters of items [0, i0)
-        for (u32 b = 0; b < i0; b += C_WG * SUM_UNR) {
-            u32 v[SUM_UNR];
-#pragma unroll
-            for (u32 u = 0; u < SUM_UNR; ++u) {
-                const u32 i = b + u * C_WG + tid;
-                v[u] = i < i0 ? kept[i] : 0u;
+        const u32* kept = ws_ptr<const u32>(E, L.kept);
+        if (j == np) {                                     // the event's status
+            const u32 ncl = E.n ? min(kept_before(kept, M, lane), E.n) : 0u;
+            if (lane == 0) {
+                const u32 err = ctl[CTL_ERR];
+                ctl[CTL_ERR] = 0u;
+                ctl[CTL_NCL] = ncl;
+                u32* hs = E.hstat;
+                st_sys(&hs[HS_ERR], err);
+                st_sys(&hs[HS_NCL], ncl);
+                st_sys(&hs[HS_EPOCH], E.epoch);
             }
-#pragma unroll
-            for (u32 u = 0; u < SUM_UNR; ++u) part += v[u];
+            continue;
         }
-        const u32 wtot = __shfl(wave_incl_scan(part), 63, 64);
-        if (lane == 0) s_red[wv] = wtot;
-        const bool mine = tid < C_ITEMS && i0 + tid < i1;
-        const u32 v = mine ? kept[i0 + tid] : 0u;
-        if (tid < C_ITEMS) s_src[tid] = mine ? item_start[i0 + tid] : 0u;
-        const u32 inc = wave_incl_scan(v);                 // offsets inside the chunk (wave 0)
-        lds_barrier();
-        u32 before = 0;
-#pragma unroll
-        for (u32 w = 0; w < C_WG / 64; ++w) before += s_red[w];
-        if (tid < C_ITEMS) s_off[tid] = before + inc - v;
-        if (tid == C_ITEMS - 1) s_off[C_ITEMS] = before + inc;
-        lds_barrier();
+        const u32 m = wave_uniform(unit_module(a, E, L, np, j));
+        const u32 cnt = wave_uniform(kept[m]);
+        if (cnt == 0) continue;                            // absent, or nothing kept
+        const u32 off = wave_uniform(kept_before(kept, m, lane));
+        const u32 src = wave_uniform(u32(ws_ptr<const ModRange>(E, L.mtab)[m].first));
+        if (lane == 0) ws_ptr<u32>(E, L.off)[m] = off;
+        if (cnt > E.n || off > E.n - cnt || src > E.n - cnt) continue;   // inconsistent (flagged)
         const int32_t* tid_ = ws_ptr<const int32_t>(E, L.tid);
         const int32_t* tch = ws_ptr<const int32_t>(E, L.tcharge);
         const int32_t* tsz = ws_ptr<const int32_t>(E, L.tsize);
         int32_t* oid = ws_ptr<int32_t>(E, L.id);
         int32_t* och = ws_ptr<int32_t>(E, L.charge);
         int32_t* osz = ws_ptr<int32_t>(E, L.size);
-        u32* item_off = ws_ptr<u32>(E, L.item_off);
-        for (u32 x = i0 + wv; x < i1; x += C_WG / 64) {
-            const u32 off = s_off[x - i0], cnt = s_off[x - i0 + 1] - off;
-            const u32 src = s_src[x - i0];
-            if (lane == 0) item_off[x] = off;
-            if (cnt > E.n || off > E.n - cnt || src > E.n - cnt) continue;   // inconsistent (flagged)
-            for (u32 j0 = 0; j0 < cnt; j0 += 64 * CP_UNR) {
-                int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
+        for (u32 j0 = 0; j0 < cnt; j0 += 64 * CP_UNR) {
+            int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
 #pragma unroll
-                for (u32 u = 0; u < CP_UNR; ++u) {
-                    const u32 j = j0 + u * 64 + lane;
-                    const u32 jj = j < cnt ? j : 0u;
-                    r0[u] = tid_[src + jj];
-                    r1[u] = tch[src + jj];
-                    r2[u] = tsz[src + jj];
-                }
+            for (u32 q = 0; q < CP_UNR; ++q) {
+                const u32 jj = j0 + q * 64 + lane;
+                const u32 js = jj < cnt ? jj : 0u;
+                r0[q] = tid_[src + js];
+                r1[q] = tch[src + js];
+                r2[q] = tsz[src + js];
+            }
 #pragma unroll
-                for (u32 u = 0; u < CP_UNR; ++u) {
-                    const u32 j = j0 + u * 64 + lane;
-                    if (j < cnt) {
-                        oid[off + j] = r0[u];
-                        och[off + j] = r1[u];
-                        osz[off + j] = r2[u];
-                    }
+            for (u32 q = 0; q < CP_UNR; ++q) {
+                const u32 jj = j0 + q * 64 + lane;
+                if (jj < cnt) {
+                    oid[off + jj] = r0[q];
+                    och[off + jj] = r1[q];
+                    osz[off + jj] = r2[q];
                 }
             }
         }
-        if (i1 >= items && tid == 0) {                     // the event's last chunk: status
-            const u32 ncl = items ? min(s_off[i1 - i0], E.n) : 0u;
-            const u32 err = ctl[CTL_ERR];
-            ctl[CTL_ERR] = 0u;
-            ctl[CTL_NCL] = ncl;
-            u32* hs = E.hstat;
-            st_sys(&hs[HS_ERR], err);
-            st_sys(&hs[HS_NCL], ncl);
-            st_sys(&hs[HS_ITEMS], items);
-            st_sys(&hs[HS_BIG], E.n ? ctl[CTL_BIG] : 0u);
-            st_sys(&hs[HS_EPOCH], E.epoch);
-        }
-        lds_barrier();
     }
 }
 
@@ -1270,17 +1238,18 @@ __global__ __launch_bounds__(H_WG) void k_hits(LaunchArgs a) {
     __shared__ u64 s_sx[H_CAP], s_sy[H_CAP];
     const u32 tid = threadIdx.x;
     const u32 k = num_events(a);
-    const u32 total = event_prefix<H_WG>(a, k, s_pref, s_wsum, CTL_ITEMS, 1, 0);
+    const u32 total = event_prefix<H_WG>(a, k, s_pref, s_wsum, CNT_UNITS, 1, 0);
     for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
         const u32 e = find_slot(s_pref, k, t);
-        const u32 it = t - s_pref[e];
         const EventDesc E = get_event(a, e);
         const EvLayout L = ev_layout(E.cap, a.n_modules);
-        const u32 st = ws_ptr<const u32>(E, L.item_start)[it];
-        const u32 nd = ws_ptr<const u32>(E, L.item_start)[it + 1] - st;
-        const u32 cnt = ws_ptr<const u32>(E, L.item_kept)[it];
-        const u32 off = ws_ptr<const u32>(E, L.item_off)[it];
-        if (cnt == 0 || cnt > E.n || off > E.n - cnt || st > E.n || nd > E.n - st) continue;
+        const u32 mod = unit_module(a, E, L, s_pref[e + 1] - s_pref[e], t - s_pref[e]);
+        const u32 cnt = ws_ptr<const u32>(E, L.kept)[mod];
+        if (cnt == 0) continue;                            // absent, or nothing kept
+        const ModRange r = ws_ptr<const ModRange>(E, L.mtab)[mod];
+        const u32 st = u32(r.first), nd = u32(r.end) - st;
+        const u32 off = ws_ptr<const u32>(E, L.off)[mod];
+        if (cnt > E.n || off > E.n - cnt || st > E.n || nd > E.n - st) continue;
         const int32_t* ids = ws_ptr<const int32_t>(E, L.id) + off;
         const int32_t* chg = ws_ptr<const int32_t>(E, L.charge) + off;
         const int32_t* dcl = ws_ptr<const int32_t>(E, L.digi) + st;

@@ -129,6 +129,8 @@ struct pxcl_event {
     u32 launches = 0;                 // for sampling launches to time
     bool timed_big = false;           // the timed launch ran the big-module kernel
     EventDesc desc{};                 // the event as the kernels saw it (for the hits)
+    u32 slot = 0;                     // launch parity of the last launch
+    bool dirty = false;               // a launch failed to queue: clear the control words
     // hits of the last acquired event
     std::atomic<int> hstate{ST_IDLE};
     std::atomic<int> hits_pending{0};
@@ -188,10 +190,11 @@ static u32 seg_flag(const pxcl_ctx* ctx, u64 digis) {
     return digis >= (u64)ctx->n_cu * seg_chunk(LF_SEG_WIDE) ? LF_SEG_WIDE : 0u;
 }
 
-// Grids of the four kernels.  `digis` and `items` bound the launch's digis and work
-// items (modules present); with `full` (a captured graph replays with any input)
+// Grids of the four kernels.  `digis` bounds the launch's digis and `present` its
+// modules present (at most min(digis, modules) per event); with `full` (a captured
+// graph replays with any input)
 // every kernel gets what fits on the device at once.
-Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 items, u32 k, u32 flags, bool full) {
+Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u32 k, u32 flags, bool full) {
     Grids g;
     const u64 ncu = ctx->n_cu;
     const u64 fa = ncu * (u64)ctx->occ_a;
@@ -206,8 +209,8 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 items, u32 
     const u64 ch = seg_chunk(flags);
     g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + ch - 1) / ch + k)));
     g.b = u32(std::max<u64>(1, std::min<u64>(fb, digis / (dcap + 1))));
-    g.s = u32(std::max<u64>(1, std::min<u64>(fs, (items + mpw - 1) / mpw)));
-    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (items + C_ITEMS - 1) / C_ITEMS + k)));
+    g.s = u32(std::max<u64>(1, std::min<u64>(fs, (present + mpw - 1) / mpw)));
+    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (present + k + C_WG / 64 - 1) / (C_WG / 64))));
     return g;
 }
 
@@ -216,9 +219,9 @@ hipError_t launch_all(const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipS
     if (tev && (e = hipEventRecord(tev[0], s)) != hipSuccess) return e;
     if ((e = launch_segment(a, g.a, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
-    if (!(a.flags & LF_NO_BIG) && (e = launch_big(a, g.b, s)) != hipSuccess) return e;
+    if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;   // lists the big modules
     if (tev && (e = hipEventRecord(tev[2], s)) != hipSuccess) return e;
-    if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;
+    if (!(a.flags & LF_NO_BIG) && (e = launch_big(a, g.b, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[3], s)) != hipSuccess) return e;
     if ((e = launch_compact(a, g.c, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[4], s)) != hipSuccess) return e;
@@ -234,14 +237,23 @@ bool digis_ok(const pxcl_digis* in) {
 
 // Stage host digis into the slot (async copies; one copy if the four arrays are
 // contiguous in the order module,row,col,adc) and describe the event.
+// The event as the kernels see it, its host inputs staged.  The launch parity
+// alternates; after a launch whose work was not all queued the control words are
+// cleared first (a count that launch left would otherwise carry over).
 hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventDesc* d) {
     const EvLayout L = ev_layout(ev->cap, ev->ctx->n_modules);
+    if (ev->dirty) {
+        const hipError_t e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
+        if (e != hipSuccess) return e;
+        ev->dirty = false;
+    }
+    ev->slot ^= 1u;
     d->ws = ev->ws;
     d->hstat = ev->hs_dev;
     d->n = in->n;
     d->cap = ev->cap;
     d->epoch = ev->epoch;
-    d->pad = 0;
+    d->slot = ev->slot;
     if (in->where == PXCL_WHERE_DEVICE) {
         d->module = in->module; d->row = in->row; d->col = in->col; d->adc = in->adc;
         return hipSuccess;
@@ -466,7 +478,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreate(&ev->hits_tev[i]);
     for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev->tev[i]);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
-    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.seg, 0, L.item_start - L.seg, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.mtab, 0, size_t(16) * ctx->n_modules, s);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (ev->done_ev) hipEventDestroy(ev->done_ev);
@@ -542,8 +554,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.flags |= seg_flag(ctx, in->n);
     hipError_t e = make_desc(ev, in, s, &a.single);
     ev->desc = a.single;
-    const u64 items = std::min<u64>(in->n, (u64)ctx->n_modules);
-    const Grids g = grids_for(ctx, wg, mpw, in->n, std::max<u64>(items, 1), 1, a.flags, false);
+    const Grids g = grids_for(ctx, wg, mpw, in->n, std::min<u64>(in->n, ctx->n_modules), 1, a.flags, false);
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) {
@@ -553,6 +564,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        ev->dirty = true;
         ev->state.store(ST_IDLE, std::memory_order_release);
         return PXCL_E_HIP;
     }
@@ -569,16 +581,19 @@ extern "C" int pxcl_query(const pxcl_event* ev) {
     return PXCL_E_INVAL;
 }
 
-// big: whether the big-module kernel was launched (otherwise it is not counted)
+// big: whether the big-module kernel was launched (otherwise it is not counted).
+// Launch order segment, small, big, compact; sums in the order segment, big, small,
+// compact.
 static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev, bool big) {
     float ms[4];
     for (int i = 0; i < 4; ++i)
         if (hipEventElapsedTime(&ms[i], tev[i], tev[i + 1]) != hipSuccess) { (void)hipGetLastError(); return; }
+    static const int slot[4] = {0, 2, 1, 3};
     std::lock_guard<std::mutex> g(ctx->tmu);
     for (int i = 0; i < 4; ++i) {
-        if (i == 1 && !big) continue;
-        ctx->tsum[i] += ms[i];
-        ctx->tcnt[i] += 1;
+        if (slot[i] == 1 && !big) continue;
+        ctx->tsum[slot[i]] += ms[i];
+        ctx->tcnt[slot[i]] += 1;
     }
 }
 
@@ -698,8 +713,7 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
     a.single = ev->desc;
     a.n_modules = ctx->n_modules;
     a.charge_cut = ctx->charge_cut;
-    const u64 items = std::min<u64>(std::max<u32>(ev->n, 1u), (u64)ctx->n_modules);
-    const u32 grid = u32(std::max<u64>(1, std::min<u64>((u64)ctx->n_cu * ctx->occ_h, items)));
+    const u32 grid = u32(std::max<u64>(1, std::min<u64>((u64)ctx->n_cu * ctx->occ_h, ctx->n_modules)));
     if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[0], s);
     if (e == hipSuccess) e = launch_hits(a, grid, s);
     if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[1], s);
@@ -1026,7 +1040,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     *reinterpret_cast<u32*>(b->hp) = k;
     EventDesc* hd = reinterpret_cast<EventDesc*>(b->hp + HDR_EV_OFFSET);
     hipError_t e = hipSuccess;
-    u64 digis = 0, items = 0;
+    u64 digis = 0, present = 0;
     const u32 dcap = cluster_capacity(wg, mpw);
     u32 lflags = LF_NO_BIG;                     // unless an event may hold a big module
     for (u32 i = 0; i < k && e == hipSuccess; ++i) {
@@ -1046,7 +1060,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         e = make_desc(ev, &ins[i], s, &hd[i]);
         ev->desc = hd[i];
         digis += ins[i].n;
-        items += std::min<u64>(ins[i].n, (u64)ctx->n_modules);
+        present += std::min<u64>(ins[i].n, (u64)ctx->n_modules);
     }
     lflags |= seg_flag(ctx, digis);
     if (e == hipSuccess) {
@@ -1057,7 +1071,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
             LaunchArgs a = batch_args(b, wg, mpw);
             a.flags = lflags;
             e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
-            const Grids g = grids_for(ctx, wg, mpw, digis, std::max<u64>(items, 1), k, lflags, false);
+            const Grids g = grids_for(ctx, wg, mpw, digis, present, k, lflags, false);
             if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? b->tev : nullptr);
         }
     }
@@ -1069,7 +1083,10 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        for (u32 i = 0; i < k; ++i) evs[i]->state.store(ST_IDLE, std::memory_order_release);
+        for (u32 i = 0; i < k; ++i) {
+            evs[i]->dirty = true;
+            evs[i]->state.store(ST_IDLE, std::memory_order_release);
+        }
         b->state.store(ST_IDLE, std::memory_order_release);
         return PXCL_E_HIP;
     }

@@ -111,6 +111,10 @@ inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v)
 }
 inline uint64_t atomicAdd(uint64_t* p, uint64_t v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline uint32_t atomicOr(uint32_t* p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline uint64_t atomicCAS(uint64_t* p, uint64_t cmp, uint64_t v) {
+    __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+    return cmp;
+}
 
 // host API subset used by the launch helpers
 typedef int hipError_t;

@@ -44,7 +44,15 @@ int main(int argc, char** argv) {
         ws[e] = static_cast<u8*>(aligned_alloc(256, (L.total + 255) / 256 * 256));
         for (size_t i = 0; i < L.total; ++i) ws[e][i] = u8(rng());        // garbage, as fresh device memory
         memset(ws[e] + L.ctl, 0, CTL_WORDS * 4);                           // what binding clears
-        memset(ws[e] + L.seg, 0, L.item_start - L.seg);
+        // what an earlier launch leaves: module-table entries with its tag and any
+        // range, and a big-module count that a failed launch did not reset
+        ModRange* mt = reinterpret_cast<ModRange*>(ws[e] + L.mtab);
+        const u64 old_tag = u64(999 + e) << 32;
+        for (u32 m = 0; m < M; ++m) {
+            mt[m].first = old_tag | (rng() % (n + 1));
+            mt[m].end = old_tag | (rng() % (n + 1));
+        }
+        reinterpret_cast<u32*>(ws[e] + L.ctl)[CTL_BIG] = 3;
         hs[e] = static_cast<u32*>(aligned_alloc(64, HS_BYTES));
         memset(hs[e], 0, HS_BYTES);
         EventDesc& d = evs[e];
@@ -57,7 +65,7 @@ int main(int argc, char** argv) {
         d.n = n;
         d.cap = cap;
         d.epoch = 1000 + e;
-        d.pad = 0;
+        d.slot = e & 1u;
     }
     fclose(f);
     LaunchArgs a;
@@ -80,8 +88,8 @@ int main(int argc, char** argv) {
         a.ctr = reinterpret_cast<u32*>(aligned_alloc(64, 64));
         memset(a.ctr, 0, 64);
     }
-    if (launch_segment(a, h[5], nullptr) || (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], nullptr)) ||
-        launch_small(h[3], h[4], a, h[7], nullptr) || launch_compact(a, h[8], nullptr)) {
+    if (launch_segment(a, h[5], nullptr) || launch_small(h[3], h[4], a, h[7], nullptr) ||
+        (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], nullptr)) || launch_compact(a, h[8], nullptr)) {
         fprintf(stderr, "launch failed\n");
         return 3;
     }

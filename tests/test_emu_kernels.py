@@ -103,20 +103,20 @@ def test_scratch_mode_column_serpentine_and_lattice(emulator):
     _check(emulator, [ev], 2, grids=(2, 2, 2, 2))
 
 
-def test_more_modules_than_one_indexing_round(emulator):
-    """More modules than the segmentation kernel indexes in one round (2,048): digis in
+def test_more_modules_than_one_prefix_round(emulator):
+    """More modules than the compaction kernel sums in one round (2,048): digis in
     modules on both sides of the round boundaries, one of them above the small
-    kernel's capacity for 64-thread groups."""
+    kernel's capacity for 64-thread groups; every absent module is a work unit."""
     mods, rows, cols = [], [], []
-    for m, npx in ((0, 5), (2047, 40), (2048, 600), (2049, 3), (4095, 7), (4096, 30), (4999, 12)):
+    for m, npx in ((0, 5), (2047, 40), (2048, 600), (2049, 3), (2500, 7), (2501, 30), (2599, 12)):
         lin = (np.arange(npx) * 37 + m) % (160 * 416)     # distinct pixels (37 is coprime to 66,560)
         mods.append(np.full(npx, m))
         rows.append(lin % 160)
         cols.append(lin // 160)
-    ev = synth.from_pixels(np.concatenate(mods), np.concatenate(rows), np.concatenate(cols), n_modules=5000, seed=8)
+    ev = synth.from_pixels(np.concatenate(mods), np.concatenate(rows), np.concatenate(cols), n_modules=2600, seed=8)
     assert emulator.cluster_event(ev, 2000)["status"] == 0
-    _check(emulator, [ev], 5000, wg=64, mpw=1, grids=(2, 2, 3, 2))
-    _check(emulator, [ev, ev], 5000, wg=256, mpw=2, grids=(3, 2, 2, 3))
+    _check(emulator, [ev], 2600, wg=64, mpw=1, grids=(2, 2, 3, 2))
+    _check(emulator, [ev, ev], 2600, wg=256, mpw=4, grids=(3, 2, 2, 3))
 
 
 def test_size_hint_skips_big_kernel(emulator):
