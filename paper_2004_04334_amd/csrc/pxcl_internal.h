@@ -58,6 +58,8 @@ constexpr u32 EB_RANGE = 1, EB_ORDER = 2, EB_DUP = 4, EB_INTERNAL = 8, EB_HINT =
 // Launch flags.
 constexpr u32 LF_NO_BIG = 1;     // the big-module kernel is not launched (size hint)
 constexpr u32 LF_SEG_WIDE = 2;   // segmentation in wide chunks
+constexpr u32 LF_FUSED = 4;      // one event, no segmentation kernel: the small kernel
+                                 // finds every module's digis by search
 __host__ __device__ constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
 // One event as the kernels see it (64 bytes).

@@ -607,6 +607,58 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
 }
 
 // ---------------------------------------------------------------------------
+// Module ranges by search (launches without the segmentation kernel): with the
+// module ids sorted, module m's digis are [lower bound of m, lower bound of m + 1).
+// One wave finds both: each round probes 64 evenly spaced points of each range and
+// keeps the stretch the ballot points to (about 65 times shorter), the last round
+// looks at up to 64 candidates directly; so three dependent loads for 50,000 digis,
+// the first round's probes being the same for every module.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void narrow_range(u32& lo, u32& hi, u64 ge) {
+    const u32 s = hi - lo;                      // > 64; probe l at lo + (l + 1) * s / 65
+    if (ge) {
+        const u32 f = __builtin_ctzll(ge);      // first probe at or above the key
+        hi = lo + u32((u64(f) + 1) * s / 65);
+        lo = f ? lo + u32(u64(f) * s / 65) + 1 : lo;
+    } else {
+        lo = lo + u32(u64(64) * s / 65) + 1;
+    }
+}
+
+__device__ __forceinline__ void module_range(const EventDesc& E, u32 key, u32 lane, u32& first, u32& end) {
+    const u16* mod = E.module;
+    u32 lo0 = 0, hi0 = E.n, lo1 = 0, hi1 = E.n;   // each answer lies in [lo, hi]
+    while (hi0 - lo0 > 64 || hi1 - lo1 > 64) {
+        const bool w0 = hi0 - lo0 > 64, w1 = hi1 - lo1 > 64;
+        const u32 q0 = lo0 + u32((u64(lane) + 1) * (hi0 - lo0) / 65);   // < hi0 <= n
+        const u32 q1 = lo1 + u32((u64(lane) + 1) * (hi1 - lo1) / 65);
+        const bool g0 = w0 && mod[q0] >= key;
+        const bool g1 = w1 && mod[q1] >= key + 1;
+        const u64 b0 = __ballot(g0), b1 = __ballot(g1);
+        if (w0) narrow_range(lo0, hi0, b0);
+        if (w1) narrow_range(lo1, hi1, b1);
+    }
+    const bool g0 = lo0 + lane < hi0 && mod[lo0 + lane] >= key;
+    const bool g1 = lo1 + lane < hi1 && mod[lo1 + lane] >= key + 1;
+    const u64 b0 = __ballot(g0), b1 = __ballot(g1);
+    first = b0 ? lo0 + u32(__builtin_ctzll(b0)) : hi0;
+    end = b1 ? lo1 + u32(__builtin_ctzll(b1)) : hi1;
+}
+
+// Order and range checks of every digi's module id (launches without the
+// segmentation kernel), one coalesced pass over the whole grid.
+template <u32 WG>
+__device__ __forceinline__ void check_module_ids(const LaunchArgs& a, const EventDesc& E) {
+    u32 err = 0;
+    for (u32 i = blockIdx.x * WG + threadIdx.x; i < E.n; i += gridDim.x * WG) {
+        const u32 m = E.module[i];
+        if (m >= a.n_modules) err |= EB_RANGE;
+        if (i + 1 < E.n && E.module[i + 1] < m) err |= EB_ORDER;
+    }
+    if (err) atomicOr(ws_ptr<u32>(E, ev_layout(E.cap, a.n_modules).ctl) + CTL_ERR, err);
+}
+
+// ---------------------------------------------------------------------------
 // small: groups of G = WG/MPW threads, one module each, modules by ticket
 // ---------------------------------------------------------------------------
 template <u32 WG, u32 MPW, u32 K>
@@ -631,10 +683,25 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     for (u32 w = lt; w < WORDS; w += G) gp.bm[w] = 0u;
     if (lt < CMW) gp.cm[lt] = 0u;
     const u32 k = num_events(a);
+    // Without the segmentation kernel (one event): every module is a unit, its
+    // digis found by search; this kernel then checks the module ids, writes the
+    // module table entries of the modules present and sets the unit count the
+    // kernels after it read.
+    const bool fused = (a.flags & LF_FUSED) != 0 && k == 1;
     u32 total;
     if (k == 1) {                             // one event, alone or in a header
         const EventDesc E0 = get_event(a, 0);
-        total = unit_count(a, E0);
+        if (fused) {
+            total = E0.n ? a.n_modules : 0u;
+            check_module_ids<WG>(a, E0);
+            if (blockIdx.x == 0 && tid == 0 && E0.n) {
+                u32* ctl = ws_ptr<u32>(E0, ev_layout(E0.cap, a.n_modules).ctl);
+                ctl[CTL_PRESENT + (E0.slot & 1u)] = a.n_modules;
+                ctl[CTL_PRESENT + ((E0.slot & 1u) ^ 1u)] = 0u;
+            }
+        } else {
+            total = unit_count(a, E0);
+        }
         if (tid == 0) {
             s.pref[0] = 0;
             s.pref[1] = total;
@@ -643,13 +710,22 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     } else {
         total = event_prefix<WG>(a, k, s.pref, s.wsum, CNT_UNITS, 1, 0);
     }
-    // Work unit t: unit t - pref[e] of event e.
-    auto entry_of = [&](u32 t, EventDesc& Ev, u32& e, u32& mod) -> const ModRange* {
+    // Work unit t: unit t - pref[e] of event e, and its module's table entry.
+    auto entry_of = [&](u32 t, EventDesc& Ev, u32& e, u32& mod) -> ModRange {
         e = k == 1 ? 0u : find_slot(s.pref, k, t);
         Ev = get_event(a, e);
         const EvLayout L = ev_layout(Ev.cap, a.n_modules);
+        if (fused) {
+            mod = t;
+            u32 f, en;
+            module_range(Ev, mod, lt & 63u, f, en);
+            const u64 tag = u64(Ev.epoch) << 32;
+            const ModRange r{tag | f, tag | en};
+            if (lt == 0 && en > f) ws_ptr<ModRange>(Ev, L.mtab)[mod] = r;   // for the big kernel, compaction, hits
+            return r;
+        }
         mod = unit_module(a, Ev, L, s.pref[e + 1] - s.pref[e], t - s.pref[e]);
-        return ws_ptr<const ModRange>(Ev, L.mtab) + mod;
+        return ws_ptr<const ModRange>(Ev, L.mtab)[mod];
     };
     // I.n = 0 for an entry that is not this launch's (or inconsistent after an
     // ordering error); ok only for a present module the group can hold.
@@ -667,19 +743,19 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     };
     // A module larger than the group goes to the big-module list (or, when that
     // kernel is not launched, keeps nothing and flags the size hint).  Other units
-    // not clustered (entries not of this launch) need nothing: segmentation cleared
-    // the kept counts.
+    // not clustered (absent modules, entries not of this launch) keep nothing: the
+    // segmentation kernel cleared the kept counts, without it this kernel does.
     auto skip = [&](const EventDesc& Ev, const Item& Is) {
-        if (Is.n <= G * K) return;
         const EvLayout L = ev_layout(Ev.cap, a.n_modules);
         u32* ctl = ws_ptr<u32>(Ev, L.ctl);
-        if (!(a.flags & LF_NO_BIG)) {
+        if (Is.n > G * K && !(a.flags & LF_NO_BIG)) {
             const u32 r = atomicAdd(&ctl[CTL_BIG], 1u);
             if (r < a.n_modules) ws_ptr<u32>(Ev, L.big)[r] = Is.mod;
             else atomicOr(&ctl[CTL_ERR], EB_INTERNAL);
-        } else {
-            atomicOr(&ctl[CTL_ERR], EB_HINT);
+            return;
         }
+        if (Is.n > G * K) atomicOr(&ctl[CTL_ERR], EB_HINT);
+        if (fused) ws_ptr<u32>(Ev, L.kept)[Is.mod] = 0u;
     };
 
     // Modules are assigned statically in rounds (round r: module r*per_round + the
@@ -696,7 +772,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         const u32 t = base + gofs;
         if (t < total) {
             u32 e, mod;
-            const ModRange r = *entry_of(t, E, e, mod);
+            const ModRange r = entry_of(t, E, e, mod);
             I = make_item(r, E, e, mod, true);
         }
         I = wave_uniform(I);                      // one module per wave (or per group of waves)
@@ -713,15 +789,15 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     while (base < total) {
         u32 nbase = total, nv2 = 0, ne = 0, nmod = 0;
         EventDesc En{};
-        const ModRange* pent = nullptr;
+        bool have = false;
         ModRange ent{0, 0};
         Item In{0, 0, 0, 0, 0, false};
         u32 NR[K], NC[K], NA[K];
         auto issue_entry = [&]() {
             const u32 t = nbase + gofs;
             if (t < total) {
-                pent = entry_of(t, En, ne, nmod);
-                ent = *pent;                      // load issued; used at stage 2
+                ent = entry_of(t, En, ne, nmod);  // a table load: issued here, used at stage 2
+                have = true;
             }
         };
         auto mid = [&](int stage) {
@@ -744,7 +820,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
                     issue_entry();
                 }
             } else if (stage == 2) {
-                In = wave_uniform(make_item(ent, En, ne, nmod, pent != nullptr));
+                In = wave_uniform(make_item(ent, En, ne, nmod, have));
                 En = wave_uniform(En);
                 if (In.ok) fetch_digis<G, K>(En, In, lt, NR, NC, NA);
             }
@@ -1177,6 +1253,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             if (lane == 0) {
                 const u32 err = ctl[CTL_ERR];
                 ctl[CTL_ERR] = 0u;
+                ctl[CTL_BIG] = 0u;                         // the big kernel has run
                 ctl[CTL_NCL] = ncl;
                 u32* hs = E.hstat;
                 st_sys(&hs[HS_ERR], err);

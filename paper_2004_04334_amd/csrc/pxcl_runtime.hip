@@ -127,7 +127,7 @@ struct pxcl_event {
     pxcl_batch* batch = nullptr;
     std::atomic<int> cb_pending{0};   // launches whose completion callback has not returned
     u32 launches = 0;                 // for sampling launches to time
-    bool timed_big = false;           // the timed launch ran the big-module kernel
+    u32 timed_flags = 0;              // launch flags of the timed launch (kernels it ran)
     EventDesc desc{};                 // the event as the kernels saw it (for the hits)
     u32 slot = 0;                     // launch parity of the last launch
     bool dirty = false;               // a launch failed to queue: clear the control words
@@ -170,7 +170,7 @@ struct pxcl_batch {
     hipGraph_t graph = nullptr;
     u32 g_wg = 0, g_mpw = 0, g_flags = 0;
     u32 launches = 0;
-    bool timed_big = false;
+    u32 timed_flags = 0;
     hipEvent_t tev[5] = {};
     bool timed = false;       // the launch in flight records per-kernel events
 };
@@ -217,7 +217,7 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
 hipError_t launch_all(const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipStream_t s, hipEvent_t* tev) {
     hipError_t e;
     if (tev && (e = hipEventRecord(tev[0], s)) != hipSuccess) return e;
-    if ((e = launch_segment(a, g.a, s)) != hipSuccess) return e;
+    if (!(a.flags & LF_FUSED) && (e = launch_segment(a, g.a, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
     if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;   // lists the big modules
     if (tev && (e = hipEventRecord(tev[2], s)) != hipSuccess) return e;
@@ -551,10 +551,10 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.charge_cut = ctx->charge_cut;
     a.dcap = cluster_capacity(wg, mpw);
     if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
-    a.flags |= seg_flag(ctx, in->n);
+    a.flags |= LF_FUSED;                       // one event: ranges by search, no segmentation kernel
     hipError_t e = make_desc(ev, in, s, &a.single);
     ev->desc = a.single;
-    const Grids g = grids_for(ctx, wg, mpw, in->n, std::min<u64>(in->n, ctx->n_modules), 1, a.flags, false);
+    const Grids g = grids_for(ctx, wg, mpw, in->n, in->n ? ctx->n_modules : 0u, 1, a.flags, false);   // every module a unit
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) {
@@ -569,7 +569,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
         return PXCL_E_HIP;
     }
     ev->timed = timed;
-    ev->timed_big = !(a.flags & LF_NO_BIG);
+    ev->timed_flags = a.flags;
     return PXCL_OK;
 }
 
@@ -581,17 +581,16 @@ extern "C" int pxcl_query(const pxcl_event* ev) {
     return PXCL_E_INVAL;
 }
 
-// big: whether the big-module kernel was launched (otherwise it is not counted).
-// Launch order segment, small, big, compact; sums in the order segment, big, small,
-// compact.
-static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev, bool big) {
+// flags: the launch's LF_* (a kernel not launched is not counted).  Launch order
+// segment, small, big, compact; sums in the order segment, big, small, compact.
+static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev, u32 flags) {
     float ms[4];
     for (int i = 0; i < 4; ++i)
         if (hipEventElapsedTime(&ms[i], tev[i], tev[i + 1]) != hipSuccess) { (void)hipGetLastError(); return; }
     static const int slot[4] = {0, 2, 1, 3};
     std::lock_guard<std::mutex> g(ctx->tmu);
     for (int i = 0; i < 4; ++i) {
-        if (slot[i] == 1 && !big) continue;
+        if ((slot[i] == 1 && (flags & LF_NO_BIG)) || (slot[i] == 0 && (flags & LF_FUSED))) continue;
         ctx->tsum[slot[i]] += ms[i];
         ctx->tcnt[slot[i]] += 1;
     }
@@ -600,7 +599,7 @@ static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev, bool big) {
 static void collect_timing(pxcl_event* ev) {
     if (!ev->timed) return;
     ev->timed = false;
-    add_timing(ev->ctx, ev->tev, ev->timed_big);
+    add_timing(ev->ctx, ev->tev, ev->timed_flags);
 }
 
 extern "C" int pxcl_produce(pxcl_event* ev, pxcl_clusters* out) {
@@ -955,7 +954,7 @@ static void drop_graph(pxcl_batch* b) {
 extern "C" int pxcl_batch_unbind(pxcl_batch* b) {
     if (!b) return PXCL_E_INVAL;
     if (b->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
-    if (b->timed) { b->timed = false; add_timing(b->ctx, b->tev, b->timed_big); }
+    if (b->timed) { b->timed = false; add_timing(b->ctx, b->tev, b->timed_flags); }
     drop_graph(b);
     hipEventDestroy(b->done_ev);
     for (int i = 0; i < 5; ++i) hipEventDestroy(b->tev[i]);
@@ -1028,7 +1027,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
     const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
-    if (b->timed) { b->timed = false; add_timing(ctx, b->tev, b->timed_big); }   // the previous launch is complete
+    if (b->timed) { b->timed = false; add_timing(ctx, b->tev, b->timed_flags); }   // the previous launch is complete
     // graph replays are never timed (elapsed times of events recorded inside a captured
     // graph are not available); plain launches are sampled every `period` launches
     const int period = ctx->timing.load();
@@ -1091,7 +1090,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         return PXCL_E_HIP;
     }
     b->timed = timed;
-    b->timed_big = !(lflags & LF_NO_BIG);
+    b->timed_flags = lflags;
     return PXCL_OK;
 }
 

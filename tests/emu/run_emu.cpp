@@ -5,7 +5,7 @@
 // input:  u32 k, n_modules, cut, wg, mpw, grid_a, grid_b, grid_s, grid_c, header
 //         (1: the events go through a batch header even when k == 1), launch flags
 //         (LF_NO_BIG: the big-module kernel is not run; LF_SEG_WIDE: segmentation in
-//         wide chunks), hits (1: run the hits kernel
+//         wide chunks; LF_FUSED: no segmentation kernel), hits (1: run the hits kernel
 //         after the launch);
 //         per event: u32 n, u32 cap, u16 module[n], row[n], col[n], adc[n]
 // output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
@@ -45,14 +45,16 @@ int main(int argc, char** argv) {
         for (size_t i = 0; i < L.total; ++i) ws[e][i] = u8(rng());        // garbage, as fresh device memory
         memset(ws[e] + L.ctl, 0, CTL_WORDS * 4);                           // what binding clears
         // what an earlier launch leaves: module-table entries with its tag and any
-        // range, and a big-module count that a failed launch did not reset
+        // range; without the fused form also a big-module count that launch did not
+        // reset (the segmentation kernel resets it; the fused form relies on the
+        // compaction of every finished launch and the host's clear after a failed one)
         ModRange* mt = reinterpret_cast<ModRange*>(ws[e] + L.mtab);
         const u64 old_tag = u64(999 + e) << 32;
         for (u32 m = 0; m < M; ++m) {
             mt[m].first = old_tag | (rng() % (n + 1));
             mt[m].end = old_tag | (rng() % (n + 1));
         }
-        reinterpret_cast<u32*>(ws[e] + L.ctl)[CTL_BIG] = 3;
+        if (!(h[10] & LF_FUSED)) reinterpret_cast<u32*>(ws[e] + L.ctl)[CTL_BIG] = 3;
         hs[e] = static_cast<u32*>(aligned_alloc(64, HS_BYTES));
         memset(hs[e], 0, HS_BYTES);
         EventDesc& d = evs[e];
@@ -88,7 +90,7 @@ int main(int argc, char** argv) {
         a.ctr = reinterpret_cast<u32*>(aligned_alloc(64, 64));
         memset(a.ctr, 0, 64);
     }
-    if (launch_segment(a, h[5], nullptr) || launch_small(h[3], h[4], a, h[7], nullptr) ||
+    if ((!(a.flags & LF_FUSED) && launch_segment(a, h[5], nullptr)) || launch_small(h[3], h[4], a, h[7], nullptr) ||
         (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], nullptr)) || launch_compact(a, h[8], nullptr)) {
         fprintf(stderr, "launch failed\n");
         return 3;

@@ -82,6 +82,61 @@ def test_wide_segmentation_chunks(emulator):
     _check(emulator, evs, 6, grids=(3, 2, 3, 2), caps=[max(1, e["module"].size) + 5 for e in evs], seg_wide=True)
 
 
+def _single_events():
+    """One-event launches of every kind the search must get right: a plain event, one
+    with a module above the small kernel's capacity, an empty one, one whose module 0
+    is absent, and one with a few modules far apart in 700."""
+    big = _mixed_events()[2]
+    empty = {k: np.zeros(0, np.uint16) for k in ("module", "row", "col", "adc")}
+    mods, rows, cols = [], [], []
+    for m, npx in ((0, 5), (300, 40), (301, 600), (302, 3), (699, 12)):
+        lin = (np.arange(npx) * 37 + m) % (160 * 416)
+        mods.append(np.full(npx, m))
+        rows.append(lin % 160)
+        cols.append(lin // 160)
+    far = synth.from_pixels(np.concatenate(mods), np.concatenate(rows), np.concatenate(cols), n_modules=700, seed=8)
+    late = synth.plain_event(4, n_modules=6)
+    late = {k: v[late["module"] > 0] if isinstance(v, np.ndarray) else v for k, v in late.items()}
+    evs = [(synth.plain_event(0, n_modules=8), 8), (big, 6), (empty, 6), (late, 6), (far, 700)]
+    return [(dict(e, n_modules=m), m) for e, m in evs]
+
+
+@pytest.mark.parametrize("wg,mpw", [(64, 1), (128, 2), (256, 4), (512, 1)])
+def test_fused_single_event(emulator, wg, mpw):
+    """Without the segmentation kernel: module ranges by search, module ids checked,
+    module table entries and kept counts written by the small kernel."""
+    evs = _single_events()
+    if wg // mpw > 64:                   # groups of several waves step through every absent module
+        evs = evs[:-1]
+    for ev, m in evs:
+        _check(emulator, [ev], m, wg=wg, mpw=mpw, grids=(1, 2, 3, 2), fused=True)
+
+
+def test_fused_single_event_sanitized(emulator):
+    """The fused form under ThreadSanitizer, and with the size hint and the hits."""
+    ev, m = _single_events()[0]
+    _check(emulator, [ev], m, wg=256, mpw=2, grids=(1, 2, 3, 2), fused=True, sanitizer="thread")
+    _check(emulator, [ev], m, wg=256, mpw=1, grids=(1, 2, 3, 2), fused=True, no_big=True)   # 733 <= 2,048
+    (r,) = emu.run([ev], m, grids=(1, 2, 3, 2), fused=True, hits=True)
+    ref = emulator.hits(ev, 2000)
+    assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])
+
+
+def test_fused_rejects_unsorted_and_out_of_range(emulator):
+    """The small kernel's own checks of the module ids flag what the segmentation
+    kernel would have flagged."""
+    ev, m = _single_events()[0]
+    bad = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
+    i = bad["module"].size // 2
+    bad["module"][i], bad["module"][-1] = bad["module"][-1], bad["module"][i]
+    (r,) = emu.run([bad], m, grids=(1, 2, 3, 2), fused=True)
+    assert r["status"] == emulator.cluster_event(bad, 2000)["status"] != 0
+    bad2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
+    bad2["module"][-1] = m
+    (r,) = emu.run([bad2], m, grids=(1, 2, 3, 2), fused=True)
+    assert r["status"] == emulator.cluster_event(bad2, 2000)["status"] != 0
+
+
 def test_scratch_mode_big_module(emulator):
     """A module above the register capacity of the big-module kernel (a serpentine
     of 33,359 pixels) next to a full-column track."""
