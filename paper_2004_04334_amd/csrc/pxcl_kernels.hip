@@ -646,14 +646,32 @@ __device__ __forceinline__ void module_range(const EventDesc& E, u32 key, u32 la
 }
 
 // Order and range checks of every digi's module id (launches without the
-// segmentation kernel), one coalesced pass over the whole grid.
+// segmentation kernel), one coalesced pass over the whole grid.  The first stride's
+// ids are loaded by id_check_load (before the first range search, so that the two
+// latencies overlap) and checked, with the rest, by id_check_finish.
+struct IdCheck {
+    u32 m0, m1;
+};
 template <u32 WG>
-__device__ __forceinline__ void check_module_ids(const LaunchArgs& a, const EventDesc& E) {
+__device__ __forceinline__ IdCheck id_check_load(const EventDesc& E) {
+    const u32 i = blockIdx.x * WG + threadIdx.x;
+    IdCheck c{0u, 0xFFFFFFFFu};
+    if (i < E.n) {
+        c.m0 = E.module[i];
+        if (i + 1 < E.n) c.m1 = E.module[i + 1];
+    }
+    return c;
+}
+template <u32 WG>
+__device__ __forceinline__ void id_check_finish(const LaunchArgs& a, const EventDesc& E, IdCheck c) {
     u32 err = 0;
     for (u32 i = blockIdx.x * WG + threadIdx.x; i < E.n; i += gridDim.x * WG) {
-        const u32 m = E.module[i];
-        if (m >= a.n_modules) err |= EB_RANGE;
-        if (i + 1 < E.n && E.module[i + 1] < m) err |= EB_ORDER;
+        if (i >= gridDim.x * WG) {               // strides after the first
+            c.m0 = E.module[i];
+            c.m1 = i + 1 < E.n ? E.module[i + 1] : 0xFFFFFFFFu;
+        }
+        if (c.m0 >= a.n_modules) err |= EB_RANGE;
+        if (c.m1 < c.m0) err |= EB_ORDER;
     }
     if (err) atomicOr(ws_ptr<u32>(E, ev_layout(E.cap, a.n_modules).ctl) + CTL_ERR, err);
 }
@@ -689,11 +707,12 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     // kernels after it read.
     const bool fused = (a.flags & LF_FUSED) != 0 && k == 1;
     u32 total;
+    IdCheck idc{0u, 0xFFFFFFFFu};
     if (k == 1) {                             // one event, alone or in a header
         const EventDesc E0 = get_event(a, 0);
         if (fused) {
             total = E0.n ? a.n_modules : 0u;
-            check_module_ids<WG>(a, E0);
+            idc = id_check_load<WG>(E0);
             if (blockIdx.x == 0 && tid == 0 && E0.n) {
                 u32* ctl = ws_ptr<u32>(E0, ev_layout(E0.cap, a.n_modules).ctl);
                 ctl[CTL_PRESENT + (E0.slot & 1u)] = a.n_modules;
@@ -779,6 +798,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         E = wave_uniform(E);
         if (I.ok) fetch_digis<G, K>(E, I, lt, R, C, A);
     }
+    if (fused) id_check_finish<WG>(a, get_event(a, 0), idc);
     const u32 nrounds = per_round < total ? max(1u, u32((3ull * total) / (4ull * per_round))) : 1u;   // static
     const u32 nstatic = nrounds * per_round;
     const bool dyn = nstatic < total;             // tickets needed at all
@@ -1263,10 +1283,12 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             continue;
         }
         const u32 m = wave_uniform(unit_module(a, E, L, np, j));
+        // count, offset and source loaded together (the offset also for a module that
+        // turns out to keep nothing: one dependent round less)
         const u32 cnt = wave_uniform(kept[m]);
-        if (cnt == 0) continue;                            // absent, or nothing kept
-        const u32 off = wave_uniform(kept_before(kept, m, lane));
         const u32 src = wave_uniform(u32(ws_ptr<const ModRange>(E, L.mtab)[m].first));
+        const u32 off = wave_uniform(kept_before(kept, m, lane));
+        if (cnt == 0) continue;                            // absent, or nothing kept
         if (lane == 0) ws_ptr<u32>(E, L.off)[m] = off;
         if (cnt > E.n || off > E.n - cnt || src > E.n - cnt) continue;   // inconsistent (flagged)
         const int32_t* tid_ = ws_ptr<const int32_t>(E, L.tid);

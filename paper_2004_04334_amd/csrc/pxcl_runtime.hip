@@ -99,6 +99,7 @@ struct pxcl_ctx {
     std::string arch;
     std::atomic<u32> wg{256}, mpw{1};
     int occ_a = 1, occ_l = 1, occ_c = 1, occ_h = 1;
+    int occ_s[4][5] = {};               // small kernel per shape [log2(wg) - 6][mpw], queried once
     std::atomic<int> bound{0};
     std::atomic<int> timing{0};
     std::mutex tmu;
@@ -199,7 +200,7 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
     const u64 ncu = ctx->n_cu;
     const u64 fa = ncu * (u64)ctx->occ_a;
     const u64 fb = ncu * (u64)ctx->occ_l;
-    const u64 fs = ncu * (u64)occupancy_cluster(wg, mpw);
+    const u64 fs = ncu * (u64)ctx->occ_s[31 - __builtin_clz(wg) - 6][mpw];
     const u64 fc = ncu * (u64)ctx->occ_c;
     if (full) {
         g.a = u32(fa); g.b = u32(fb); g.s = u32(fs); g.c = u32(fc);
@@ -378,6 +379,9 @@ extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** ou
         c->arch = a.substr(0, a.find(':'));
     }
     c->occ_a = occupancy_segment();
+    for (u32 w = 64; w <= 512; w *= 2)
+        for (u32 m = 1; m <= 4; m *= 2)
+            if (cluster_config_valid(w, m)) c->occ_s[31 - __builtin_clz(w) - 6][m] = occupancy_cluster(w, m);
     c->occ_l = occupancy_big();
     c->occ_c = occupancy_compact();
     c->occ_h = occupancy_hits();
