@@ -609,10 +609,12 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
 // ---------------------------------------------------------------------------
 // Module ranges by search (launches without the segmentation kernel): with the
 // module ids sorted, module m's digis are [lower bound of m, lower bound of m + 1).
-// One wave finds both: each round probes 64 evenly spaced points of each range and
-// keeps the stretch the ballot points to (about 65 times shorter), the last round
-// looks at up to 64 candidates directly; so three dependent loads for 50,000 digis,
-// the first round's probes being the same for every module.
+// One wave finds both.  The first round probes 64 points SEARCH_STEP apart around
+// where module m would start if the modules were evenly filled; when that brackets
+// a bound, it is within SEARCH_STEP digis and the last round (up to 128 candidates,
+// two per lane) finds it: two dependent loads.  Otherwise each further round probes
+// 64 evenly spaced points of the remaining range and keeps the stretch the ballot
+// points to (about 65 times shorter).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void narrow_range(u32& lo, u32& hi, u64 ge) {
     const u32 s = hi - lo;                      // > 64; probe l at lo + (l + 1) * s / 65
@@ -625,11 +627,39 @@ __device__ __forceinline__ void narrow_range(u32& lo, u32& hi, u64 ge) {
     }
 }
 
-__device__ __forceinline__ void module_range(const EventDesc& E, u32 key, u32 lane, u32& first, u32& end) {
+constexpr u32 SEARCH_STEP = 128, SEARCH_LAST = 128;
+
+// Narrow [lo, hi] by a ballot over probes at q(l) = clamp(guess + (l - 32) * step),
+// non-decreasing in l; the answer is the first index whose id is >= the key.
+__device__ __forceinline__ void narrow_window(u32& lo, u32& hi, u64 ge, long long guess, u32 n) {
+    auto q = [&](u32 l) -> u32 {
+        const long long p = guess + (static_cast<long long>(l) - 32) * SEARCH_STEP;
+        return u32(p < 0 ? 0 : (p >= (long long)n ? (long long)n - 1 : p));
+    };
+    if (ge) {
+        const u32 f = __builtin_ctzll(ge);
+        hi = q(f);
+        if (f) lo = q(f - 1) + 1;
+    } else {
+        lo = q(63) + 1;
+    }
+}
+
+__device__ __forceinline__ void module_range(const EventDesc& E, u32 n_modules, u32 key, u32 lane, u32& first,
+                                             u32& end) {
     const u16* mod = E.module;
-    u32 lo0 = 0, hi0 = E.n, lo1 = 0, hi1 = E.n;   // each answer lies in [lo, hi]
-    while (hi0 - lo0 > 64 || hi1 - lo1 > 64) {
-        const bool w0 = hi0 - lo0 > 64, w1 = hi1 - lo1 > 64;
+    const u32 n = E.n;
+    u32 lo0 = 0, hi0 = n, lo1 = 0, hi1 = n;       // each answer lies in [lo, hi]
+    {
+        const long long guess = static_cast<long long>((u64(key) * n) / n_modules);
+        const long long p = guess + (static_cast<long long>(lane) - 32) * SEARCH_STEP;
+        const u32 v = mod[p < 0 ? 0 : (p >= (long long)n ? n - 1 : u32(p))];
+        const u64 b0 = __ballot(v >= key), b1 = __ballot(v >= key + 1);
+        narrow_window(lo0, hi0, b0, guess, n);
+        narrow_window(lo1, hi1, b1, guess, n);
+    }
+    while (hi0 - lo0 > SEARCH_LAST || hi1 - lo1 > SEARCH_LAST) {
+        const bool w0 = hi0 - lo0 > SEARCH_LAST, w1 = hi1 - lo1 > SEARCH_LAST;
         const u32 q0 = lo0 + u32((u64(lane) + 1) * (hi0 - lo0) / 65);   // < hi0 <= n
         const u32 q1 = lo1 + u32((u64(lane) + 1) * (hi1 - lo1) / 65);
         const bool g0 = w0 && mod[q0] >= key;
@@ -638,11 +668,14 @@ __device__ __forceinline__ void module_range(const EventDesc& E, u32 key, u32 la
         if (w0) narrow_range(lo0, hi0, b0);
         if (w1) narrow_range(lo1, hi1, b1);
     }
+    // at most SEARCH_LAST = 128 candidates per bound: positions lo + lane, lo + 64 + lane
     const bool g0 = lo0 + lane < hi0 && mod[lo0 + lane] >= key;
+    const bool h0 = lo0 + 64 + lane < hi0 && mod[lo0 + 64 + lane] >= key;
     const bool g1 = lo1 + lane < hi1 && mod[lo1 + lane] >= key + 1;
-    const u64 b0 = __ballot(g0), b1 = __ballot(g1);
-    first = b0 ? lo0 + u32(__builtin_ctzll(b0)) : hi0;
-    end = b1 ? lo1 + u32(__builtin_ctzll(b1)) : hi1;
+    const bool h1 = lo1 + 64 + lane < hi1 && mod[lo1 + 64 + lane] >= key + 1;
+    const u64 b0 = __ballot(g0), c0 = __ballot(h0), b1 = __ballot(g1), c1 = __ballot(h1);
+    first = b0 ? lo0 + u32(__builtin_ctzll(b0)) : c0 ? lo0 + 64 + u32(__builtin_ctzll(c0)) : hi0;
+    end = b1 ? lo1 + u32(__builtin_ctzll(b1)) : c1 ? lo1 + 64 + u32(__builtin_ctzll(c1)) : hi1;
 }
 
 // Order and range checks of every digi's module id (launches without the
@@ -737,7 +770,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         if (fused) {
             mod = t;
             u32 f, en;
-            module_range(Ev, mod, lt & 63u, f, en);
+            module_range(Ev, a.n_modules, mod, lt & 63u, f, en);
             const u64 tag = u64(Ev.epoch) << 32;
             const ModRange r{tag | f, tag | en};
             if (lt == 0 && en > f) ws_ptr<ModRange>(Ev, L.mtab)[mod] = r;   // for the big kernel, compaction, hits

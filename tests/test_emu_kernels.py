@@ -122,6 +122,18 @@ def test_fused_single_event_sanitized(emulator):
     assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])
 
 
+def test_fused_search_far_from_even_fill(emulator):
+    """Modules far from evenly filled (500 digis in module 1, 10,000 in module 4 of 6):
+    the first search round does not bracket the bounds and the general rounds finish
+    them; module 4 also goes to the big-module kernel."""
+    lin1 = (np.arange(500) * 37) % (160 * 416)
+    lin4 = (np.arange(10000) * 37 + 5) % (160 * 416)
+    m = np.concatenate([np.full(500, 1), np.full(10000, 4)])
+    lin = np.concatenate([lin1, lin4])
+    ev = dict(synth.from_pixels(m, lin % 160, lin // 160, n_modules=6, seed=12), n_modules=6)
+    _check(emulator, [ev], 6, wg=256, mpw=1, grids=(1, 2, 3, 2), fused=True)
+
+
 def test_fused_rejects_unsorted_and_out_of_range(emulator):
     """The small kernel's own checks of the module ids flag what the segmentation
     kernel would have flagged."""
