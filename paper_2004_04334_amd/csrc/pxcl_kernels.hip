@@ -1361,7 +1361,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
 // digi of the module whose id falls in the held range finds its cluster by binary
 // search and adds its weighted coordinates with LDS atomics.
 // ---------------------------------------------------------------------------
-constexpr u32 H_WG = 256, H_CAP = 2048;
+constexpr u32 H_WG = 64, H_CAP = 512;     // one wave, ~10 KB of LDS: every module resident at once
 
 __global__ __launch_bounds__(H_WG) void k_hits(LaunchArgs a) {
     __shared__ u32 s_pref[MAXB + 1];
