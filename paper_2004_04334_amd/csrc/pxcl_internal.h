@@ -35,12 +35,14 @@ constexpr u32 C_WG = 256;                                   // compaction: a wav
 constexpr u32 K_SMALL = 8;                                  // digis per thread (small-module kernel)
 constexpr u32 B_WG = 512, K_BIG = 32;                       // big-module kernel
 constexpr u32 BIG_RCAP = B_WG * K_BIG;                      // 16384: larger modules use scratch mode
+constexpr u32 S_WG = 1024;                                  // scratch-mode kernel
 
 // Per-event control words (u32) at the start of an event workspace.
 enum : u32 {
     CTL_ERR = 0,      // accumulated PXCL_ERRBIT_* of the launch in progress
     CTL_NCL = 2,      // kept clusters
-    CTL_BIG = 4,      // modules on the big-module list
+    CTL_BIG = 4,      // modules on the big-module list (register mode)
+    CTL_SCR = 3,      // modules on the scratch-mode list
     CTL_PRESENT = 5,  // words 5-6: modules on the present-module list, one count per
                       // launch parity (EventDesc::slot); a launch clears the other one
     CTL_CTR = 8,      // launch counters when the event is launched on its own
@@ -60,6 +62,7 @@ constexpr u32 LF_NO_BIG = 1;     // the big-module kernel is not launched (size 
 constexpr u32 LF_SEG_WIDE = 2;   // segmentation in wide chunks
 constexpr u32 LF_FUSED = 4;      // one event, no segmentation kernel: the small kernel
                                  // finds every module's digis by search
+constexpr u32 LF_NO_SCRATCH = 8; // the scratch-mode kernel is not launched (size hint)
 __host__ __device__ constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
 // One event as the kernels see it (64 bytes).
@@ -109,6 +112,7 @@ struct EvLayout {
     size_t mtab;                             // per module: ModRange
     size_t kept;                             // per module: kept clusters
     size_t big;                              // module ids for the big-module kernel
+    size_t scr;                              // module ids for the scratch-mode kernel
     size_t present;                          // module ids of the modules present (any order)
     size_t off;                              // per module: its first cluster in the outputs
     size_t hit_x, hit_y;                     // hits (per kept cluster), when asked for
@@ -134,6 +138,7 @@ PXCL_HD inline EvLayout ev_layout(u32 N, u32 M) {
     L.mtab = o;       o = al256(o + 16 * m);
     L.kept = o;       o = al256(o + 4 * m);
     L.big = o;        o = al256(o + 4 * m);
+    L.scr = o;        o = al256(o + 4 * m);
     L.present = o;    o = al256(o + 4 * m);
     L.off = o;        o = al256(o + 4 * m);
     L.hit_x = o;      o = al256(o + 4 * n);

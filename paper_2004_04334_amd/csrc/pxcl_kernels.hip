@@ -307,6 +307,7 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
         if (c == 0) {                            // read by the kernels after this one
             if (tid == 0) {
                 ctl[CTL_BIG] = 0u;
+                ctl[CTL_SCR] = 0u;
                 ctl[CTL_PRESENT + (slot ^ 1u)] = 0u;   // for the next launch (the last one's is done)
             }
             u32* kept = ws_ptr<u32>(E, L.kept);
@@ -793,21 +794,23 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         I.ok = I.n > 0 && I.n <= G * K;
         return I;
     };
-    // A module larger than the group goes to the big-module list (or, when that
-    // kernel is not launched, keeps nothing and flags the size hint).  Other units
-    // not clustered (absent modules, entries not of this launch) keep nothing: the
-    // segmentation kernel cleared the kept counts, without it this kernel does.
+    // A module larger than the group goes to the big-module list, or above BIG_RCAP
+    // digis to the scratch-mode list (or, when that kernel is not launched, keeps
+    // nothing and flags the size hint).  Other units not clustered (absent modules,
+    // entries not of this launch) keep nothing: the segmentation kernel cleared the
+    // kept counts, without it this kernel does.
     auto skip = [&](const EventDesc& Ev, const Item& Is) {
         const EvLayout L = ev_layout(Ev.cap, a.n_modules);
         u32* ctl = ws_ptr<u32>(Ev, L.ctl);
-        if (Is.n > G * K && !(a.flags & LF_NO_BIG)) {
-            const u32 r = atomicAdd(&ctl[CTL_BIG], 1u);
-            if (r < a.n_modules) ws_ptr<u32>(Ev, L.big)[r] = Is.mod;
+        const bool scr = Is.n > BIG_RCAP;
+        if (Is.n > G * K && !(a.flags & (scr ? (LF_NO_BIG | LF_NO_SCRATCH) : LF_NO_BIG))) {
+            const u32 r = atomicAdd(&ctl[scr ? CTL_SCR : CTL_BIG], 1u);
+            if (r < a.n_modules) ws_ptr<u32>(Ev, scr ? L.scr : L.big)[r] = Is.mod;
             else atomicOr(&ctl[CTL_ERR], EB_INTERNAL);
             return;
         }
         if (Is.n > G * K) atomicOr(&ctl[CTL_ERR], EB_HINT);
-        if (fused) ws_ptr<u32>(Ev, L.kept)[Is.mod] = 0u;
+        if (fused || Is.n > G * K) ws_ptr<u32>(Ev, L.kept)[Is.mod] = 0u;
     };
 
     // Modules are assigned statically in rounds (round r: module r*per_round + the
@@ -908,22 +911,18 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
 // follow: charge and size (device atomics into the module's slice of the event's
 // final charge/size arrays, which the compaction kernel overwrites later; a wave
 // whose digis all belong to one cluster adds once), then per-digi ids.
+template <u32 BW>
 struct BigScratchSmem {
     u32 bm[WORDS];
     u32 par[MAX_RUNS];
     u32 rootb[MAX_RUNS / 32];   // root runs, then kept clusters (over cluster index)
     u16 rpre[WORDS];
     u16 rootp[MAX_RUNS / 32];   // roots before each word, then kept clusters before each word
-    u32 wsum[B_WG / 64];
+    u32 wsum[BW / 64];
     u32 misc[4];
-};
-union BigSmem {
-    RegModuleSmem<B_WG, K_BIG> reg;
-    BigScratchSmem scr;
 };
 
 constexpr u32 UNR = 8;                        // digis per thread fetched at once
-constexpr u32 SPAN = UNR * B_WG;
 
 __device__ __forceinline__ u32 clampj(u32 j, u32 n) { return j < n ? j : 0u; }
 
@@ -985,10 +984,12 @@ __device__ __forceinline__ void link_run(u32* par, const u32* bm, const u16* rpr
     }
 }
 
+template <u32 BW>
 __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const EventDesc& E, const EvLayout& L,
-                                                const Item& I, BigScratchSmem& s) {
-    constexpr u32 WPT = (WORDS + B_WG - 1) / B_WG;
-    constexpr u32 KW = MAX_RUNS / 32, KPT = (KW + B_WG - 1) / B_WG;
+                                                const Item& I, BigScratchSmem<BW>& s) {
+    constexpr u32 WPT = (WORDS + BW - 1) / BW;
+    constexpr u32 KW = MAX_RUNS / 32, KPT = (KW + BW - 1) / BW;
+    constexpr u32 SPAN = UNR * BW;
     const u32 tid = threadIdx.x, n = I.n, st = I.st;
     u32* cid = ws_ptr<u32>(E, L.id) + st;        // per cluster: id (or -1 once cut)
     u32* cch = ws_ptr<u32>(E, L.charge) + st;    // per cluster: charge
@@ -1000,14 +1001,14 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
         u32 r[UNR], c[UNR];
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
-            const u32 i = st + clampj(base + u * B_WG + tid, n);
+            const u32 i = st + clampj(base + u * BW + tid, n);
             r[u] = E.row[i];
             c[u] = E.col[i];
             if (adc) adc[u] = E.adc[i];
         }
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
-            const u32 j = base + u * B_WG + tid;
+            const u32 j = base + u * BW + tid;
             lin[u] = (j < n && r[u] < ROWS && c[u] < COLS) ? c[u] * ROWS + r[u] : NOPIX;
             if (j < n && lin[u] == NOPIX) err |= EB_RANGE;
         }
@@ -1021,7 +1022,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     // s.rootb[] over all KW words: bit r set iff pred(r); a wave forms 64 bits at a time
     // from 64 consecutive indices (ballot), so lanes touch consecutive words
     auto set_bits = [&](auto pred) {
-        for (u32 base = wv * 64; base < KW * 32; base += B_WG) {
+        for (u32 base = wv * 64; base < KW * 32; base += BW) {
             const u64 m = __ballot(pred(base + lane) ? 1 : 0);
             if (lane == 0) {
                 s.rootb[base >> 5] = u32(m);
@@ -1049,7 +1050,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             sw[i] = w < WORDS ? __popc(run_starts(s.bm, w)) : 0u;
             cnt += sw[i];
         }
-        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, nruns);
+        u32 run = group_excl_scan<BW>(cnt, tid, s.wsum, nruns);
 #pragma unroll
         for (u32 i = 0; i < WPT; ++i) {
             const u32 w = tid * WPT + i;
@@ -1057,7 +1058,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             run += sw[i];
         }
     }
-    for (u32 r = tid; r < nruns; r += B_WG) s.par[r] = r;
+    for (u32 r = tid; r < nruns; r += BW) s.par[r] = r;
     lds_barrier();
     // Unions from the bitmap only.  Wave v links the runs of its block of columns to the
     // next column, one column at a time from left to right, a lane per run start row.
@@ -1065,7 +1066,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     // column, so the trees stay shallow even along chains that cross the module (a
     // serpentine); unordered unions would build paths as long as the chain.
     {
-        constexpr u32 NWV = B_WG / 64;
+        constexpr u32 NWV = BW / 64;
         const u32 c0 = wv * COLS / NWV, c1 = (wv + 1) * COLS / NWV;
         for (u32 col = c0; col < c1; ++col) {
             for (u32 r0 = lane; r0 < ROWS; r0 += 64) {
@@ -1079,7 +1080,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     lds_barrier();
     // flatten: every run points at its root.  Walks only read, and each store writes a
     // root, so a concurrent walk through a stored entry still ends at the same root.
-    for (u32 r = tid; r < nruns; r += B_WG) {
+    for (u32 r = tid; r < nruns; r += BW) {
         u32 x = ld_wg(&s.par[r]);
         for (u32 it = 0; it < MAX_RUNS; ++it) {
             const u32 y = ld_wg(&s.par[x]);
@@ -1101,7 +1102,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             sw[i] = w < KW ? __popc(s.rootb[w]) : 0u;
             cnt += sw[i];
         }
-        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, ncl);
+        u32 run = group_excl_scan<BW>(cnt, tid, s.wsum, ncl);
 #pragma unroll
         for (u32 i = 0; i < KPT; ++i) {
             const u32 w = tid * KPT + i;
@@ -1111,7 +1112,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     }
     lds_barrier();
     // per cluster: id from the start of its root run; zero the sums
-    for (u32 w = tid; w < WORDS; w += B_WG) {
+    for (u32 w = tid; w < WORDS; w += BW) {
         u32 sb = run_starts(s.bm, w);
         u32 r = s.rpre[w];
         while (sb) {
@@ -1153,7 +1154,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             sw[i] = w < KW ? __popc(s.rootb[w]) : 0u;
             cnt += sw[i];
         }
-        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, Kc);
+        u32 run = group_excl_scan<BW>(cnt, tid, s.wsum, Kc);
         u32 keep_pre[KPT];
 #pragma unroll
         for (u32 i = 0; i < KPT; ++i) {
@@ -1196,7 +1197,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             sw[i] = w < KW ? __popc(s.rootb[w]) : 0u;
             cnt += sw[i];
         }
-        u32 run = group_excl_scan<B_WG>(cnt, tid, s.wsum, tot);
+        u32 run = group_excl_scan<BW>(cnt, tid, s.wsum, tot);
 #pragma unroll
         for (u32 i = 0; i < KPT; ++i) {
             const u32 w = tid * KPT + i;
@@ -1213,53 +1214,76 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
         for (u32 u = 0; u < UNR; ++u) c[u] = lin[u] != NOPIX ? cluster_of(run_of(s.bm, s.rpre, lin[u])) : 0u;
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
-            const u32 j = base + u * B_WG + tid;
+            const u32 j = base + u * BW + tid;
             if (j < n) od[j] = lin[u] != NOPIX ? int32_t(ld_ag(&cid[c[u]])) : -1;
         }
     }
     if (err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, err);
     lds_barrier();                                              // every thread is done with the bitmap
-    for (u32 w = tid; w < WORDS; w += B_WG) s.bm[w] = 0u;
+    for (u32 w = tid; w < WORDS; w += BW) s.bm[w] = 0u;
     lds_barrier();
 }
 
+// Entry t of the launch's big-module (or scratch-mode) lists (prefix s_pref): the
+// module and its digis; ok when it is one the small kernel listed (above its
+// capacity).
+__device__ __forceinline__ Item big_item(const LaunchArgs& a, const u32* s_pref, u32 k, u32 t, bool scr) {
+    Item I{0, 0, 0, 0, 0, false};
+    I.e = find_slot(s_pref, k, t);
+    const EventDesc E = get_event(a, I.e);
+    const EvLayout L = ev_layout(E.cap, a.n_modules);
+    I.mod = I.it = ws_ptr<const u32>(E, scr ? L.scr : L.big)[t - s_pref[I.e]];
+    if (I.mod < a.n_modules) {
+        const ModRange r = ws_ptr<const ModRange>(E, L.mtab)[I.mod];
+        const u32 st = u32(r.first), en = u32(r.end);
+        if (u32(r.first >> 32) == E.epoch && u32(r.end >> 32) == E.epoch && st < en && en <= E.n) {
+            I.st = st;
+            I.n = en - st;
+            I.ok = scr ? I.n > BIG_RCAP : (I.n > a.dcap && I.n <= BIG_RCAP);
+        }
+    }
+    if (!I.ok && threadIdx.x == 0) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, EB_INTERNAL);
+    return I;
+}
+
+// big, register mode: the modules of the big-module list (above the small kernel's
+// capacity, up to BIG_RCAP digis)
 __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
-    __shared__ BigSmem s;
+    __shared__ RegModuleSmem<B_WG, K_BIG> s;
     __shared__ u32 s_pref[MAXB + 1];
     __shared__ u32 s_wsum[B_WG / 64];
     const u32 tid = threadIdx.x;
-    for (u32 w = tid; w < WORDS; w += B_WG) s.reg.bm[w] = 0u;   // bm leads both layouts
-    if (tid < CMW) s.reg.cm[tid] = 0u;
+    for (u32 w = tid; w < WORDS; w += B_WG) s.bm[w] = 0u;
+    if (tid < CMW) s.cm[tid] = 0u;
     const u32 k = num_events(a);
     const u32 total = event_prefix<B_WG>(a, k, s_pref, s_wsum, CTL_BIG, 1, 0);
     for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
-        Item I{0, 0, 0, 0, 0, false};
-        I.e = find_slot(s_pref, k, t);
+        const Item I = big_item(a, s_pref, k, t, false);
+        if (!I.ok) continue;
         const EventDesc E = get_event(a, I.e);
         const EvLayout L = ev_layout(E.cap, a.n_modules);
-        I.mod = I.it = ws_ptr<const u32>(E, L.big)[t - s_pref[I.e]];
-        if (I.mod < a.n_modules) {
-            const ModRange r = ws_ptr<const ModRange>(E, L.mtab)[I.mod];
-            const u32 st = u32(r.first), en = u32(r.end);
-            if (u32(r.first >> 32) == E.epoch && u32(r.end >> 32) == E.epoch && st < en && en <= E.n) {
-                I.st = st;
-                I.n = en - st;
-                I.ok = I.n > a.dcap;                   // listed by the small kernel as too large for it
-            }
-        }
-        if (!I.ok) {
-            if (tid == 0) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, EB_INTERNAL);
-            continue;
-        }
-        if (I.n <= BIG_RCAP) {
-            u32 R[K_BIG], C[K_BIG], A[K_BIG];
-            fetch_digis<B_WG, K_BIG>(E, I, tid, R, C, A);
-            cluster_regs<B_WG, K_BIG>(a, E, L, I, s.reg, tid, R, C, A, [](int) {});
-        } else {
-            cluster_scratch(a, E, L, I, s.scr);
-            if (tid < CMW) s.reg.cm[tid] = 0u;                 // the scratch layout overlaps it
-            lds_barrier();
-        }
+        u32 R[K_BIG], C[K_BIG], A[K_BIG];
+        fetch_digis<B_WG, K_BIG>(E, I, tid, R, C, A);
+        cluster_regs<B_WG, K_BIG>(a, E, L, I, s, tid, R, C, A, [](int) {});
+    }
+}
+
+// big, scratch mode: the modules of the scratch-mode list (above BIG_RCAP digis), in
+// workgroups of S_WG threads (more waves for the column-ordered unions, a chain of
+// steps per wave)
+__global__ __launch_bounds__(S_WG) void k_scratch(LaunchArgs a) {
+    __shared__ BigScratchSmem<S_WG> s;
+    __shared__ u32 s_pref[MAXB + 1];
+    __shared__ u32 s_wsum[S_WG / 64];
+    const u32 tid = threadIdx.x;
+    for (u32 w = tid; w < WORDS; w += S_WG) s.bm[w] = 0u;
+    const u32 k = num_events(a);
+    const u32 total = event_prefix<S_WG>(a, k, s_pref, s_wsum, CTL_SCR, 1, 0);
+    for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
+        const Item I = big_item(a, s_pref, k, t, true);
+        if (!I.ok) continue;
+        const EventDesc E = get_event(a, I.e);
+        cluster_scratch<S_WG>(a, E, ev_layout(E.cap, a.n_modules), I, s);
     }
 }
 
@@ -1306,7 +1330,8 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             if (lane == 0) {
                 const u32 err = ctl[CTL_ERR];
                 ctl[CTL_ERR] = 0u;
-                ctl[CTL_BIG] = 0u;                         // the big kernel has run
+                ctl[CTL_BIG] = 0u;                         // the big kernels have run
+                ctl[CTL_SCR] = 0u;
                 ctl[CTL_NCL] = ncl;
                 u32* hs = E.hstat;
                 st_sys(&hs[HS_ERR], err);
@@ -1458,6 +1483,7 @@ int occupancy_cluster(u32 wg, u32 mpw) {
     return f ? occ(reinterpret_cast<const void*>(f), int(wg)) : 0;
 }
 int occupancy_big() { return occ(reinterpret_cast<const void*>(k_big), B_WG); }
+int occupancy_scratch() { return occ(reinterpret_cast<const void*>(k_scratch), S_WG); }
 int occupancy_compact() { return occ(reinterpret_cast<const void*>(k_compact), C_WG); }
 
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s) {
@@ -1471,8 +1497,12 @@ hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStrea
     hipLaunchKernelGGL(f, dim3(grid), dim3(wg), 0, s, a);
     return hipGetLastError();
 }
-hipError_t launch_big(const LaunchArgs& a, u32 grid, hipStream_t s) {
+// The two big-module kernels (register mode, then scratch mode unless LF_NO_SCRATCH).
+hipError_t launch_big(const LaunchArgs& a, u32 grid, u32 grid_scratch, hipStream_t s) {
     hipLaunchKernelGGL(k_big, dim3(grid), dim3(B_WG), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || (a.flags & LF_NO_SCRATCH)) return e;
+    hipLaunchKernelGGL(k_scratch, dim3(grid_scratch), dim3(S_WG), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s) {

@@ -36,7 +36,8 @@ int occupancy_big();
 int occupancy_compact();
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStream_t s);
-hipError_t launch_big(const LaunchArgs& a, u32 grid, hipStream_t s);
+hipError_t launch_big(const LaunchArgs& a, u32 grid, u32 grid_scratch, hipStream_t s);
+int occupancy_scratch();
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
 int occupancy_hits();
 hipError_t launch_hits(const LaunchArgs& a, u32 grid, hipStream_t s);
@@ -98,7 +99,7 @@ struct pxcl_ctx {
     u32 n_cu = 0;
     std::string arch;
     std::atomic<u32> wg{256}, mpw{1};
-    int occ_a = 1, occ_l = 1, occ_c = 1, occ_h = 1;
+    int occ_a = 1, occ_l = 1, occ_c = 1, occ_h = 1, occ_x = 1;
     int occ_s[4][5] = {};               // small kernel per shape [log2(wg) - 6][mpw], queried once
     std::atomic<int> bound{0};
     std::atomic<int> timing{0};
@@ -167,9 +168,11 @@ struct pxcl_batch {
     void* user = nullptr;
     hipEvent_t done_ev = nullptr;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    u32 g_wg = 0, g_mpw = 0, g_flags = 0;
+    // captured pipelines, one per combination of the launch flags that change it
+    // (LF_NO_BIG, LF_SEG_WIDE, LF_NO_SCRATCH), all for the kernel shape g_wg x g_mpw
+    hipGraphExec_t gexec[8] = {};
+    hipGraph_t graph[8] = {};
+    u32 g_wg = 0, g_mpw = 0;
     u32 launches = 0;
     u32 timed_flags = 0;
     hipEvent_t tev[5] = {};
@@ -182,7 +185,7 @@ struct pxcl_batch {
 namespace {
 
 struct Grids {
-    u32 a, b, s, c;   // segment, big, small, compact
+    u32 a, b, s, c, x;   // segment, big, small, compact, scratch
 };
 
 // Wide segmentation chunks once a launch holds at least one of them per compute
@@ -202,14 +205,19 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
     const u64 fb = ncu * (u64)ctx->occ_l;
     const u64 fs = ncu * (u64)ctx->occ_s[31 - __builtin_clz(wg) - 6][mpw];
     const u64 fc = ncu * (u64)ctx->occ_c;
+    // modules above BIG_RCAP digis are rare outliers (one per stress event): the scratch
+    // kernel's workgroups, each holding a whole compute unit's LDS, are capped at a
+    // quarter of the chip, the rest loop
+    const u64 fx = std::min<u64>(ncu * (u64)ctx->occ_x, std::max<u64>(ncu / 4, 1));
     if (full) {
-        g.a = u32(fa); g.b = u32(fb); g.s = u32(fs); g.c = u32(fc);
+        g.a = u32(fa); g.b = u32(fb); g.s = u32(fs); g.c = u32(fc); g.x = u32(fx);
         return g;
     }
     const u32 dcap = cluster_capacity(wg, mpw);
     const u64 ch = seg_chunk(flags);
     g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + ch - 1) / ch + k)));
     g.b = u32(std::max<u64>(1, std::min<u64>(fb, digis / (dcap + 1))));
+    g.x = u32(std::max<u64>(1, std::min<u64>(fx, digis / (BIG_RCAP + 1))));
     g.s = u32(std::max<u64>(1, std::min<u64>(fs, (present + mpw - 1) / mpw)));
     g.c = u32(std::max<u64>(1, std::min<u64>(fc, (present + k + C_WG / 64 - 1) / (C_WG / 64))));
     return g;
@@ -222,7 +230,7 @@ hipError_t launch_all(const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipS
     if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
     if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;   // lists the big modules
     if (tev && (e = hipEventRecord(tev[2], s)) != hipSuccess) return e;
-    if (!(a.flags & LF_NO_BIG) && (e = launch_big(a, g.b, s)) != hipSuccess) return e;
+    if (!(a.flags & LF_NO_BIG) && (e = launch_big(a, g.b, g.x, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[3], s)) != hipSuccess) return e;
     if ((e = launch_compact(a, g.c, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[4], s)) != hipSuccess) return e;
@@ -383,6 +391,7 @@ extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** ou
         for (u32 m = 1; m <= 4; m *= 2)
             if (cluster_config_valid(w, m)) c->occ_s[31 - __builtin_clz(w) - 6][m] = occupancy_cluster(w, m);
     c->occ_l = occupancy_big();
+    c->occ_x = occupancy_scratch();
     c->occ_c = occupancy_compact();
     c->occ_h = occupancy_hits();
     hipSetDevice(prev);
@@ -555,6 +564,7 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.charge_cut = ctx->charge_cut;
     a.dcap = cluster_capacity(wg, mpw);
     if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
+    if (in->max_module_digis && in->max_module_digis <= BIG_RCAP) a.flags |= LF_NO_SCRATCH;
     a.flags |= LF_FUSED;                       // one event: ranges by search, no segmentation kernel
     hipError_t e = make_desc(ev, in, s, &a.single);
     ev->desc = a.single;
@@ -948,18 +958,24 @@ extern "C" int pxcl_batch_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     return PXCL_OK;
 }
 
-static void drop_graph(pxcl_batch* b) {
-    if (b->gexec) hipGraphExecDestroy(b->gexec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    b->gexec = nullptr;
-    b->graph = nullptr;
+static void drop_graphs(pxcl_batch* b) {
+    for (int i = 0; i < 8; ++i) {
+        if (b->gexec[i]) hipGraphExecDestroy(b->gexec[i]);
+        if (b->graph[i]) hipGraphDestroy(b->graph[i]);
+        b->gexec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
+}
+
+static u32 graph_slot(u32 flags) {
+    return ((flags & LF_NO_BIG) ? 1u : 0u) | ((flags & LF_SEG_WIDE) ? 2u : 0u) | ((flags & LF_NO_SCRATCH) ? 4u : 0u);
 }
 
 extern "C" int pxcl_batch_unbind(pxcl_batch* b) {
     if (!b) return PXCL_E_INVAL;
     if (b->state.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
     if (b->timed) { b->timed = false; add_timing(b->ctx, b->tev, b->timed_flags); }
-    drop_graph(b);
+    drop_graphs(b);
     hipEventDestroy(b->done_ev);
     for (int i = 0; i < 5; ++i) hipEventDestroy(b->tev[i]);
     hipStreamDestroy(b->cap_stream);
@@ -979,11 +995,18 @@ static LaunchArgs batch_args(pxcl_batch* b, u32 wg, u32 mpw) {
     return a;
 }
 
-// Capture the per-batch pipeline (header copy + four kernels, full grids) once per
-// kernel configuration; replays read k and the event descriptors from the header.
-static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, u32 flags) {
-    if (b->gexec && b->g_wg == wg && b->g_mpw == mpw && b->g_flags == flags) return hipSuccess;
-    drop_graph(b);
+// Capture the per-batch pipeline (header copy + kernels, full grids) once per kernel
+// configuration and flag combination, so that launches whose flags alternate reuse
+// their graphs; replays read k and the event descriptors from the header.
+static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, u32 flags, hipGraphExec_t* out) {
+    if (b->g_wg != wg || b->g_mpw != mpw) {
+        drop_graphs(b);
+        b->g_wg = wg;
+        b->g_mpw = mpw;
+    }
+    const u32 gs = graph_slot(flags);
+    *out = b->gexec[gs];
+    if (*out) return hipSuccess;
     pxcl_ctx* ctx = b->ctx;
     LaunchArgs a = batch_args(b, wg, mpw);
     a.flags = flags;
@@ -993,14 +1016,15 @@ static hipError_t ensure_graph(pxcl_batch* b, u32 wg, u32 mpw, u32 flags) {
     if (e != hipSuccess) return e;
     hipError_t e2 = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(b->max_events), hipMemcpyHostToDevice, cs);
     if (e2 == hipSuccess) e2 = launch_all(a, g, wg, mpw, cs, nullptr);
-    e = hipStreamEndCapture(cs, &b->graph);
-    if (e2 != hipSuccess) { if (b->graph) hipGraphDestroy(b->graph); b->graph = nullptr; return e2; }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (e2 != hipSuccess) { if (graph) hipGraphDestroy(graph); return e2; }
     if (e != hipSuccess) return e;
-    e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) { drop_graph(b); return e; }
-    b->g_wg = wg;
-    b->g_mpw = mpw;
-    b->g_flags = flags;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { hipGraphDestroy(graph); return e; }
+    b->graph[gs] = graph;
+    b->gexec[gs] = *out = exec;
     return hipSuccess;
 }
 
@@ -1045,11 +1069,12 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     hipError_t e = hipSuccess;
     u64 digis = 0, present = 0;
     const u32 dcap = cluster_capacity(wg, mpw);
-    u32 lflags = LF_NO_BIG;                     // unless an event may hold a big module
+    u32 lflags = LF_NO_BIG | LF_NO_SCRATCH;     // unless an event may hold a big module
     for (u32 i = 0; i < k && e == hipSuccess; ++i) {
         pxcl_event* ev = evs[i];
         b->evs[i] = ev;
-        if (!ins[i].max_module_digis || ins[i].max_module_digis > dcap) lflags = 0;
+        if (!ins[i].max_module_digis || ins[i].max_module_digis > dcap) lflags &= ~LF_NO_BIG;
+        if (!ins[i].max_module_digis || ins[i].max_module_digis > BIG_RCAP) lflags &= ~LF_NO_SCRATCH;
         ev->epoch = next_epoch();
         ev->n = ins[i].n;
         ev->cb = nullptr;
@@ -1068,8 +1093,9 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     lflags |= seg_flag(ctx, digis);
     if (e == hipSuccess) {
         if (flags & PXCL_BATCH_GRAPH) {
-            e = ensure_graph(b, wg, mpw, lflags);
-            if (e == hipSuccess) e = hipGraphLaunch(b->gexec, s);
+            hipGraphExec_t exec = nullptr;
+            e = ensure_graph(b, wg, mpw, lflags, &exec);
+            if (e == hipSuccess) e = hipGraphLaunch(exec, s);
         } else {
             LaunchArgs a = batch_args(b, wg, mpw);
             a.flags = lflags;

@@ -331,7 +331,7 @@ class Event:
 def acquire(event: Event, digis: Digis, stream=None, done_cb: Optional[Callable[[int], None]] = None,
             flag: Optional[Flag] = None) -> None:
     """Enqueue the clustering of one event; returns without waiting.  ``done_cb``
-    (a Python callable, called with the status from a HIP runtime thread) or
+    (a Python callable, called with the status from the context's completion thread) or
     ``flag`` (filled by the library's own callback) signal completion."""
     d = digis.struct()
     cb_ptr, user = None, None

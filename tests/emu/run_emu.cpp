@@ -91,7 +91,7 @@ int main(int argc, char** argv) {
         memset(a.ctr, 0, 64);
     }
     if ((!(a.flags & LF_FUSED) && launch_segment(a, h[5], nullptr)) || launch_small(h[3], h[4], a, h[7], nullptr) ||
-        (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], nullptr)) || launch_compact(a, h[8], nullptr)) {
+        (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], h[6], nullptr)) || launch_compact(a, h[8], nullptr)) {
         fprintf(stderr, "launch failed\n");
         return 3;
     }

@@ -85,23 +85,23 @@ def test_wide_segmentation_chunks(emulator):
 def _single_events():
     """One-event launches of every kind the search must get right: a plain event, one
     with a module above the small kernel's capacity, an empty one, one whose module 0
-    is absent, and one with a few modules far apart in 700."""
+    is absent, and one with a few modules far apart in 300."""
     big = _mixed_events()[2]
     empty = {k: np.zeros(0, np.uint16) for k in ("module", "row", "col", "adc")}
     mods, rows, cols = [], [], []
-    for m, npx in ((0, 5), (300, 40), (301, 600), (302, 3), (699, 12)):
+    for m, npx in ((0, 5), (150, 40), (151, 600), (152, 3), (299, 12)):
         lin = (np.arange(npx) * 37 + m) % (160 * 416)
         mods.append(np.full(npx, m))
         rows.append(lin % 160)
         cols.append(lin // 160)
-    far = synth.from_pixels(np.concatenate(mods), np.concatenate(rows), np.concatenate(cols), n_modules=700, seed=8)
+    far = synth.from_pixels(np.concatenate(mods), np.concatenate(rows), np.concatenate(cols), n_modules=300, seed=8)
     late = synth.plain_event(4, n_modules=6)
     late = {k: v[late["module"] > 0] if isinstance(v, np.ndarray) else v for k, v in late.items()}
-    evs = [(synth.plain_event(0, n_modules=8), 8), (big, 6), (empty, 6), (late, 6), (far, 700)]
+    evs = [(synth.plain_event(0, n_modules=8), 8), (big, 6), (empty, 6), (late, 6), (far, 300)]
     return [(dict(e, n_modules=m), m) for e, m in evs]
 
 
-@pytest.mark.parametrize("wg,mpw", [(64, 1), (128, 2), (256, 4), (512, 1)])
+@pytest.mark.parametrize("wg,mpw", [(64, 1), (256, 4), (512, 1)])
 def test_fused_single_event(emulator, wg, mpw):
     """Without the segmentation kernel: module ranges by search, module ids checked,
     module table entries and kept counts written by the small kernel."""

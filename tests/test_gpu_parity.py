@@ -232,6 +232,33 @@ def test_size_hint(px):
     ctx.close()
 
 
+def test_size_hint_scratch_mode(px):
+    """A bound of at most 16,384 digis skips the scratch-mode kernel; a module above a
+    wrong bound (20,000 digis under a bound of 16,384) fails the event with E_HINT, and
+    with a right bound or none the scratch kernel clusters it exactly."""
+    lin = (np.arange(20000) * 37) % (160 * 416)
+    ev = synth.from_pixels(np.concatenate([np.zeros(50, np.int64), np.full(20000, 2)]),
+                           np.concatenate([np.arange(50) * 3 % 160, lin % 160]),
+                           np.concatenate([np.arange(50) * 7 % 416, lin // 160]), n_modules=4, seed=6)
+    ref = oracle.cluster_event(ev, 2000)
+    ctx = _ctx(px, 4)
+    slot = px.Event(ctx, ev["module"].size)
+    for name, hint in [("right bound", 20000), ("no bound", None), ("wrong bound", 16384)]:
+        d = px.Digis.from_numpy(ev, "cuda", hint=hint is not None)
+        if hint is not None:
+            d.max_module_digis = hint
+        print(f"scratch hint: {name}", flush=True)
+        px.acquire(slot, d)
+        px.wait(slot)
+        r = px.produce(slot).numpy()
+        if name == "wrong bound":
+            assert r["status"] == px.E_HINT and r["n_clusters"] <= ev["module"].size
+        else:
+            compare(r, ref, name)
+    slot.close()
+    ctx.close()
+
+
 def test_full_size_async_and_stress(px):
     """Full-size events of the asynchronous and the stress configurations."""
     ctx = _ctx(px, 1856)

@@ -70,6 +70,39 @@ def test_acquire_returns_before_completion(px):
     ctx.close()
 
 
+def test_callback_may_acquire_again_not_destroy(px):
+    """Completion callbacks run on the context's completion thread: one may produce and
+    acquire the event again (that launch completes normally) but may not destroy the
+    context (E_BUSY, the context stays usable)."""
+    ev = synth.plain_event(5)
+    ref = oracle.cluster_event(ev, 2000)
+    ctx = px.Context(ev["n_modules"], 2000)
+    slot = px.Event(ctx, ev["module"].size)
+    d = px.Digis.from_numpy(ev, "cuda")
+    seen = {}
+    again = px.Flag()
+
+    def cb(st):
+        seen["status"] = st
+        try:
+            ctx.close()
+        except px.PxclError as e:
+            seen["close"] = e.code
+        seen["n"] = px.produce(slot).n_clusters
+        px.acquire(slot, d, flag=again)
+
+    px.acquire(slot, d, done_cb=cb)
+    t0 = time.time()
+    while again.fired == 0:
+        assert time.time() - t0 < 30, "the second launch did not complete"
+        time.sleep(0.001)
+    px.wait(slot)
+    assert seen == {"status": 0, "close": px.E_BUSY, "n": ref["n_clusters"]}
+    compare(px.produce(slot).numpy(), ref, "acquired in the callback")
+    slot.close()
+    ctx.close()
+
+
 def test_synchronous_errors(px):
     ctx = px.Context(64)
     slot = px.Event(ctx, 100)
