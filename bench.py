@@ -29,6 +29,9 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 KERNELS = ["segment", "big", "small", "compact", "hits"]
 KERNEL_SYMBOLS = {"segment": "k_segment", "big": "k_big", "small": "k_small", "compact": "k_compact", "hits": "k_hits"}
+# kernels behind each timing slot: the big-module slot times register and scratch mode
+KERNEL_PARTS = {"big": ["k_big", "k_scratch"]}
+ALL_SYMBOLS = list(KERNEL_SYMBOLS.values()) + ["k_scratch"]
 
 
 def event_bytes(n_digis: int, n_kept: int) -> int:
@@ -43,15 +46,20 @@ def kernel_src_sha() -> str:
 
 
 def load_traffic(workload: str, kernel: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"pmc_{KERNEL_SYMBOLS[kernel]}_{workload}.json")
-    if not os.path.exists(p):
-        return None
-    d = json.load(open(p))
-    if d.get("kernel_src_sha") != kernel_src_sha():
-        return None
-    return d.get("traffic_bytes_per_launch")
+    """HBM traffic per launch from the committed rocprofv3 counter summaries of the
+    kernels behind a timing slot, if they were taken on the current kernel source
+    (a kernel without a summary did not run in that workload)."""
+    total, found = 0, False
+    for sym in KERNEL_PARTS.get(kernel, [KERNEL_SYMBOLS[kernel]]):
+        p = os.path.join(ROOT, "profiles", f"pmc_{sym}_{workload}.json")
+        if not os.path.exists(p):
+            continue
+        d = json.load(open(p))
+        if d.get("kernel_src_sha") != kernel_src_sha():
+            return None
+        total += d.get("traffic_bytes_per_launch", 0)
+        found = True
+    return total if found else None
 
 
 def roofline(ctx, bytes_per_launch: float, workload: str):
@@ -65,7 +73,8 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
     achieved = bytes_per_launch / t / 1e9 if t > 0 else 0.0
     pipe = sum(avg.values()) * 1e-3
     return {
-        "bound": "hbm", "kernel": KERNEL_SYMBOLS[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "bound": "hbm", "kernel": "+".join(KERNEL_PARTS.get(dom, [KERNEL_SYMBOLS[dom]])), "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": load_traffic(workload, dom),
         "algorithmic_bytes_per_launch": int(bytes_per_launch),
@@ -149,7 +158,7 @@ def _read_csv(path):
 
 
 def _short(name: str) -> str:
-    for k in KERNEL_SYMBOLS.values():
+    for k in ALL_SYMBOLS:
         if f"::{k}(" in name or f"::{k}<" in name:
             return k
     return name
@@ -187,7 +196,7 @@ def summarize_profiles(prof: str, workload: str, command: dict):
     fetch, write = per_kernel("fetch"), per_kernel("write")
     ff, fw = copy_factor("fetch"), copy_factor("write")
     sha = kernel_src_sha()
-    for k in KERNEL_SYMBOLS.values():
+    for k in ALL_SYMBOLS:
         if k not in fetch or k not in write:
             continue
         fk, nf = fetch[k]
@@ -200,7 +209,7 @@ def summarize_profiles(prof: str, workload: str, command: dict):
                           "copy_fetch": command["copy_fetch"], "copy_write": command["copy_write"]}}
         json.dump(d, open(os.path.join(out_dir, f"pmc_{k}_{workload}.json"), "w"), indent=1)
     print(json.dumps({"workload": workload, "fetch_scale": ff, "write_scale": fw,
-                      "kernels": {k: [fetch.get(k), write.get(k)] for k in KERNEL_SYMBOLS.values()}}))
+                      "kernels": {k: [fetch.get(k), write.get(k)] for k in ALL_SYMBOLS}}))
 
 
 def tune(px, ctx, args, events, digis, slots=None, batch=None):
