@@ -103,8 +103,9 @@ typedef struct {
  * unmodified until the done callback has fired.
  * max_module_digis: optional upper bound on the digis of any one module (0 =
  * unknown).  When it is at most the small-module kernel's capacity (workgroup size /
- * modules per workgroup * 8 digis), the big-module kernel is not launched; a module
- * above the bound is then not clustered and the event fails with PXCL_E_HINT. */
+ * modules per workgroup * 8 digis), neither big-module kernel is launched; when it
+ * is at most 16,384 the scratch-mode kernel is not launched.  A module above the
+ * bound is then not clustered and the event fails with PXCL_E_HINT. */
 typedef struct {
     const uint16_t* module;
     const uint16_t* row;
@@ -158,9 +159,11 @@ int pxcl_get_kernel_config(const pxcl_ctx* ctx, uint32_t* wg, uint32_t* mpw);
  * the default; 1: every launch).  Launches that replay a captured graph are never
  * timed: elapsed times of events recorded inside a captured graph are not
  * available.  Stats: for each of the 5 kernels (0 segmentation, 1 big-module
- * clustering, 2 small-module clustering, 3 compaction, 4 hits) the summed
- * milliseconds and the number of timed launches; a launch is counted once its event
- * (or its hits) is produced, or the event or batch object is used again or unbound. */
+ * clustering in register and scratch mode, 2 small-module clustering, 3 compaction,
+ * 4 hits) the summed milliseconds and the number of timed launches; a kernel a launch
+ * did not run (segmentation of single-event launches, big-module kernels skipped by
+ * the size hint) is not counted; a launch is counted once its event (or its hits) is
+ * produced, or the event or batch object is used again or unbound. */
 int pxcl_set_timing(pxcl_ctx* ctx, int period);
 int pxcl_get_timing(pxcl_ctx* ctx, double* ms_sum /*[5]*/, uint64_t* launches /*[5]*/, int reset);
 
@@ -185,8 +188,10 @@ int pxcl_event_unbind(pxcl_event* ev);
 uint32_t pxcl_event_capacity(const pxcl_event* ev);
 
 /* Enqueue the clustering of one event on `stream` (hipStream_t): an async copy of
- * host digis into the slot (PXCL_WHERE_HOST), the device kernels, and a host
- * callback.  Returns without waiting for the device.  Synchronous errors
+ * host digis into the slot (PXCL_WHERE_HOST), the device kernels (a single event
+ * needs no segmentation kernel: the small-module kernel finds every module's digis
+ * by search and checks the module ids itself), and a completion event that the
+ * context's completion thread polls.  Returns without waiting for the device.  Synchronous errors
  * (PXCL_E_INVAL, PXCL_E_CAPACITY, PXCL_E_BUSY, PXCL_E_HIP) mean nothing was queued
  * and `cb` will not be called; otherwise `cb` (may be NULL) fires exactly once. */
 int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, pxcl_done_cb cb,
