@@ -86,6 +86,7 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
 
 
 COPY_BYTES = 1 << 30
+SERVE_LOAD = 0.6           # serving: offered load as a fraction of the saturated rate
 N_STREAMS = 4              # streams the batched workloads spread their launches over
 
 
@@ -454,10 +455,11 @@ def bench_serve(px, torch, args, synth):
     tuned = tune(px, ctx, args, evs[:16], pool[:16])      # a typical continuous batch
     common = dict(budget_bytes=16 << 30, n_slots=n_slots, max_batch=max_batch, n_cpu_threads=16,
                   cpu_task_ns=args.cpu_task_ns, graph=True)
-    # calibration: saturated throughput (all requests arrive at once)
-    cal, _, _ = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=1e9, n_requests=4000, seed=7, **common)
+    # calibration: saturated throughput (all requests arrive at once, the largest
+    # batches); Poisson arrivals form smaller batches, so the offered load is 0.6 of it
+    cal, _, _ = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=1e9, n_requests=10000, seed=7, **common)
     sat = cal["events"] / cal["wall_s"]
-    rate = 0.7 * sat
+    rate = SERVE_LOAD * sat
     torch.cuda.synchronize()
     st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=rate,
                                n_requests=args.steps, seed=11, **common)
@@ -483,7 +485,7 @@ def bench_serve(px, torch, args, synth):
         "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
         "host_blocked_us_per_event": st["blocked_us_per_event"], "cpu_tasks_per_s": st["cpu_tasks_per_s"],
         "errors": st["errors"], "saturated_events_per_s": sat, "arrival_rate_hz": rate,
-        "config": {"workload": "serve: Poisson arrivals at 0.7x saturated rate, 10k-200k digis/event, "
+        "config": {"workload": f"serve: Poisson arrivals at {SERVE_LOAD}x saturated rate, 10k-200k digis/event, "
                                "16 GB admission budget, continuous batching over 4 streams, 16 CPU threads",
                    "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
                    "requests": args.steps, "mean_events_per_launch": round(args.steps / n_batches, 2),
