@@ -207,6 +207,8 @@ struct SlotPool {
 
 struct ServeState;
 
+constexpr double BATCH_DELAY_US = 300.0;   // longest wait for a fuller batch while others run
+
 struct BatchCtx {
     ServeState* S;
     u32 bi;
@@ -409,7 +411,14 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
             }
         }
         u32 mask = S.batch_free_mask.load(std::memory_order_acquire);
-        if (!admitted.empty() && mask) {
+        // While other batches are in flight, a batch waits to be half full or for its
+        // oldest request to have waited BATCH_DELAY_US: larger batches are what keeps
+        // up with arrivals; with nothing in flight it starts at once.
+        const u32 all = n_batches >= 32 ? 0xFFFFFFFFu : ((1u << n_batches) - 1u);
+        const bool ready = !admitted.empty() &&
+                           (mask == all || admitted.size() >= std::max<u32>(1, o->max_batch / 2) ||
+                            now - req[admitted.front()].arrival_us >= BATCH_DELAY_US);
+        if (ready && mask) {
             const u32 b = __builtin_ctz(mask);
             S.batch_free_mask.fetch_and(~(1u << b), std::memory_order_acq_rel);
             BatchCtx& bc = bctx[b];
