@@ -448,7 +448,7 @@ def bench_serve(px, torch, args, synth):
     ctx = px.Context(1856, 2000)
     pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
     arena = torch.empty(16 << 30, dtype=torch.uint8, device="cuda")
-    n_slots, n_b, max_batch = 512, 4, 64
+    n_slots, n_b, max_batch = 512, 8, 64
     pinned = torch.empty(n_slots * 64, dtype=torch.uint8, pin_memory=True)
     batches = [px.Batch(ctx, max_batch) for _ in range(n_b)]
     streams = [torch.cuda.Stream() for _ in range(n_b)]
@@ -486,7 +486,7 @@ def bench_serve(px, torch, args, synth):
         "host_blocked_us_per_event": st["blocked_us_per_event"], "cpu_tasks_per_s": st["cpu_tasks_per_s"],
         "errors": st["errors"], "saturated_events_per_s": sat, "arrival_rate_hz": rate,
         "config": {"workload": f"serve: Poisson arrivals at {SERVE_LOAD}x saturated rate, 10k-200k digis/event, "
-                               "16 GB admission budget, continuous batching over 4 streams, 16 CPU threads",
+                               "16 GB admission budget, continuous batching over 8 streams, 16 CPU threads",
                    "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
                    "requests": args.steps, "mean_events_per_launch": round(args.steps / n_batches, 2),
                    "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned,
