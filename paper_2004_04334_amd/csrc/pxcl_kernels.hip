@@ -1,23 +1,31 @@
 // Device kernels of the pixel-clustering path (gfx950 / CDNA4, wave64).
 //
-// One launch processes k >= 1 events through four kernels:
+// One launch processes k >= 1 events through these kernels, in this order:
 //
-//   segment  streams the module ids, scatters the first digi of every module
-//            present into a per-module table, checks module range and order; the
-//            workgroup that finishes an event's last chunk turns the table into
-//            the event's ordered list of modules ("items") and splits it into
-//            small and big items.
-//   big      one big module per 512-thread workgroup (digis held in registers
-//            up to 16,384 per module, beyond that re-read from memory).
-//   small    one small module per group of threads (a single wave, or a whole
+//   segment  (batches) streams the module ids; every digi at a module boundary
+//            writes the module's entry of a per-module table (first digi, one past
+//            the last, tagged with the launch), module starts go to a list of the
+//            modules present; checks module range and order.  A single-event
+//            launch has no segmentation kernel: the small kernel finds each
+//            module's digis by search and checks the ids itself.
+//   small    one module per group of threads (a single wave, or a whole
 //            workgroup): fired-pixel bitmap in LDS, vertical runs, union-find over
 //            runs, charge/size per cluster, charge cut; the module's kept clusters
 //            go in ascending id to a staging area at the module's first digi, and
-//            every digi gets its cluster id.  Groups take modules with an atomic
-//            ticket and prefetch the next module while working on the current one.
-//   compact  per event, the offset of each module's clusters (a sum over the
-//            kept counts of the modules before it) and a copy of the staged
-//            records to their final position; status write-back to the host.
+//            every digi gets its cluster id.  Modules above the group's capacity go
+//            to the big-module or the scratch-mode list.  Groups take modules by
+//            static rounds, then an atomic ticket, and prefetch the next module
+//            while working on the current one.
+//   big      one listed module per 512-thread workgroup, digis held in registers
+//            (up to 16,384 per module).
+//   scratch  one listed module above 16,384 digis per 1,024-thread workgroup, the
+//            digis re-read from memory in three passes.
+//   compact  a wave per module: the offset of its clusters (the kept counts of the
+//            modules before it) and a copy of its staged records to their final
+//            position; a wave per event writes the status back to the host.
+//
+// On demand, after a launch: hits, the charge-weighted centroid of every kept
+// cluster.
 //
 // The clustering: 8-connected components of fired pixels within a module; cluster
 // id = smallest linear index module*66560 + col*160 + row; charge = sum of ADC
@@ -26,11 +34,11 @@
 // asserts, which would synchronise (Sec. 4.1).
 //
 // Memory ordering.  Workgroup barriers here order LDS only (global loads and stores
-// stay in flight across them).  Data that another workgroup of the same kernel reads
-// is written with device-scope atomic stores and published by a device-scope atomic
-// counter after the writer has waited for its stores to complete; everything else
-// crosses a kernel boundary.  No device-scope release/acquire fence is used: on
-// gfx950 those write back and invalidate the L2.
+// stay in flight across them).  No workgroup reads what another workgroup of the same
+// kernel writes: data crosses kernel boundaries, and the only device-scope atomics
+// are counters whose returned values serve as indexes (tickets, list places).  No
+// device-scope release/acquire fence is used: on gfx950 those write back and
+// invalidate the L2.
 #include <hip/hip_runtime.h>
 
 #include "pxcl_internal.h"
@@ -817,7 +825,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     // group's index) for about three quarters of the work, the rest comes from a
     // ticket counter, which every group contends for.  The ticket of the module after
     // next is drawn while the current one is clustered, and the next module's
-    // work-list entry and digis are loaded meanwhile.
+    // table entry (or range, by search) and digis are loaded meanwhile.
     const u32 per_round = gridDim.x * MPW;
     u32 base = blockIdx.x * MPW + (WAVE ? g : 0u);
     EventDesc E{};

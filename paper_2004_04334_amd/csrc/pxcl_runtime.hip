@@ -1,7 +1,7 @@
 // Host runtime of the pixel-clustering library: the C ABI of include/pxcl.h.
 //
 // acquire() only validates, stages host inputs with async copies, launches the
-// four kernels on the caller's stream and records a completion event -- the split
+// kernels on the caller's stream and records a completion event -- the split
 // of a module's work into acquire/produce with a completion callback that releases
 // the waiting task (paper Sec. 2 and Sec. 4.1).  The callback runs on the context's
 // completion thread, which polls the completion events of the launches in flight:
@@ -194,7 +194,7 @@ static u32 seg_flag(const pxcl_ctx* ctx, u64 digis) {
     return digis >= (u64)ctx->n_cu * seg_chunk(LF_SEG_WIDE) ? LF_SEG_WIDE : 0u;
 }
 
-// Grids of the four kernels.  `digis` bounds the launch's digis and `present` its
+// Grids of the kernels.  `digis` bounds the launch's digis and `present` its
 // modules present (at most min(digis, modules) per event); with `full` (a captured
 // graph replays with any input)
 // every kernel gets what fits on the device at once.
