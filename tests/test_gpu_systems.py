@@ -164,6 +164,42 @@ def test_batch_identity_alone_batch_graph(px, batch_events):
     ctx.close()
 
 
+def test_graph_per_flag_combination(px):
+    """One batch object replayed with launches whose flags alternate (size hints that
+    skip the big-module kernels, none, a bound that skips only the scratch kernel, and
+    a module above 16,384 digis): each combination has a captured graph of its own, and
+    every replay matches the oracle."""
+    import torch
+    lin = (np.arange(20000) * 37) % (160 * 416)
+    huge = synth.from_pixels(np.concatenate([np.zeros(50, np.int64), np.full(20000, 2)]),
+                             np.concatenate([np.arange(50) * 3 % 160, lin % 160]),
+                             np.concatenate([np.arange(50) * 7 % 416, lin // 160]), n_modules=1856, seed=6)
+    small = [synth.batch_event(70 + i) for i in range(3)]      # largest module 3,328 digis
+    plains = [synth.plain_event(80 + i) for i in range(3)]     # 733 digis per module
+    # flags: NO_SCRATCH; none; NO_BIG | NO_SCRATCH; none (a module of 20,000 digis); ...
+    cases = [(small, True), (small, False), (plains, True), (small + [huge], True), (plains, True),
+             (small, True), (small + [huge], False), (small, False)]
+    refs = {id(e): oracle.cluster_event(e, 2000) for e in small + plains + [huge]}
+    ctx = px.Context(1856, 2000)
+    ctx.set_kernel_config(256, 1)
+    b = px.Batch(ctx, 4)
+    cap = max(e["module"].size for e in small + plains + [huge])
+    slots = [px.Event(ctx, cap) for _ in range(4)]
+    for rep, (evs, hint) in enumerate(cases):
+        print(f"graph flags case {rep}", flush=True)
+        digis = [px.Digis.from_numpy(e, "cuda", hint=hint) for e in evs]
+        px.acquire_batch(b, slots[:len(evs)], digis, graph=True)
+        for s in slots[:len(evs)]:
+            px.wait(s)
+        torch.ones(1000, device="cuda").sum().item()
+        for i, (s, e) in enumerate(zip(slots, evs)):
+            compare(px.produce(s).numpy(), refs[id(e)], f"case {rep} event {i}")
+    for s in slots:
+        s.close()
+    b.close()
+    ctx.close()
+
+
 def test_full_batch_of_64(px):
     """Batching configuration at full size: 64 events, one captured-graph launch."""
     evs = [synth.batch_event(100 + i) for i in range(64)]
