@@ -1325,7 +1325,18 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
     const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const u32 k = num_events(a), M = a.n_modules;
     if (blockIdx.x == 0 && tid == 0) st_ag(&a.ctr[S_TICK], 0u);   // the small kernel has finished
-    const u32 total = event_prefix<C_WG>(a, k, s_pref, s_wsum, CNT_UNITS, 1, 0, 1);   // + status unit
+    u32 total;
+    if (k == 1 && (a.flags & LF_FUSED)) {         // every module a unit, no count to load
+        const EventDesc E0 = get_event(a, 0);
+        total = (E0.n ? M : 0u) + 1u;
+        if (tid == 0) {
+            s_pref[0] = 0;
+            s_pref[1] = total;
+        }
+        lds_barrier();
+    } else {
+        total = event_prefix<C_WG>(a, k, s_pref, s_wsum, CNT_UNITS, 1, 0, 1);       // + status unit
+    }
     for (u32 u = wave_uniform(blockIdx.x * C_WAVES + wv); u < total; u += gridDim.x * C_WAVES) {
         const u32 e = wave_uniform(find_slot(s_pref, k, u));
         const u32 j = u - s_pref[e], np = s_pref[e + 1] - s_pref[e] - 1;

@@ -823,6 +823,14 @@ static void completer_loop(pxcl_completer* c, int device) {
             const hipError_t q = hipEventQuery(mine[i].done);
             if (q == hipErrorNotReady) { ++i; continue; }
             if (q != hipSuccess) (void)hipGetLastError();
+            // hits and copies read an event's results: their completion follows the
+            // event's own (whose work has finished too, by stream order or the wait
+            // on its completion event, so it is processed in this pass or the next)
+            if ((mine[i].kind == CK_HITS || mine[i].kind == CK_COPY) &&
+                static_cast<pxcl_event*>(mine[i].obj)->state.load(std::memory_order_acquire) == ST_INFLIGHT) {
+                ++i;
+                continue;
+            }
             const Pending p = mine[i];
             mine[i] = mine.back();
             mine.pop_back();

@@ -83,6 +83,29 @@ def test_hits_on_another_stream_while_in_flight(px):
     ctx.close()
 
 
+def test_hits_complete_after_their_event(px):
+    """A hits launch on the event's stream finishes right after the event: its
+    completion is still delivered after the event's own (the event reads complete in
+    the hits callback), every time."""
+    import torch
+    ev = synth.async_event(12)
+    ctx = px.Context(1856, 2000)
+    slot = px.Event(ctx, ev["module"].size)
+    d = px.Digis.from_numpy(ev, "cuda")
+    s = torch.cuda.Stream()
+    seen = []
+    for i in range(200):
+        px.acquire(slot, d, s)
+        px.hits_enqueue(slot, s, done_cb=lambda st: seen.append((st, px.query(slot))))
+        px.hits_wait(slot)
+        px.wait(slot)
+        px.produce(slot)
+        px.hits_produce(slot)
+    assert seen == [(0, px.OK)] * 200
+    slot.close()
+    ctx.close()
+
+
 def test_hits_after_batch(px):
     import torch
     evs = [synth.batch_event(40 + i) for i in range(6)]
