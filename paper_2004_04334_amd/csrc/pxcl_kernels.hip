@@ -616,6 +616,18 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware order of workgroups: consecutive workgroup ids go to the eight XCDs in
+// turn, so the order (id % 8, id / 8) gives each XCD a contiguous share of the work
+// and the data its modules read and write stays in that XCD's L2.  A bijection on
+// [0, n) for any n.
+// ---------------------------------------------------------------------------
+constexpr u32 N_XCD = 8;
+__device__ __forceinline__ u32 xcd_order(u32 b, u32 n) {
+    const u32 q = n / N_XCD, r = n % N_XCD, x = b % N_XCD, i = b / N_XCD;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ---------------------------------------------------------------------------
 // Module ranges by search (launches without the segmentation kernel): with the
 // module ids sorted, module m's digis are [lower bound of m, lower bound of m + 1).
 // One wave finds both.  The first round probes 64 points SEARCH_STEP apart around
@@ -827,7 +839,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     // next is drawn while the current one is clustered, and the next module's
     // table entry (or range, by search) and digis are loaded meanwhile.
     const u32 per_round = gridDim.x * MPW;
-    u32 base = blockIdx.x * MPW + (WAVE ? g : 0u);
+    u32 base = xcd_order(blockIdx.x, gridDim.x) * MPW + (WAVE ? g : 0u);
     EventDesc E{};
     Item I{0, 0, 0, 0, 0, false};
     u32 R[K], C[K], A[K];
