@@ -1349,7 +1349,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
     } else {
         total = event_prefix<C_WG>(a, k, s_pref, s_wsum, CNT_UNITS, 1, 0, 1);       // + status unit
     }
-    for (u32 u = wave_uniform(blockIdx.x * C_WAVES + wv); u < total; u += gridDim.x * C_WAVES) {
+    for (u32 u = wave_uniform(xcd_order(blockIdx.x, gridDim.x) * C_WAVES + wv); u < total; u += gridDim.x * C_WAVES) {
         const u32 e = wave_uniform(find_slot(s_pref, k, u));
         const u32 j = u - s_pref[e], np = s_pref[e + 1] - s_pref[e] - 1;
         const EventDesc E = wave_uniform(get_event(a, e));
@@ -1427,7 +1427,7 @@ __global__ __launch_bounds__(H_WG) void k_hits(LaunchArgs a) {
     const u32 tid = threadIdx.x;
     const u32 k = num_events(a);
     const u32 total = event_prefix<H_WG>(a, k, s_pref, s_wsum, CNT_UNITS, 1, 0);
-    for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
+    for (u32 t = xcd_order(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
         const u32 e = find_slot(s_pref, k, t);
         const EventDesc E = get_event(a, e);
         const EvLayout L = ev_layout(E.cap, a.n_modules);
