@@ -51,6 +51,8 @@ def _load():
         f32p = ctypes.POINTER(ctypes.c_float)
         lib.pxo_cluster_event_hits.restype = ctypes.c_int
         lib.pxo_cluster_event_hits.argtypes = lib.pxo_cluster_event.argtypes + [f32p, f32p]
+        lib.pxo_cluster_event_any_order.restype = ctypes.c_int
+        lib.pxo_cluster_event_any_order.argtypes = lib.pxo_cluster_event_hits.argtypes
         _lib = lib
     return _lib
 
@@ -59,13 +61,18 @@ def _p(a, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
-def cluster_event(ev, charge_cut: int = 2000):
+def cluster_event(ev, charge_cut: int = 2000, any_order: bool = False):
     """Run the oracle on one event (dict of uint16 arrays + ``n_modules``).
 
     Returns a dict: ``status``, ``err_bits``, ``n_clusters``, ``id``, ``charge``,
     ``size`` (int32 arrays of the kept clusters, ascending id) and ``digi`` (int32
-    per digi: kept cluster id or -1).
+    per digi: kept cluster id or -1).  With ``any_order`` the digis need not be
+    grouped by module (``pxo_cluster_event_any_order``).
     """
+    if any_order:
+        r = hits(ev, charge_cut, any_order=True)
+        del r["x"], r["y"]
+        return r
     lib = _load()
     mod = np.ascontiguousarray(ev["module"], dtype=np.uint16)
     row = np.ascontiguousarray(ev["row"], dtype=np.uint16)
@@ -91,10 +98,11 @@ def cluster_event(ev, charge_cut: int = 2000):
             "digi": digi[:n].copy()}
 
 
-def hits(ev, charge_cut: int = 2000):
+def hits(ev, charge_cut: int = 2000, any_order: bool = False):
     """The clustering result plus, per kept cluster, its hit: the charge-weighted
     centroid x = sum(adc*col)/charge, y = sum(adc*row)/charge (exact 64-bit sums,
-    divided in double, rounded to float32; NaN for zero charge)."""
+    divided in double, rounded to float32; NaN for zero charge).  With ``any_order``
+    the digis need not be grouped by module."""
     lib = _load()
     mod = np.ascontiguousarray(ev["module"], dtype=np.uint16)
     row = np.ascontiguousarray(ev["row"], dtype=np.uint16)
@@ -107,7 +115,8 @@ def hits(ev, charge_cut: int = 2000):
     hx, hy = np.zeros(cap, dtype=np.float32), np.zeros(cap, dtype=np.float32)
     ncl = np.zeros(1, dtype=np.uint32)
     bits = np.zeros(1, dtype=np.uint32)
-    st = lib.pxo_cluster_event_hits(_p(mod, ctypes.c_uint16), _p(row, ctypes.c_uint16),
+    fn = lib.pxo_cluster_event_any_order if any_order else lib.pxo_cluster_event_hits
+    st = fn(_p(mod, ctypes.c_uint16), _p(row, ctypes.c_uint16),
                                     _p(col, ctypes.c_uint16), _p(adc, ctypes.c_uint16),
                                     n, int(ev["n_modules"]), int(charge_cut) & 0xFFFFFFFF,
                                     _p(digi, ctypes.c_int32), _p(cid, ctypes.c_int32),

@@ -32,6 +32,14 @@
  * Errors (checked in this order; the first class found is reported):
  *   out-of-range module/row/col -> -6, module ids decreasing -> -7,
  *   the same pixel fired twice  -> -5.  Outputs are unspecified on error.
+ *
+ * Digis in any order (pxo_cluster_event_any_order): the raw data of the figure's
+ * producer carries no grouping, and the definition above does not depend on the
+ * order of the digis.  That entry point first groups the digis by module with a
+ * stable counting sort (count per module, exclusive prefix, place in input order),
+ * runs the grouped definition on the grouped copy and returns every per-digi id at
+ * the digi's input position.  No order error exists there: out of range -> -6, the
+ * same pixel fired twice -> -5.
  */
 #include <math.h>
 #include <stdint.h>
@@ -204,4 +212,51 @@ int64_t pxo_components(const uint16_t* module, const uint16_t* row, const uint16
     int rc = pxo_cluster_event(module, row, col, adc, n, n_modules, 0u, digi_cluster, cl_id,
                                cl_charge, cl_size, &nc, &bits);
     return rc == O_OK ? (int64_t)nc : (int64_t)rc;
+}
+
+/* Digis in any order: group by module (stable counting sort), cluster the grouped
+ * copy with the definition above, per-digi ids back at the input positions. */
+int pxo_cluster_event_any_order(const uint16_t* module, const uint16_t* row, const uint16_t* col,
+                                const uint16_t* adc, uint32_t n, uint32_t n_modules,
+                                uint32_t charge_cut, int32_t* digi_cluster, int32_t* cl_id,
+                                int32_t* cl_charge, int32_t* cl_size, uint32_t* n_clusters,
+                                uint32_t* err_bits, float* hit_x, float* hit_y)
+{
+    *n_clusters = 0;
+    if (n > 0 && (!module || !row || !col || !adc || !digi_cluster))
+        return O_E_INVAL;
+    uint32_t bits = 0;
+    for (uint32_t i = 0; i < n; ++i)
+        if (module[i] >= n_modules || row[i] >= O_ROWS || col[i] >= O_COLS)
+            bits |= 1u;
+    if (bits) {
+        if (err_bits) *err_bits = bits;
+        return O_E_RANGE;
+    }
+    uint32_t* start = (uint32_t*)calloc((size_t)n_modules + 1, sizeof(uint32_t));
+    uint32_t* pos = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));      /* grouped slot -> input index */
+    uint16_t* g = (uint16_t*)malloc(sizeof(uint16_t) * 4 * (n ? n : 1));
+    int32_t* gd = (int32_t*)malloc(sizeof(int32_t) * (n ? n : 1));
+    if (!start || !pos || !g || !gd) {
+        free(start); free(pos); free(g); free(gd);
+        return O_E_NOMEM;
+    }
+    /* count per module, exclusive prefix, then every digi in input order to the next
+     * free slot of its module */
+    for (uint32_t i = 0; i < n; ++i) start[module[i] + 1] += 1;
+    for (uint32_t m = 0; m < n_modules; ++m) start[m + 1] += start[m];
+    for (uint32_t i = 0; i < n; ++i) pos[start[module[i]]++] = i;
+    uint16_t *gm = g, *gr = g + n, *gc = g + 2 * (size_t)n, *ga = g + 3 * (size_t)n;
+    for (uint32_t j = 0; j < n; ++j) {
+        gm[j] = module[pos[j]];
+        gr[j] = row[pos[j]];
+        gc[j] = col[pos[j]];
+        ga[j] = adc[pos[j]];
+    }
+    int rc = pxo_cluster_event_hits(gm, gr, gc, ga, n, n_modules, charge_cut, gd, cl_id, cl_charge, cl_size,
+                                    n_clusters, err_bits, hit_x, hit_y);
+    if (rc == O_OK)
+        for (uint32_t j = 0; j < n; ++j) digi_cluster[pos[j]] = gd[j];
+    free(start); free(pos); free(g); free(gd);
+    return rc;
 }

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import test_oracle_any_order as apins
 from tests import test_oracle_hits as hpins
 from tests import test_oracle_pins as pins
 
@@ -26,6 +27,9 @@ MUTANTS = {
     "hit_axes_swapped": ("sum_row += (uint64_t)adc[d] * row[d];", "sum_row += (uint64_t)adc[d] * col[d];"),
     "hit_in_float": ("(float)((double)cls[j].sum_col / (double)cls[j].charge)",
                      "((float)cls[j].sum_col / (float)cls[j].charge)"),
+    # digis in any order
+    "any_order_ids_not_returned_to_input_positions": ("digi_cluster[pos[j]] = gd[j];", "digi_cluster[j] = gd[j];"),
+    "any_order_rows_not_gathered": ("gr[j] = row[pos[j]];", "gr[j] = row[j];"),
 }
 
 
@@ -36,11 +40,11 @@ class _Fake:
         self._lib = lib
         self.E_DUP, self.E_RANGE, self.E_ORDER = oracle.E_DUP, oracle.E_RANGE, oracle.E_ORDER
 
-    def cluster_event(self, ev, charge_cut=2000):
+    def cluster_event(self, ev, charge_cut=2000, any_order=False):
         saved = oracle._lib
         oracle._lib = self._lib
         try:
-            return oracle.cluster_event(ev, charge_cut)
+            return oracle.cluster_event(ev, charge_cut, any_order=any_order)
         finally:
             oracle._lib = saved
 
@@ -70,6 +74,8 @@ def _build_mutant(tmp_path, name, old, new):
                                       ctypes.c_uint32, i32p, i32p, i32p, i32p, u32p, u32p]
     lib.pxo_cluster_event_hits.restype = ctypes.c_int
     lib.pxo_cluster_event_hits.argtypes = lib.pxo_cluster_event.argtypes + [ctypes.POINTER(ctypes.c_float)] * 2
+    lib.pxo_cluster_event_any_order.restype = ctypes.c_int
+    lib.pxo_cluster_event_any_order.argtypes = lib.pxo_cluster_event_hits.argtypes
     return lib
 
 
@@ -85,6 +91,8 @@ def _caught(fake):
         lambda: hpins.test_against_scipy_label(fake, 0.05),
         lambda: hpins.test_against_scipy_label(fake, 0.5),
         lambda: hpins.test_large_clusters_exact(fake),          # sums above 2**24
+        lambda: apins.test_patterns_shuffled_across_modules(fake),
+        lambda: apins.test_random_small_shuffled_vs_pairwise(fake),
     ]
     for chk in checks:
         try:
