@@ -1,17 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the pixel-clustering path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload async|plain|batch|serve|stress]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|stress|batch|serve|async|plain|hits]
 
-Default workload ("async"): full-size events (1,856 modules of 160x416 pixels,
-~50k digis each) through the non-blocking acquire/produce boundary, 4 host threads
-each with one event in flight and synthetic CPU tasks filling the wait.  A step is
-one event per host thread (4 events).  Inputs are resident in HBM before the timed
-region starts.  One JSON line is printed; ``roofline`` describes the dominant kernel
-(algorithmic bytes per launch / its mean duration, from hipEvents recorded on the
-launch stream in a second run of the same workload right after the timed region, so
-that the timed region carries no timing events) and ``cpu_baseline`` the plain CPU
-oracle on a bounded sample of the same events.
+Default ("all"): one JSON line whose headline (``value``) is the high-pileup stress
+configuration, the largest one that runs on one GPU: batches of 16 events of ~320k
+digis (16 modules at 20 % occupancy with mean-40 clusters, 142 sparse modules, a
+full-column track and a serpentine per event).  A step is one batch launch (the whole
+pipeline over 16 events); W untimed launches, then exactly K timed ones, replayed
+from captured graphs and spread over 4 streams, with inputs resident in HBM.  The
+same line carries, under ``workloads``, the other configurations measured in the
+same run with fixed step counts of their own (independent of --steps): ``batch`` (64
+events of 10k-120k digis per launch), ``serve`` (Poisson arrivals at 0.5, 0.7 and 0.9
+of the saturated rate, continuous batching), ``async`` (~50k-digi events through the
+non-blocking acquire/produce boundary from 4 host threads, device- and host-resident
+input) and ``plain`` (46,912-digi events, one synchronous launch each).
+
+``roofline`` describes the dominant kernel of the headline: its algorithmic bytes per
+launch divided by its mean duration, from hipEvents recorded on the launch stream
+around every kernel of launches made one after another on one stream without a
+graph (hipEvents cannot be timed inside captured graphs, and on one stream no other
+launch shares the compute units); ``--roofline-only`` runs just those launches, which
+is the command the committed rocprofv3 summaries profile.  ``cpu_baseline`` times the
+plain CPU oracle on the host, on one thread and on all available cores.
 """
 from __future__ import annotations
 
@@ -33,6 +44,15 @@ KERNEL_SYMBOLS = {"segment": "k_segment", "big": "k_big", "small": "k_small", "c
 # kernels behind each timing slot: the big-module slot times register and scratch mode
 KERNEL_PARTS = {"big": ["k_big", "k_scratch"]}
 ALL_SYMBOLS = list(KERNEL_SYMBOLS.values()) + ["k_scratch"]
+METRIC = "events/s + digis/s clustered (frac HBM peak); p50/p99 event latency; host block time"
+
+COPY_BYTES = 1 << 30
+SERVE_LOADS = (0.5, 0.7, 0.9)   # serving: offered load as fractions of the saturated rate
+SERVE_REQUESTS = 10000          # requests per serving run (p99 over 10,000)
+N_STREAMS = 4                   # streams the batched workloads spread their launches over
+SUB_STEPS = {"batch": 200, "async": 2000, "plain": 2000}   # fixed step counts of the sub-records
+ROOFLINE_LAUNCHES = 32          # one-stream graph-free launches timed for the roofline
+MAX_CPU_THREADS = 16            # the oracle's N-thread baseline uses at most this many cores
 
 
 def event_bytes(n_digis: int, n_kept: int) -> int:
@@ -64,6 +84,7 @@ def load_traffic(workload: str, kernel: str):
 
 
 def roofline(ctx, bytes_per_launch: float, workload: str):
+    """Roofline of the dominant kernel from the context's per-kernel hipEvent sums."""
     ms, cnt = ctx.timing(reset=True)
     avg = {k: (ms[i] / cnt[i] if cnt[i] else 0.0) for i, k in enumerate(KERNELS)}
     if not cnt[KERNELS.index("hits")]:
@@ -75,32 +96,26 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
     pipe = sum(avg.values()) * 1e-3
     return {
         "bound": "hbm", "kernel": "+".join(KERNEL_PARTS.get(dom, [KERNEL_SYMBOLS[dom]])), "achieved": round(achieved, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": load_traffic(workload, dom),
         "algorithmic_bytes_per_launch": int(bytes_per_launch),
         "kernel_mean_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
         "timed_launches": int(max(cnt)),
+        "pipeline_us": round(pipe * 1e6, 3),
         "pipeline_GBps": round(bytes_per_launch / pipe / 1e9, 2) if pipe > 0 else 0.0,
     }
 
 
-COPY_BYTES = 1 << 30
-SERVE_LOAD = 0.6           # serving: offered load as a fraction of the saturated rate
-N_STREAMS = 4              # streams the batched workloads spread their launches over
-
-
 def profile_commands(workload: str) -> dict:
     """The rocprofv3 commands whose output --summarize-profiles reads (run from the
-    repository root with the output directory DIR)."""
-    extra = "" if workload in ("async", "hits") else " --no-graph"
-    steps = {"async": 100, "hits": 100, "batch": 20, "stress": 10}.get(workload, 20)
-    b = f"python3 bench.py --workload {workload}{extra} --no-cpu-baseline"
-    pmc = f"{b} --steps {steps} --warmup 2"
+    repository root with the output directory DIR): the one-stream roofline launches
+    of the workload with its kernel shape pinned."""
+    shape = {"stress": "512x1", "batch": "64x1", "async": "256x4", "hits": "256x4"}.get(workload, "256x1")
+    b = f"python3 bench.py --workload {workload} --roofline-only --kernel-config {shape}"
     return {
         "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d DIR/kt_{workload} -o run -- {b}",
-        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_{workload} -o run -- {pmc}",
-        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_{workload} -o run -- {pmc}",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_{workload} -o run -- {b}",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_{workload} -o run -- {b}",
         "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_copy -o run -- "
                       "python3 bench.py --copy-calibration 5",
         "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_copy -o run -- "
@@ -132,27 +147,69 @@ def copy_calibration(torch, reps: int):
     print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps, "copy_GBps": gbs}), flush=True)
 
 
-def cpu_baseline(events, seconds: float, unit_events: bool = True):
-    """The oracle as it stands, single-threaded, over the workload's events for about
-    `seconds` of CPU time."""
+# ---------------------------------------------------------------------------
+# CPU oracle baseline
+# ---------------------------------------------------------------------------
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads() -> int:
+    return max(1, min(len(os.sched_getaffinity(0)), MAX_CPU_THREADS))
+
+
+def oracle_rate(events, seconds: float, threads: int):
+    """The oracle as it stands over `events` (cycled) for about `seconds`: one event
+    per call, `threads` threads (ctypes releases the interpreter lock during a call)."""
+    import threading
+
     import oracle
     oracle.build()
+    stop = time.perf_counter() + seconds
+    counts = [[0, 0] for _ in range(threads)]
+
+    def work(t):
+        i = t
+        while time.perf_counter() < stop:
+            ev = events[i % len(events)]
+            oracle.cluster_event(ev, 2000)
+            counts[t][0] += 1
+            counts[t][1] += ev["module"].size
+            i += threads
+
     t0 = time.perf_counter()
-    n_ev = n_dg = 0
-    i = 0
-    while time.perf_counter() - t0 < seconds:
-        ev = events[i % len(events)]
-        oracle.cluster_event(ev, 2000)
-        n_ev += 1
-        n_dg += ev["module"].size
-        i += 1
+    th = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
     dt = time.perf_counter() - t0
-    return {"value": round(n_ev / dt, 2), "unit": "events/s", "cores": 1, "kind": "oracle",
-            "digis_per_s": round(n_dg / dt, 1),
-            "sample": f"{n_ev} events ({n_dg} digis) cycled from the workload's {len(events)} distinct "
-                      f"events, one thread, {dt:.1f} s"}
+    n_ev, n_dg = sum(c[0] for c in counts), sum(c[1] for c in counts)
+    return n_ev / dt, n_dg / dt, n_ev, n_dg, dt
 
 
+def cpu_baseline(events, seconds: float, what: str):
+    """The oracle on the host: one thread, then every available core (up to
+    MAX_CPU_THREADS), each over about `seconds`."""
+    n = cpu_threads()
+    e1, d1, n1, g1, t1 = oracle_rate(events, seconds, 1)
+    en, dn, nn, gn, tn = oracle_rate(events, seconds, n)
+    return {"value": round(en, 2), "unit": "events/s", "cores": n, "kind": "oracle",
+            "digis_per_s": round(dn, 1), "one_thread": {"value": round(e1, 2), "digis_per_s": round(d1, 1)},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{what}: {nn} events ({gn} digis) on {n} threads in {tn:.1f} s and {n1} events ({g1} digis) "
+                      f"on one thread in {t1:.1f} s, cycled from the workload's {len(events)} distinct events"}
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries
+# ---------------------------------------------------------------------------
 def _read_csv(path):
     import csv
     with open(path, newline="") as f:
@@ -175,8 +232,8 @@ def summarize_profiles(prof: str, workload: str, command: dict):
     out_dir = os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
     stats = _read_csv(os.path.join(prof, f"kt_{workload}", "run_kernel_stats.csv"))
-    lines = [f"rocprofv3 kernel-trace statistics, workload {workload}",
-             f"command: {command['kt']}", "",
+    lines = [f"rocprofv3 kernel-trace statistics, workload {workload} (one-stream roofline launches)",
+             f"command: {command['kt']}", f"kernel source sha256[:16]: {kernel_src_sha()}", "",
              f"{'kernel':<40}{'calls':>8}{'avg_us':>10}{'min_us':>10}{'max_us':>10}{'pct':>8}"]
     for r in stats:
         lines.append(f"{_short(r['Name'])[:39]:<40}{int(r['Calls']):>8}{float(r['AverageNs']) / 1e3:>10.2f}"
@@ -214,10 +271,31 @@ def summarize_profiles(prof: str, workload: str, command: dict):
                       "kernels": {k: [fetch.get(k), write.get(k)] for k in ALL_SYMBOLS}}))
 
 
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def _gen(args):
+    kind, i = args
+    from paper_2004_04334_amd import synth
+    return getattr(synth, f"{kind}_event")(i)
+
+
+def gen_events(kind: str, count: int):
+    """`count` seeded events of a configuration, drawn in parallel processes."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(count, cpu_threads()),
+                             mp_context=multiprocessing.get_context("spawn")) as ex:
+        return list(ex.map(_gen, [(kind, i) for i in range(count)]))
+
+
 def tune(px, ctx, args, events, digis, slots=None, batch=None):
-    """Run the library's autotuner on one representative launch of the workload
-    (every kernel shape, a few replays each) and keep the fastest shape; returns the
-    table of mean microseconds per shape."""
+    """Pin the kernel shape (--kernel-config), keep the default (--no-autotune), or run
+    the library's autotuner on one representative launch (every kernel shape, a few
+    replays each) and keep the fastest; returns the table of mean microseconds."""
+    if args.kernel_config:
+        ctx.set_kernel_config(*map(int, args.kernel_config.split("x")))
+        return None
     if args.no_autotune:
         return None
     own_b = batch is None
@@ -233,74 +311,166 @@ def tune(px, ctx, args, events, digis, slots=None, batch=None):
     return {f"{wg}x{mpw}": round(t, 1) for (wg, mpw), t in sorted(times.items())}
 
 
-def gen_events(maker, count, **kw):
-    return [maker(i, **kw) for i in range(count)]
-
-
-# ---------------------------------------------------------------------------
-def bench_async(px, torch, args, synth, hits: bool = False):
-    n_threads = 4
-    evs = gen_events(synth.async_event, 32)
+def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, steps, warmup, hint=False,
+             timed=True):
+    """Graph-replayed batches over `n_copies` device-resident copies of the events (a
+    working set larger than the 256 MB Infinity Cache); each copy has its own batch
+    object and event slots, so the host only waits when it wraps around.  Then the
+    roofline launches: the same batches one after another on one stream, without a
+    graph, every kernel timed with hipEvents."""
     ctx = px.Context(1856, 2000)
-    pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
+    # consecutive launches go to different streams, so that one batch's completion
+    # (a device -> host -> device round trip) overlaps the next batch's kernels
+    streams = [torch.cuda.Stream() for _ in range(N_STREAMS)]
+    cap = max(e["module"].size for e in evs)
+    groups = []
+    for c in range(n_copies if timed else 1):
+        digis = [px.Digis.from_numpy(e, "cuda", hint=hint) for e in evs]
+        slots = [px.Event(ctx, cap) for _ in range(per_batch)]
+        groups.append((px.Batch(ctx, per_batch), slots, digis, px.BatchInputs(slots, digis)))
+    n_groups = len(groups)
+    flags = [px.Flag() for _ in range(n_groups)]
+    tuned = tune(px, ctx, args, evs, groups[0][2], slots=groups[0][1], batch=groups[0][0])
+
+    def launch(i, graph, stream=None):
+        b, _, _, prepared = groups[i % n_groups]
+        while px.batch_query(b) == px.E_NOT_READY:     # this copy's previous launch
+            time.sleep(0)
+        px.acquire_batch(b, prepared, None, stream or streams[i % N_STREAMS], flag=flags[i % n_groups], graph=graph)
+
+    def drain():
+        torch.cuda.synchronize()
+        for g in groups:
+            while px.batch_query(g[0]) == px.E_NOT_READY:
+                time.sleep(0)
+
+    graph = not args.no_graph
+    out = {}
+    if timed:
+        for i in range(max(warmup, n_groups)):          # also captures every graph
+            launch(i, graph)
+        drain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host = 0.0
+        for i in range(steps):
+            h0 = time.perf_counter()
+            launch(i, graph)
+            host += time.perf_counter() - h0
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        drain()
+        n_dg = sum(e["module"].size for e in evs)
+        out = {"value": per_batch * steps / wall, "ms_per_step": wall * 1e3 / steps,
+               "digis_per_s": n_dg * steps / wall, "host_us_per_launch": host * 1e6 / steps}
+    # roofline launches: one stream, no graph, every kernel timed
+    launch(0, False, streams[0])
+    drain()
+    res = [px.produce(s).n_clusters for s in groups[0][1]]
+    assert all(px.produce(s).status == 0 for s in groups[0][1])
+    b_batch = float(sum(event_bytes(e["module"].size, k) for e, k in zip(evs, res)))
+    ctx.set_timing(True, 1)
+    ctx.timing(reset=True)
+    for i in range(ROOFLINE_LAUNCHES):
+        launch(i, False, streams[0])
+    drain()
+    for b, slots, _, _ in groups:
+        b.close()
+        for s in slots:
+            s.close()
+    rl = roofline(ctx, b_batch, workload)
+    rl["kernel_times_from"] = f"{ROOFLINE_LAUNCHES} graph-free launches of the same batches on one stream"
+    ctx.set_timing(False)
+    if timed:
+        out["hbm_frac_whole_job"] = round(b_batch / per_batch * out["value"] / 1e9 / HBM_PEAK_GBS, 5)
+    out.update({
+        "config": {"workload": desc, "n_modules": 1856, "events_per_launch": per_batch,
+                   "mean_digis": int(np.mean([e["module"].size for e in evs])), "device_copies": n_groups,
+                   "streams": N_STREAMS, "size_hint": bool(hint), "kernel_config": list(ctx.kernel_config()),
+                   "autotune_us": tuned},
+        "roofline": rl})
+    ctx.close()
+    return out
+
+
+STRESS_DESC = ("stress: 16 events/launch of ~320k digis (16 modules at 20% occupancy with mean-40 clusters, "
+               "142 sparse modules, a full-column track and a serpentine per event), 1856 modules of 160x416, "
+               "persistent kernels replayed from captured graphs over 4 streams")
+BATCH_DESC = ("batch: 64 events/launch (persistent kernels, captured graph), 1856 modules, 10k-120k digis/event, "
+              "log-normal module occupancy")
+
+
+def bench_stress(px, torch, args, evs, steps, warmup, timed=True):
+    return _batched(px, torch, args, evs, 4, 16, "stress", STRESS_DESC, steps, warmup, timed=timed)
+
+
+def bench_batch(px, torch, args, evs, steps, warmup, timed=True):
+    r = _batched(px, torch, args, evs, 8, 64, "batch", BATCH_DESC, steps, warmup, timed=timed)
+    if timed:
+        h = _batched(px, torch, args, evs, 8, 64, "batch", BATCH_DESC, steps, warmup, hint=True)
+        r["with_size_hint"] = {"value": round(h["value"], 2), "digis_per_s": round(h["digis_per_s"], 1),
+                               "note": "every event's largest module passed as max_module_digis (host-side "
+                                       "bincount outside the timed region): the scratch-mode kernel is skipped"}
+    return r
+
+
+def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda", hint=False, shape=None):
+    """4 host threads, one event in flight each, synthetic 20 us CPU tasks while waiting;
+    the rate is over the driver's own timed window (after its threads are ready)."""
+    n_threads = 4
+    ctx = px.Context(1856, 2000)
+    pool = [px.Digis.from_numpy(e, where, hint=hint) for e in evs]
     cap = max(e["module"].size for e in evs)
     slots = [px.Event(ctx, cap) for _ in range(n_threads)]
     streams = [torch.cuda.Stream() for _ in range(n_threads)]
-    tuned = tune(px, ctx, args, evs[:1], pool[:1])
-    if tuned:
-        # one event alone does not show how shapes share the GPU across the streams:
-        # the three fastest shapes are run briefly in the driver itself, the best kept
-        best, best_rate = None, 0.0
-        for shape in sorted(tuned, key=tuned.get)[:3]:
-            ctx.set_kernel_config(*map(int, shape.split("x")))
-            px.run_async(ctx, slots, streams, pool, 25, cpu_task_ns=args.cpu_task_ns, hits=hits)
-            st = px.run_async(ctx, slots, streams, pool, 150, cpu_task_ns=args.cpu_task_ns, hits=hits)
-            rate = st["events"] / st["wall_s"]
-            if rate > best_rate:
-                best, best_rate = shape, rate
-        ctx.set_kernel_config(*map(int, best.split("x")))
+    tuned = None
+    if shape:
+        ctx.set_kernel_config(*shape)
+    else:
+        tuned = tune(px, ctx, args, evs[:1], pool[:1])
+        if tuned and not args.kernel_config:
+            # one event alone does not show how shapes share the GPU across the streams:
+            # the three fastest shapes are run briefly in the driver itself, the best kept
+            best, best_rate = None, 0.0
+            for sh in sorted(tuned, key=tuned.get)[:3]:
+                ctx.set_kernel_config(*map(int, sh.split("x")))
+                px.run_async(ctx, slots, streams, pool, 25, cpu_task_ns=args.cpu_task_ns, hits=hits)
+                st = px.run_async(ctx, slots, streams, pool, 150, cpu_task_ns=args.cpu_task_ns, hits=hits)
+                rate = st["events"] / st["wall_s"]
+                if rate > best_rate:
+                    best, best_rate = sh, rate
+            ctx.set_kernel_config(*map(int, best.split("x")))
     kept = []
     for d in pool:                       # one pass for the kept-cluster counts (bytes per event)
         px.acquire(slots[0], d)
         px.wait(slots[0])
         kept.append(px.produce(slots[0]).n_clusters)
-    px.run_async(ctx, slots, streams, pool, max(1, args.warmup), cpu_task_ns=args.cpu_task_ns, hits=hits)
+    px.run_async(ctx, slots, streams, pool, 100, cpu_task_ns=args.cpu_task_ns, hits=hits)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = px.run_async(ctx, slots, streams, pool, args.steps, cpu_task_ns=args.cpu_task_ns, hits=hits)
+    st = px.run_async(ctx, slots, streams, pool, events_per_thread, cpu_task_ns=args.cpu_task_ns, hits=hits)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # kernel times from a second run of the same workload with timing events (so that
-    # the throughput above carries no timing overhead)
+    # kernel times from a second run with timing events on every 8th launch of each slot
     ctx.timing(reset=True)
-    ctx.set_timing(True, args.timing_period)
-    px.run_async(ctx, slots, streams, pool, max(200, args.steps // 2), cpu_task_ns=args.cpu_task_ns, hits=hits)
+    ctx.set_timing(True, 8)
+    px.run_async(ctx, slots, streams, pool, 400, cpu_task_ns=args.cpu_task_ns, hits=hits)
     torch.cuda.synchronize()
     ctx.set_timing(False)
-    n_ev = st["events"]
     b_mean = float(np.mean([event_bytes(e["module"].size, k) for e, k in zip(evs, kept)]))
     rl = roofline(ctx, b_mean, "hits" if hits else "async")
-    rl["kernel_times_from"] = "a second run of the same workload with timing events"
-    if hits and rl["kernel_mean_us"].get("hits"):
-        # hits kernel: reads row, col, adc and the per-digi id (10 B/digi), the kept ids
-        # and charges (8 B/cluster), writes x and y (8 B/cluster)
-        hb = float(np.mean([10 * e["module"].size + 16 * k for e, k in zip(evs, kept)]))
-        gbs = hb / (rl["kernel_mean_us"]["hits"] * 1e-6) / 1e9
-        rl["hits_kernel"] = {"algorithmic_bytes_per_launch": int(hb), "achieved": round(gbs, 2),
-                             "frac": round(gbs / HBM_PEAK_GBS, 5)}
+    rl["kernel_times_from"] = "a second run of the same workload with timing events on every 8th launch"
+    rate = st["events"] / st["wall_s"]
     out = {
-        "value": n_ev / wall, "ms_per_step": wall * 1e3 / args.steps,
-        "digis_per_s": st["digis"] / wall,
+        "value": rate, "digis_per_s": st["digis"] / st["wall_s"], "events": st["events"],
         "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
-        "host_blocked_us_per_event": st["blocked_us_per_event"],
-        "cpu_tasks_per_s": st["cpu_tasks_per_s"], "errors": st["errors"],
+        "host_blocked_us_per_event": st["blocked_us_per_event"], "cpu_tasks_per_s": st["cpu_tasks_per_s"],
+        "errors": st["errors"], "hbm_frac_whole_job": round(b_mean * rate / 1e9 / HBM_PEAK_GBS, 5),
         "config": {"workload": "async: 1856 modules x 160x416, ~50k digis/event, 4 host threads x 1 event "
-                               "in flight, synthetic CPU tasks while waiting" +
-                               (", hits queued behind every event" if hits else ""),
-                   "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
-                   "host_threads": n_threads, "cpu_task_ns": args.cpu_task_ns, "distinct_events": len(evs),
-                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
-        "roofline": rl, "events": evs,
+                               "in flight, synthetic 20 us CPU tasks while waiting" +
+                               (", hits queued behind every event" if hits else "") +
+                               (", input in pinned host memory (PCIe copy per event)" if where == "pinned" else ""),
+                   "mean_digis": int(np.mean([e["module"].size for e in evs])), "input": where,
+                   "size_hint": bool(hint), "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
+        "roofline": rl,
     }
     for s in slots:
         s.close()
@@ -308,14 +478,7 @@ def bench_async(px, torch, args, synth, hits: bool = False):
     return out
 
 
-def bench_hits(px, torch, args, synth):
-    """The asynchronous workload with every event's hits queued behind it on the
-    same stream (a consumer of the clusters) and produced with it."""
-    return bench_async(px, torch, args, synth, hits=True)
-
-
-def bench_plain(px, torch, args, synth):
-    evs = gen_events(synth.plain_event, 32)
+def bench_plain(px, torch, args, evs, steps):
     ctx = px.Context(64, 2000)
     pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
     slot = px.Event(ctx, max(e["module"].size for e in evs))
@@ -326,125 +489,34 @@ def bench_plain(px, torch, args, synth):
         px.acquire(slot, d)
         px.wait(slot)
         kept.append(px.produce(slot).n_clusters)
-    px.run_async(ctx, [slot], [stream], pool, max(1, args.warmup), blocking=True)
+    px.run_async(ctx, [slot], [stream], pool, 100, blocking=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = px.run_async(ctx, [slot], [stream], pool, args.steps, blocking=True)
+    st = px.run_async(ctx, [slot], [stream], pool, steps, blocking=True)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     ctx.timing(reset=True)              # kernel times: a second run with timing events
-    ctx.set_timing(True, args.timing_period)
-    px.run_async(ctx, [slot], [stream], pool, max(200, args.steps // 2), blocking=True)
+    ctx.set_timing(True, 1)
+    px.run_async(ctx, [slot], [stream], pool, 200, blocking=True)
     torch.cuda.synchronize()
     ctx.set_timing(False)
     b_mean = float(np.mean([event_bytes(e["module"].size, k) for e, k in zip(evs, kept)]))
+    rate = st["events"] / st["wall_s"]
     out = {
-        "value": st["events"] / wall, "ms_per_step": wall * 1e3 / args.steps, "digis_per_s": st["digis"] / wall,
+        "value": rate, "digis_per_s": st["digis"] / st["wall_s"], "events": st["events"],
         "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
         "host_blocked_us_per_event": st["blocked_us_per_event"], "errors": st["errors"],
+        "hbm_frac_whole_job": round(b_mean * rate / 1e9 / HBM_PEAK_GBS, 5),
         "config": {"workload": "plain: 64 modules x 160x416, 46,912 digis/event, one event per synchronous launch",
-                   "n_modules": 64, "mean_digis": 46912, "distinct_events": len(evs),
                    "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
-        "roofline": roofline(ctx, b_mean, "plain"), "events": evs,
+        "roofline": roofline(ctx, b_mean, "plain"),
     }
     slot.close()
     ctx.close()
     return out
 
 
-def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, n_modules=1856):
-    """Graph-replayed batches over `n_copies` device-resident copies of the events (a
-    working set larger than the 256 MB Infinity Cache); each copy has its own batch
-    object and event slots, so the host only waits when it wraps around."""
-    ctx = px.Context(n_modules, 2000)
-    # consecutive launches go to different streams, so that one batch's completion
-    # callback (a device -> host -> device round trip on its stream) overlaps the next
-    # batch's kernels
-    streams = [torch.cuda.Stream() for _ in range(N_STREAMS)]
-    cap = max(e["module"].size for e in evs)
-    groups = []
-    for c in range(n_copies):
-        digis = [px.Digis.from_numpy(e, "cuda") for e in evs]
-        slots = [px.Event(ctx, cap) for _ in range(per_batch)]
-        groups.append((px.Batch(ctx, per_batch), slots, digis, px.BatchInputs(slots, digis)))
-    flags = [px.Flag() for _ in range(n_copies)]
-    tuned = tune(px, ctx, args, evs, groups[0][2], slots=groups[0][1], batch=groups[0][0])
-
-    def launch(i, graph, stream=None):
-        b, _, _, prepared = groups[i % n_copies]
-        while px.batch_query(b) == px.E_NOT_READY:     # this copy's previous launch
-            time.sleep(0)
-        px.acquire_batch(b, prepared, None, stream or streams[i % N_STREAMS], flag=flags[i % n_copies], graph=graph)
-
-    def drain():
-        torch.cuda.synchronize()
-        for g in groups:
-            while px.batch_query(g[0]) == px.E_NOT_READY:
-                time.sleep(0)
-
-    graph = not args.no_graph
-    for i in range(max(args.warmup, n_copies)):          # also captures every graph
-        launch(i, graph)
-    drain()
-    res = [px.produce(s).n_clusters for s in groups[0][1]]
-    b_batch = float(sum(event_bytes(e["module"].size, k) for e, k in zip(evs, res)))
-    if not graph:
-        ctx.set_timing(True, args.timing_period)
-    ctx.timing(reset=True)
-    t0 = time.perf_counter()
-    host = 0.0
-    for i in range(args.steps):
-        h0 = time.perf_counter()
-        launch(i, graph)
-        host += time.perf_counter() - h0
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    drain()
-    if graph:
-        # hipEvents recorded inside a captured graph cannot be timed: the kernel times
-        # come from the same batches launched without a graph
-        # (on one stream, so that concurrent batches do not stretch each other's kernels)
-        ctx.set_timing(True)
-        for i in range(min(args.steps, 8 * n_copies)):
-            launch(i, False, streams[0])
-        drain()
-    for b, slots, _, _ in groups:
-        b.close()
-        for s in slots:
-            s.close()
-    rl = roofline(ctx, b_batch, workload)
-    rl["kernel_times_from"] = "graph-free launches of the same batches" if graph else "the timed launches"
-    ctx.set_timing(False)
-    n_dg = sum(e["module"].size for e in evs)
-    out = {
-        "value": per_batch * args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
-        "digis_per_s": n_dg * args.steps / wall,
-        "host_us_per_launch": host * 1e6 / args.steps,
-        "config": {"workload": desc, "n_modules": n_modules, "events_per_launch": per_batch,
-                   "mean_digis": int(n_dg / len(evs)), "device_copies": n_copies, "streams": N_STREAMS,
-                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
-        "roofline": rl, "events": evs,
-    }
-    ctx.close()
-    return out
-
-
-def bench_batch(px, torch, args, synth):
-    evs = gen_events(synth.batch_event, 64)
-    return _batched(px, torch, args, evs, 8, 64, "batch",
-                    "batch: 64 events/launch (persistent kernels, captured graph), 1856 modules, "
-                    "10k-120k digis/event, log-normal module occupancy")
-
-
-def bench_stress(px, torch, args, synth):
-    evs = gen_events(synth.stress_event, 16)
-    return _batched(px, torch, args, evs, 4, 16, "stress",
-                    "stress: 16 events/launch of ~320k digis, 16 modules at 20% occupancy with "
-                    "mean-40 clusters, a full-column track and a serpentine per event")
-
-
-def bench_serve(px, torch, args, synth):
-    evs = gen_events(synth.serve_event, 32)
+def bench_serve(px, torch, args, evs):
+    """Calibration: the saturated rate (all requests arrive at once, the largest
+    batches); then Poisson arrivals at SERVE_LOADS of it."""
     ctx = px.Context(1856, 2000)
     pool = [px.Digis.from_numpy(e, "cuda") for e in evs]
     arena = torch.empty(16 << 30, dtype=torch.uint8, device="cuda")
@@ -455,67 +527,75 @@ def bench_serve(px, torch, args, synth):
     tuned = tune(px, ctx, args, evs[:16], pool[:16])      # a typical continuous batch
     common = dict(budget_bytes=16 << 30, n_slots=n_slots, max_batch=max_batch, n_cpu_threads=16,
                   cpu_task_ns=args.cpu_task_ns, graph=True)
-    # calibration: saturated throughput (all requests arrive at once, the largest
-    # batches); Poisson arrivals form smaller batches, so the offered load is 0.6 of it
-    cal, _, _ = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=1e9, n_requests=10000, seed=7, **common)
+    cal, _, _ = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=1e9, n_requests=SERVE_REQUESTS,
+                         seed=7, **common)
     sat = cal["events"] / cal["wall_s"]
-    rate = SERVE_LOAD * sat
-    torch.cuda.synchronize()
-    st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=rate,
-                               n_requests=args.steps, seed=11, **common)
-    torch.cuda.synchronize()
-    # kernel times: hipEvents cannot be timed inside captured graphs, so a shorter run
-    # of the same request stream launches its batches without a graph
-    n_t = min(args.steps, 2000)
-    ctx.timing(reset=True)
-    ctx.set_timing(True)
-    st_t, _, ncl_t = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=rate, n_requests=n_t,
-                              seed=11, **dict(common, graph=False))
-    torch.cuda.synchronize()
+    mean_b = float(np.mean([event_bytes(e["module"].size, 0) for e in evs]))
+    runs = []
+    for load in SERVE_LOADS:
+        torch.cuda.synchronize()
+        st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=load * sat,
+                                   n_requests=SERVE_REQUESTS, seed=11, **common)
+        rate = st["events"] / st["wall_s"]
+        runs.append({"load": load, "arrival_rate_hz": round(load * sat, 1), "value": round(rate, 2),
+                     "digis_per_s": round(st["digis"] / st["wall_s"], 1),
+                     "lat_p50_us": round(st["lat_p50_us"], 2), "lat_p99_us": round(st["lat_p99_us"], 2),
+                     "host_blocked_us_per_event": round(st["blocked_us_per_event"], 3),
+                     "cpu_tasks_per_s": round(st["cpu_tasks_per_s"], 1), "errors": st["errors"],
+                     "mean_events_per_launch": round(st["events"] / max(1, st["batches"]), 2),
+                     "kept_up": bool(rate >= 0.95 * load * sat),
+                     "hbm_frac_whole_job": round(mean_b * rate / 1e9 / HBM_PEAK_GBS, 5)})
     for b in batches:
         b.close()
-    b_mean = float(np.mean([event_bytes(evs[r % len(evs)]["module"].size, ncl_t[r]) for r in range(n_t)]))
-    rl = roofline(ctx, b_mean * n_t / max(1, st_t["batches"]), "serve")
-    rl["kernel_times_from"] = f"graph-free launches of the first {n_t} requests"
-    ctx.set_timing(False)
-    n_batches = max(1, st["batches"])
-    out = {
-        "value": st["events"] / st["wall_s"], "ms_per_step": st["wall_s"] * 1e3 / args.steps,
-        "digis_per_s": st["digis"] / st["wall_s"],
-        "lat_p50_us": st["lat_p50_us"], "lat_p99_us": st["lat_p99_us"],
-        "host_blocked_us_per_event": st["blocked_us_per_event"], "cpu_tasks_per_s": st["cpu_tasks_per_s"],
-        "errors": st["errors"], "saturated_events_per_s": sat, "arrival_rate_hz": rate,
-        "config": {"workload": f"serve: Poisson arrivals at {SERVE_LOAD}x saturated rate, 10k-200k digis/event, "
-                               "16 GB admission budget, continuous batching over 8 streams, 16 CPU threads",
-                   "n_modules": 1856, "mean_digis": int(np.mean([e["module"].size for e in evs])),
-                   "requests": args.steps, "mean_events_per_launch": round(args.steps / n_batches, 2),
-                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned,
-                   "peak_resident_bytes": st["peak_resident_bytes"]},
-        "roofline": rl, "events": evs,
-    }
     ctx.close()
+    mid = runs[1]
+    return {
+        "value": mid["value"], "digis_per_s": mid["digis_per_s"], "lat_p50_us": mid["lat_p50_us"],
+        "lat_p99_us": mid["lat_p99_us"], "host_blocked_us_per_event": mid["host_blocked_us_per_event"],
+        "saturated_events_per_s": round(sat, 1), "runs": runs,
+        "config": {"workload": "serve: Poisson arrivals, 10k-200k digis/event, 16 GB admission budget, "
+                               "continuous batching over 8 streams, 16 CPU threads with 20 us synthetic tasks",
+                   "requests_per_run": SERVE_REQUESTS, "kernel_config": list(ctx.kernel_config()),
+                   "autotune_us": tuned, "value_is": "the run at 0.7 of the saturated rate"},
+    }
+
+
+def _round(d):
+    if isinstance(d, float):
+        return round(d, 3)
+    if isinstance(d, dict):
+        return {k: _round(v) for k, v in d.items()}
+    if isinstance(d, list):
+        return [_round(v) for v in d]
+    return d
+
+
+def sub_record(r, evs, args, with_oracle=True):
+    out = _round(r)
+    if with_oracle and not args.no_cpu_baseline:
+        e1, d1, *_ = oracle_rate(evs, args.sub_cpu_seconds, 1)
+        n = cpu_threads()
+        en, dn, *_ = oracle_rate(evs, args.sub_cpu_seconds, n)
+        out["oracle"] = {"events_per_s_1_thread": round(e1, 2), "events_per_s_n_threads": round(en, 2),
+                         "threads": n, "digis_per_s_n_threads": round(dn, 1)}
     return out
-
-
-WORKLOADS = {"async": (bench_async, 2000, 100), "hits": (bench_hits, 2000, 100), "plain": (bench_plain, 2000, 100),
-             "batch": (bench_batch, 200, 10), "stress": (bench_stress, 100, 5),
-             "serve": (bench_serve, 20000, 0)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="async")
+    ap.add_argument("--steps", type=int, default=100, help="timed batch launches of the headline workload")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["all", "stress", "batch", "serve", "async", "plain", "hits"], default="all")
     ap.add_argument("--cpu-task-ns", type=int, default=20000)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="oracle baseline of the headline, per thread count")
+    ap.add_argument("--sub-cpu-seconds", type=float, default=2.0, help="oracle rates of the sub-records")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="batched workloads: plain launches, no captured graph")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default kernel shape instead of tuning it on the workload first")
-    ap.add_argument("--timing-period", type=int, default=8,
-                    help="time the kernels of every N-th launch of each event object in the timed region")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shape")
+    ap.add_argument("--kernel-config", metavar="WGxMPW", help="pin the small kernel's shape (no autotuning)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the one-stream roofline launches of the workload (the profiled command)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
                     help="only run REPS device copies of 1 GiB (counter calibration) and exit")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -528,13 +608,19 @@ def main():
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(events shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
-    fn, d_steps, d_warm = WORKLOADS[args.workload]
-    args.steps = args.steps or d_steps
-    args.warmup = d_warm if args.warmup is None else args.warmup
+
+    wl = args.workload
+    head = "stress" if wl == "all" else wl
+    need = {"stress": ("stress", 16), "batch": ("batch", 64), "serve": ("serve", 32), "async": ("async", 32),
+            "hits": ("async", 32), "plain": ("plain", 32)}
+    kinds = [head] if wl != "all" else ["stress", "batch", "serve", "async", "plain"]
+    evsets = {}
+    if not args.copy_calibration:             # drawn before the GPU is touched
+        print(f"bench: drawing events for {kinds}", file=sys.stderr, flush=True)
+        evsets = {k: gen_events(*need[k]) for k in kinds}
 
     import torch
     from paper_2004_04334_amd import pxcl as px
-    from paper_2004_04334_amd import synth
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -543,21 +629,63 @@ def main():
         copy_calibration(torch, args.copy_calibration)
         return
     px.lib()
+    if args.roofline_only:
+        fn = {"stress": bench_stress, "batch": bench_batch}.get(head)
+        if fn is None:
+            r = bench_async(px, torch, args, evsets[head], 50, hits=(head == "hits"))
+        else:
+            r = fn(px, torch, args, evsets[head], 0, 0, timed=False)
+        print(json.dumps(_round({"workload": head, "roofline": r["roofline"]})), flush=True)
+        return
     copy_gbs = copy_bandwidth(torch)
-    r = fn(px, torch, args, synth)
+    print(f"bench: headline {head}", file=sys.stderr, flush=True)
+    if head == "stress":
+        r = bench_stress(px, torch, args, evsets["stress"], args.steps, args.warmup)
+    elif head == "batch":
+        r = bench_batch(px, torch, args, evsets["batch"], args.steps, args.warmup)
+    elif head == "serve":
+        r = bench_serve(px, torch, args, evsets["serve"])
+    elif head in ("async", "hits"):
+        r = bench_async(px, torch, args, evsets[head], args.steps, hits=(head == "hits"))
+    else:
+        r = bench_plain(px, torch, args, evsets["plain"], args.steps)
     r["roofline"]["copy_GBps"] = copy_gbs
     r["roofline"]["frac_of_copy"] = round(r["roofline"]["achieved"] / copy_gbs, 5) if copy_gbs else None
-    evs = r.pop("events")
     line = {
-        "metric": "events/s + digis/s clustered (frac HBM peak); p50/p99 event latency; host block time",
-        "value": round(r.pop("value"), 2), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(r.pop("ms_per_step"), 4), "higher_is_better": True,
+        "metric": METRIC, "value": round(r.pop("value"), 2), "unit": "events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r.pop("ms_per_step", 0.0), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u16/i32", "data": "synthetic",
     }
-    line.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()})
+    line.update(_round(r))
     line["device"] = torch.cuda.get_device_name(0)
+    if wl == "all":
+        subs = {}
+        print("bench: batch", file=sys.stderr, flush=True)
+        subs["batch"] = sub_record(bench_batch(px, torch, args, evsets["batch"], SUB_STEPS["batch"], 10),
+                                   evsets["batch"], args)
+        print("bench: serve", file=sys.stderr, flush=True)
+        subs["serve"] = sub_record(bench_serve(px, torch, args, evsets["serve"]), evsets["serve"], args)
+        print("bench: async", file=sys.stderr, flush=True)
+        a = bench_async(px, torch, args, evsets["async"], SUB_STEPS["async"])
+        shape = tuple(a["config"]["kernel_config"])
+        a["with_size_hint"] = _round({k: bench_async(px, torch, args, evsets["async"], SUB_STEPS["async"],
+                                                     hint=True, shape=shape)[k]
+                                      for k in ("value", "digis_per_s", "lat_p50_us", "lat_p99_us")})
+        a["with_size_hint"]["note"] = ("every event's largest module passed as max_module_digis (host-side "
+                                       "bincount outside the timed region): neither big-module kernel is launched")
+        hs = bench_async(px, torch, args, evsets["async"], SUB_STEPS["async"] // 4, where="pinned", shape=shape)
+        a["host_staged"] = _round({k: hs[k] for k in ("value", "digis_per_s", "lat_p50_us", "lat_p99_us",
+                                                      "host_blocked_us_per_event")})
+        a["host_staged"]["note"] = "input in pinned host memory: a PCIe copy of 8 B/digi per event, never in value"
+        subs["async"] = sub_record(a, evsets["async"], args)
+        print("bench: plain", file=sys.stderr, flush=True)
+        subs["plain"] = sub_record(bench_plain(px, torch, args, evsets["plain"], SUB_STEPS["plain"]),
+                                   evsets["plain"], args)
+        line["workloads"] = subs
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(evs, args.cpu_seconds)
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(evsets[kinds[0] if head != "hits" else "async"], args.cpu_seconds, head)
     print(json.dumps(line), flush=True)
 
 

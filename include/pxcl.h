@@ -71,7 +71,8 @@ extern "C" {
 #define PXCL_E_RANGE (-6)       /* async: module >= n_modules, row >= 160 or col >= 416 */
 #define PXCL_E_ORDER (-7)       /* async: module ids decrease along the input */
 #define PXCL_E_HIP (-8)         /* a HIP runtime call failed */
-#define PXCL_E_INTERNAL (-10)   /* a bounded device-side wait expired (library bug) */
+#define PXCL_E_INTERNAL (-10)   /* library bug: inconsistent device state (a list overflowed, a
+                                   module entry out of range) or a missing status write-back */
 #define PXCL_E_NOTFOUND (-11)   /* autotune cache file missing or without this key */
 #define PXCL_E_HINT (-12)       /* async: a module has more digis than pxcl_digis.max_module_digis */
 

@@ -65,20 +65,35 @@ constexpr u32 LF_FUSED = 4;      // one event, no segmentation kernel: the small
 constexpr u32 LF_NO_SCRATCH = 8; // the scratch-mode kernel is not launched (size hint)
 __host__ __device__ constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
-// One event as the kernels see it (64 bytes).
+// Event flags (EventDesc::flags).
+constexpr u32 EF_UNSORTED = 1;   // the digis are in any order: the grouping kernels read them
+                                 // from r_*, write a copy grouped by module to the workspace
+                                 // (module..adc point there) and the permutation back
+
+// One event as the kernels see it (144 bytes).
 struct EventDesc {
-    const u16* module;
+    const u16* module;   // digis grouped by module (the input, or the workspace's grouped copy)
     const u16* row;
     const u16* col;
     const u16* adc;
-    u8* ws;          // event workspace (device)
-    u32* hstat;      // host status block (pinned, device-accessible)
-    u32 n;           // digis
-    u32 cap;         // workspace capacity in digis
-    u32 epoch;       // launch tag of the module-table words
-    u32 slot;        // launch parity: which present-module count this launch uses
+    const u16* r_module; // with EF_UNSORTED: the digis as given (any order)
+    const u16* r_row;
+    const u16* r_col;
+    const u16* r_adc;
+    u8* ws;              // event workspace (device)
+    u32* hstat;          // status block (pinned host memory or device memory)
+    int32_t* o_digi;     // per-digi cluster ids [n], in input order
+    int32_t* o_id;       // kept clusters (ascending id); room for n entries each, used as
+    int32_t* o_charge;   // per-cluster temporaries of the big-module kernel's scratch mode
+    int32_t* o_size;
+    u32 n;               // digis
+    u32 cap;             // workspace capacity in digis
+    u32 epoch;           // launch tag of the module-table words
+    u32 slot;            // launch parity: which present-module count this launch uses
+    u32 flags;           // EF_*
+    u32 pad[3];
 };
-static_assert(sizeof(EventDesc) == 64, "EventDesc is 64 bytes");
+static_assert(sizeof(EventDesc) == 144, "EventDesc is 144 bytes");
 
 // A module's digis [first, end), each word tagged with the launch (epoch << 32):
 // written by the digis at the module's boundaries, so an entry whose tags are not
@@ -116,6 +131,9 @@ struct EvLayout {
     size_t present;                          // module ids of the modules present (any order)
     size_t off;                              // per module: its first cluster in the outputs
     size_t hit_x, hit_y;                     // hits (per kept cluster), when asked for
+    size_t perm;                             // digis in any order: input index of each grouped digi
+    size_t grp;                              // digis in any order: the grouped copy (4 x u16[N])
+    size_t gcnt;                             // digis in any order: per module, digis counted (zero between launches)
     size_t total;
 };
 
@@ -143,6 +161,9 @@ PXCL_HD inline EvLayout ev_layout(u32 N, u32 M) {
     L.off = o;        o = al256(o + 4 * m);
     L.hit_x = o;      o = al256(o + 4 * n);
     L.hit_y = o;      o = al256(o + 4 * n);
+    L.perm = o;       o = al256(o + 4 * n);
+    L.grp = o;        o = al256(o + 8 * n);
+    L.gcnt = o;       o = al256(o + 4 * m);
     L.total = o;
     return L;
 }

@@ -98,6 +98,12 @@ template <typename T>
 __device__ __forceinline__ T* ws_ptr(const EventDesc& E, size_t off) {
     return reinterpret_cast<T*>(E.ws + off);
 }
+// Digis in any order: the input position of grouped digi p is perm[p]; per-digi
+// outputs go there.  nullptr when the digis came grouped (position p itself).
+__device__ __forceinline__ const u32* perm_of(const EventDesc& E, const EvLayout& L) {
+    return (E.flags & EF_UNSORTED) ? ws_ptr<const u32>(E, L.perm) : nullptr;
+}
+__device__ __forceinline__ u32 out_pos(const u32* perm, u32 p) { return perm ? perm[p] : p; }
 
 // Inclusive scan across the 64 lanes of a wave.
 __device__ __forceinline__ u32 wave_incl_scan(u32 v) {
@@ -283,6 +289,10 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
     const u32 tid = threadIdx.x;
     const u32 k = num_events(a);
     const u32 total = event_prefix<A_WG>(a, k, s_pref, s_wsum, CNT_DIGIS, CH, 0);
+    // The small kernel's ticket starts at zero in every launch: the compaction kernel
+    // of a finished launch resets it, and this reset also covers a launch whose later
+    // kernels were never queued.
+    if (blockIdx.x == 0 && tid == 0) st_ag(&a.ctr[S_TICK], 0u);
 
     for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
         if (tid == 0) s_err = 0;
@@ -399,9 +409,27 @@ __device__ __forceinline__ Item wave_uniform(const Item& I) {
                 wave_uniform(I.ok ? 1u : 0u) != 0};
 }
 __device__ __forceinline__ EventDesc wave_uniform(const EventDesc& E) {
-    return EventDesc{wave_uniform(E.module), wave_uniform(E.row), wave_uniform(E.col), wave_uniform(E.adc),
-                     wave_uniform(E.ws), wave_uniform(E.hstat), wave_uniform(E.n), wave_uniform(E.cap),
-                     wave_uniform(E.epoch), 0u};
+    EventDesc U{};
+    U.module = wave_uniform(E.module);
+    U.row = wave_uniform(E.row);
+    U.col = wave_uniform(E.col);
+    U.adc = wave_uniform(E.adc);
+    U.r_module = wave_uniform(E.r_module);
+    U.r_row = wave_uniform(E.r_row);
+    U.r_col = wave_uniform(E.r_col);
+    U.r_adc = wave_uniform(E.r_adc);
+    U.ws = wave_uniform(E.ws);
+    U.hstat = wave_uniform(E.hstat);
+    U.o_digi = wave_uniform(E.o_digi);
+    U.o_id = wave_uniform(E.o_id);
+    U.o_charge = wave_uniform(E.o_charge);
+    U.o_size = wave_uniform(E.o_size);
+    U.n = wave_uniform(E.n);
+    U.cap = wave_uniform(E.cap);
+    U.epoch = wave_uniform(E.epoch);
+    U.slot = wave_uniform(E.slot);
+    U.flags = wave_uniform(E.flags);
+    return U;
 }
 
 // Issue the loads of the module's digis j = lt + q*G < n (raw row, col, adc); the
@@ -600,11 +628,13 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
     gsync<G>();
     // P9: per-digi cluster id; clear the bitmap words used
     if (act) {
-        int32_t* od = ws_ptr<int32_t>(E, L.digi);
+        int32_t* od = E.o_digi;
+        const u32* perm = perm_of(E, L);
 #pragma unroll
         for (u32 q = 0; q < K; ++q) {
             const u32 j = lt + q * G;
-            if (q < nq && j < I.n) od[I.st + j] = (LIN[q] != NOPIX) ? int32_t(u32(gp.acc[AR[q] >> 16])) : -1;
+            if (q < nq && j < I.n)
+                od[out_pos(perm, I.st + j)] = (LIN[q] != NOPIX) ? int32_t(u32(gp.acc[AR[q] >> 16])) : -1;
         }
 #pragma unroll
         for (u32 q = 0; q < K; ++q)
@@ -1011,10 +1041,11 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     constexpr u32 KW = MAX_RUNS / 32, KPT = (KW + BW - 1) / BW;
     constexpr u32 SPAN = UNR * BW;
     const u32 tid = threadIdx.x, n = I.n, st = I.st;
-    u32* cid = ws_ptr<u32>(E, L.id) + st;        // per cluster: id (or -1 once cut)
-    u32* cch = ws_ptr<u32>(E, L.charge) + st;    // per cluster: charge
-    u32* csz = ws_ptr<u32>(E, L.size) + st;      // per cluster: size
-    int32_t* od = ws_ptr<int32_t>(E, L.digi) + st;
+    u32* cid = reinterpret_cast<u32*>(E.o_id) + st;       // per cluster: id (or -1 once cut)
+    u32* cch = reinterpret_cast<u32*>(E.o_charge) + st;   // per cluster: charge
+    u32* csz = reinterpret_cast<u32*>(E.o_size) + st;     // per cluster: size
+    int32_t* od = E.o_digi;
+    const u32* perm = perm_of(E, L);
     u32 err = 0;
     // UNR digis' linear index (NOPIX when absent or out of range), loads first
     auto fetch = [&](u32 base, u32* lin, u32* adc) {
@@ -1235,7 +1266,7 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
             const u32 j = base + u * BW + tid;
-            if (j < n) od[j] = lin[u] != NOPIX ? int32_t(ld_ag(&cid[c[u]])) : -1;
+            if (j < n) od[out_pos(perm, st + j)] = lin[u] != NOPIX ? int32_t(ld_ag(&cid[c[u]])) : -1;
         }
     }
     if (err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, err);
@@ -1308,14 +1339,20 @@ __global__ __launch_bounds__(S_WG) void k_scratch(LaunchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// compact: one wave per work unit (module) and one per event for its status.  A
-// module's first output position is the sum of the kept counts of all modules before
-// it (PS_UNR loads per lane in flight); the wave copies the module's records, CP_UNR
-// per lane at a time.
+// compact: one wave per block of C_BLK consecutive modules of an event (every module,
+// present or not: an absent module keeps nothing).  The block's first output position
+// is the sum of the kept counts of the modules before it, which the wave adds up
+// (PS_UNR loads per lane in flight); a wave scan over the block's 64 counts gives
+// every module its position, and the wave copies the block's records 64 at a time,
+// each lane finding its record's module by a search over that scan.  The wave of an
+// event's last block has the event's total and writes the status back to the host.
+// Loads per event grow as (modules / 64)^2 * 64, not modules^2.
 // ---------------------------------------------------------------------------
-constexpr u32 CP_UNR = 4, PS_UNR = 32, C_WAVES = C_WG / 64;
+constexpr u32 CP_UNR = 4, PS_UNR = 16, C_WAVES = C_WG / 64, C_BLK = 64;
 
-// Sum of kept[0, end) over the wave.
+__device__ __forceinline__ u32 compact_blocks(u32 n_modules) { return (n_modules + C_BLK - 1) / C_BLK; }
+
+// Sum of kept[0, end) over the wave (end a multiple of 64).
 __device__ __forceinline__ u32 kept_before(const u32* kept, u32 end, u32 lane) {
     u32 part = 0;
     for (u32 b = 0; b < end; b += 64 * PS_UNR) {
@@ -1332,77 +1369,73 @@ __device__ __forceinline__ u32 kept_before(const u32* kept, u32 end, u32 lane) {
 }
 
 __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
-    __shared__ u32 s_pref[MAXB + 1];
-    __shared__ u32 s_wsum[C_WG / 64];
     const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const u32 k = num_events(a), M = a.n_modules;
+    const u32 k = num_events(a), M = a.n_modules, nblk = compact_blocks(M);
     if (blockIdx.x == 0 && tid == 0) st_ag(&a.ctr[S_TICK], 0u);   // the small kernel has finished
-    u32 total;
-    if (k == 1 && (a.flags & LF_FUSED)) {         // every module a unit, no count to load
-        const EventDesc E0 = get_event(a, 0);
-        total = (E0.n ? M : 0u) + 1u;
-        if (tid == 0) {
-            s_pref[0] = 0;
-            s_pref[1] = total;
-        }
-        lds_barrier();
-    } else {
-        total = event_prefix<C_WG>(a, k, s_pref, s_wsum, CNT_UNITS, 1, 0, 1);       // + status unit
-    }
+    const u32 total = k * nblk;
     for (u32 u = wave_uniform(xcd_order(blockIdx.x, gridDim.x) * C_WAVES + wv); u < total; u += gridDim.x * C_WAVES) {
-        const u32 e = wave_uniform(find_slot(s_pref, k, u));
-        const u32 j = u - s_pref[e], np = s_pref[e + 1] - s_pref[e] - 1;
+        const u32 e = u / nblk, b = u - e * nblk;
         const EventDesc E = wave_uniform(get_event(a, e));
         const EvLayout L = ev_layout(E.cap, M);
         u32* ctl = ws_ptr<u32>(E, L.ctl);
         const u32* kept = ws_ptr<const u32>(E, L.kept);
-        if (j == np) {                                     // the event's status
-            const u32 ncl = E.n ? min(kept_before(kept, M, lane), E.n) : 0u;
-            if (lane == 0) {
-                const u32 err = ctl[CTL_ERR];
-                ctl[CTL_ERR] = 0u;
-                ctl[CTL_BIG] = 0u;                         // the big kernels have run
-                ctl[CTL_SCR] = 0u;
-                ctl[CTL_NCL] = ncl;
-                u32* hs = E.hstat;
-                st_sys(&hs[HS_ERR], err);
-                st_sys(&hs[HS_NCL], ncl);
-                st_sys(&hs[HS_EPOCH], E.epoch);
-            }
-            continue;
+        const u32 m = b * C_BLK + lane;
+        // an empty event's kept counts were never written: it has no clusters
+        const bool live = E.n != 0 && m < M;
+        u32 cnt = live ? kept[m] : 0u;
+        const u32 src = live ? u32(ws_ptr<const ModRange>(E, L.mtab)[m].first) : 0u;
+        const u32 base = E.n ? wave_uniform(kept_before(kept, b * C_BLK, lane)) : 0u;
+        if (cnt > E.n) cnt = 0u;                           // inconsistent (only after an input error)
+        const u32 incl = wave_incl_scan(cnt), excl = incl - cnt;
+        const u32 T = wave_uniform(__shfl(incl, 63, 64));
+        const bool fits = base <= E.n && T <= E.n - base;  // every position below n
+        if (b + 1 == nblk && lane == 0) {                  // the event's status
+            const u32 ncl = fits ? base + T : E.n;
+            const u32 err = ctl[CTL_ERR];
+            ctl[CTL_ERR] = 0u;
+            ctl[CTL_BIG] = 0u;                             // the big kernels have run
+            ctl[CTL_SCR] = 0u;
+            ctl[CTL_NCL] = ncl;
+            u32* hs = E.hstat;
+            st_sys(&hs[HS_ERR], err);
+            st_sys(&hs[HS_NCL], ncl);
+            st_sys(&hs[HS_EPOCH], E.epoch);
         }
-        const u32 m = wave_uniform(unit_module(a, E, L, np, j));
-        // count, offset and source loaded together (the offset also for a module that
-        // turns out to keep nothing: one dependent round less)
-        const u32 cnt = wave_uniform(kept[m]);
-        const u32 src = wave_uniform(u32(ws_ptr<const ModRange>(E, L.mtab)[m].first));
-        const u32 off = wave_uniform(kept_before(kept, m, lane));
-        if (cnt == 0) continue;                            // absent, or nothing kept
-        if (lane == 0) ws_ptr<u32>(E, L.off)[m] = off;
-        if (cnt > E.n || off > E.n - cnt || src > E.n - cnt) continue;   // inconsistent (flagged)
+        if (!fits || T == 0) continue;
+        if (cnt) ws_ptr<u32>(E, L.off)[m] = base + excl;
+        const bool src_ok = cnt == 0 || src <= E.n - cnt;
         const int32_t* tid_ = ws_ptr<const int32_t>(E, L.tid);
         const int32_t* tch = ws_ptr<const int32_t>(E, L.tcharge);
         const int32_t* tsz = ws_ptr<const int32_t>(E, L.tsize);
-        int32_t* oid = ws_ptr<int32_t>(E, L.id);
-        int32_t* och = ws_ptr<int32_t>(E, L.charge);
-        int32_t* osz = ws_ptr<int32_t>(E, L.size);
-        for (u32 j0 = 0; j0 < cnt; j0 += 64 * CP_UNR) {
+        int32_t* oid = E.o_id;
+        int32_t* och = E.o_charge;
+        int32_t* osz = E.o_size;
+        const u32 mod_src = src_ok ? src : NOPIX;          // a record of a bad module is skipped
+        for (u32 j0 = 0; j0 < T; j0 += 64 * CP_UNR) {
             int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
+            u32 from[CP_UNR];
 #pragma unroll
             for (u32 q = 0; q < CP_UNR; ++q) {
-                const u32 jj = j0 + q * 64 + lane;
-                const u32 js = jj < cnt ? jj : 0u;
-                r0[q] = tid_[src + js];
-                r1[q] = tch[src + js];
-                r2[q] = tsz[src + js];
+                const u32 j = j0 + q * 64 + lane;
+                // the module holding record j: the first lane whose inclusive count exceeds j
+                u32 lo = 0;
+#pragma unroll
+                for (u32 step = 32; step; step >>= 1)
+                    if (__shfl(incl, lo + step - 1, 64) <= j) lo += step;
+                const u32 s0 = __shfl(mod_src, lo, 64), x0 = __shfl(excl, lo, 64);
+                from[q] = (j < T && s0 != NOPIX) ? s0 + (j - x0) : NOPIX;
+                const u32 fs = from[q] != NOPIX ? from[q] : 0u;
+                r0[q] = tid_[fs];
+                r1[q] = tch[fs];
+                r2[q] = tsz[fs];
             }
 #pragma unroll
             for (u32 q = 0; q < CP_UNR; ++q) {
-                const u32 jj = j0 + q * 64 + lane;
-                if (jj < cnt) {
-                    oid[off + jj] = r0[q];
-                    och[off + jj] = r1[q];
-                    osz[off + jj] = r2[q];
+                const u32 j = j0 + q * 64 + lane;
+                if (from[q] != NOPIX) {
+                    oid[base + j] = r0[q];
+                    och[base + j] = r1[q];
+                    osz[base + j] = r2[q];
                 }
             }
         }
@@ -1438,9 +1471,10 @@ __global__ __launch_bounds__(H_WG) void k_hits(LaunchArgs a) {
         const u32 st = u32(r.first), nd = u32(r.end) - st;
         const u32 off = ws_ptr<const u32>(E, L.off)[mod];
         if (cnt > E.n || off > E.n - cnt || st > E.n || nd > E.n - st) continue;
-        const int32_t* ids = ws_ptr<const int32_t>(E, L.id) + off;
-        const int32_t* chg = ws_ptr<const int32_t>(E, L.charge) + off;
-        const int32_t* dcl = ws_ptr<const int32_t>(E, L.digi) + st;
+        const int32_t* ids = E.o_id + off;
+        const int32_t* chg = E.o_charge + off;
+        const int32_t* dcl = E.o_digi;
+        const u32* perm = perm_of(E, L);
         float* hx = ws_ptr<float>(E, L.hit_x) + off;
         float* hy = ws_ptr<float>(E, L.hit_y) + off;
         for (u32 c0 = 0; c0 < cnt; c0 += H_CAP) {
@@ -1453,7 +1487,7 @@ __global__ __launch_bounds__(H_WG) void k_hits(LaunchArgs a) {
             lds_barrier();
             const int32_t lo = s_id[0], hi = s_id[len - 1];
             for (u32 j = tid; j < nd; j += H_WG) {
-                const int32_t id = dcl[j];
+                const int32_t id = dcl[out_pos(perm, st + j)];
                 if (id < lo || id > hi) continue;          // cut (-1) or held by another chunk
                 u32 l = 0, h = len;
                 while (h - l > 1) {

@@ -219,7 +219,8 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
     g.b = u32(std::max<u64>(1, std::min<u64>(fb, digis / (dcap + 1))));
     g.x = u32(std::max<u64>(1, std::min<u64>(fx, digis / (BIG_RCAP + 1))));
     g.s = u32(std::max<u64>(1, std::min<u64>(fs, (present + mpw - 1) / mpw)));
-    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (present + k + C_WG / 64 - 1) / (C_WG / 64))));
+    const u64 blocks = u64(k) * ((ctx->n_modules + 63) / 64);       // compaction: a wave per 64 modules
+    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (blocks + C_WG / 64 - 1) / (C_WG / 64))));
     return g;
 }
 
@@ -244,9 +245,8 @@ bool digis_ok(const pxcl_digis* in) {
     return true;
 }
 
-// Stage host digis into the slot (async copies; one copy if the four arrays are
-// contiguous in the order module,row,col,adc) and describe the event.
-// The event as the kernels see it, its host inputs staged.  The launch parity
+// The event as the kernels see it, its host inputs staged into the slot (one async
+// copy per array: the caller's four arrays need not be adjacent).  The launch parity
 // alternates; after a launch whose work was not all queued the control words are
 // cleared first (a count that launch left would otherwise carry over).
 hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventDesc* d) {
@@ -257,8 +257,13 @@ hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventD
         ev->dirty = false;
     }
     ev->slot ^= 1u;
+    std::memset(d, 0, sizeof(*d));
     d->ws = ev->ws;
     d->hstat = ev->hs_dev;
+    d->o_digi = reinterpret_cast<int32_t*>(ev->ws + L.digi);
+    d->o_id = reinterpret_cast<int32_t*>(ev->ws + L.id);
+    d->o_charge = reinterpret_cast<int32_t*>(ev->ws + L.charge);
+    d->o_size = reinterpret_cast<int32_t*>(ev->ws + L.size);
     d->n = in->n;
     d->cap = ev->cap;
     d->epoch = ev->epoch;
@@ -575,13 +580,18 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
         ev->cb_pending.fetch_add(1, std::memory_order_acq_rel);
         completer_post(ctx, CK_EVENT, ev, ev->done_ev);
     }
-    if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
+        // part of the launch may be queued: let it drain before the slot is released
+        // (its kernels write the workspace; the next launch clears the control words)
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
         (void)hipGetLastError();
         ev->dirty = true;
         ev->state.store(ST_IDLE, std::memory_order_release);
+        if (prev != ctx->device) hipSetDevice(prev);
         return PXCL_E_HIP;
     }
+    if (prev != ctx->device) hipSetDevice(prev);
     ev->timed = timed;
     ev->timed_flags = a.flags;
     return PXCL_OK;
@@ -1117,16 +1127,22 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         for (u32 i = 0; i < k; ++i) evs[i]->cb_pending.fetch_add(1, std::memory_order_acq_rel);
         completer_post(ctx, CK_BATCH, b, b->done_ev);
     }
-    if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
+        // part of the launch may be queued: let it drain before the batch and its
+        // events are released (the segmentation kernel of the next launch resets the
+        // batch's ticket counter; the events' control words are cleared then too)
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
         (void)hipGetLastError();
         for (u32 i = 0; i < k; ++i) {
             evs[i]->dirty = true;
             evs[i]->state.store(ST_IDLE, std::memory_order_release);
         }
         b->state.store(ST_IDLE, std::memory_order_release);
+        if (prev != ctx->device) hipSetDevice(prev);
         return PXCL_E_HIP;
     }
+    if (prev != ctx->device) hipSetDevice(prev);
     b->timed = timed;
     b->timed_flags = lflags;
     return PXCL_OK;
@@ -1154,7 +1170,7 @@ extern "C" const char* pxcl_strerror(int code) {
         case PXCL_E_RANGE: return "module, row or column out of range";
         case PXCL_E_ORDER: return "digis not grouped by ascending module";
         case PXCL_E_HIP: return "HIP runtime error";
-        case PXCL_E_INTERNAL: return "internal error (device wait expired)";
+        case PXCL_E_INTERNAL: return "internal error (inconsistent device state or missing status write-back)";
         case PXCL_E_NOTFOUND: return "not found";
         case PXCL_E_HINT: return "a module has more digis than the size hint";
         default: return "unknown error";

@@ -222,9 +222,9 @@ class Digis:
                       int(self.max_module_digis))
 
     @staticmethod
-    def from_numpy(ev, device: str = "cuda", hint: bool = True) -> "Digis":
+    def from_numpy(ev, device: str = "cuda", hint: bool = False) -> "Digis":
         """Copy a numpy event; with `hint`, the largest number of digis sharing a
-        module id is passed as max_module_digis."""
+        module id (a host-side count over the event) is passed as max_module_digis."""
         ts = []
         for k in ("module", "row", "col", "adc"):
             t = torch.from_numpy(ev[k].astype("uint16", copy=True))

@@ -5,8 +5,8 @@
 // input:  u32 k, n_modules, cut, wg, mpw, grid_a, grid_b, grid_s, grid_c, header
 //         (1: the events go through a batch header even when k == 1), launch flags
 //         (LF_NO_BIG: the big-module kernel is not run; LF_SEG_WIDE: segmentation in
-//         wide chunks; LF_FUSED: no segmentation kernel), hits (1: run the hits kernel
-//         after the launch);
+//         wide chunks; LF_FUSED: no segmentation kernel; bit 31: the ticket counter
+//         starts non-zero), hits (1: run the hits kernel after the launch);
 //         per event: u32 n, u32 cap, u16 module[n], row[n], col[n], adc[n]
 // output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
 //         (with hits: then f32 x[nc], y[nc])
@@ -64,6 +64,10 @@ int main(int argc, char** argv) {
         d.adc = in[e].data() + 3 * size_t(n);
         d.ws = ws[e];
         d.hstat = hs[e];
+        d.o_digi = reinterpret_cast<int32_t*>(ws[e] + L.digi);
+        d.o_id = reinterpret_cast<int32_t*>(ws[e] + L.id);
+        d.o_charge = reinterpret_cast<int32_t*>(ws[e] + L.charge);
+        d.o_size = reinterpret_cast<int32_t*>(ws[e] + L.size);
         d.n = n;
         d.cap = cap;
         d.epoch = 1000 + e;
@@ -78,7 +82,10 @@ int main(int argc, char** argv) {
     a.n_modules = M;
     a.charge_cut = h[2];
     a.dcap = cluster_capacity(h[3], h[4]);
-    a.flags = h[10];
+    // bit 31 of the flags word is the driver's own: the launch starts with a ticket
+    // counter left non-zero (a launch before it stopped after the small kernel)
+    const bool stale_ticket = (h[10] >> 31) != 0;
+    a.flags = h[10] & 0x7FFFFFFFu;
     const bool use_header = h[9] != 0;
     if (k == 1 && !use_header) {
         a.single = evs[0];
@@ -90,6 +97,7 @@ int main(int argc, char** argv) {
         a.ctr = reinterpret_cast<u32*>(aligned_alloc(64, 64));
         memset(a.ctr, 0, 64);
     }
+    if (stale_ticket) a.ctr[S_TICK] = 1000003u;
     if ((!(a.flags & LF_FUSED) && launch_segment(a, h[5], nullptr)) || launch_small(h[3], h[4], a, h[7], nullptr) ||
         (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], h[6], nullptr)) || launch_compact(a, h[8], nullptr)) {
         fprintf(stderr, "launch failed\n");

@@ -222,3 +222,13 @@ def test_hits_kernel_many_clusters_per_module(emulator):
     assert ref["n_clusters"] > 2 * 2048
     compare(r, ref, "lattice")
     assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])
+
+
+def test_batch_launch_after_one_that_stopped_early(emulator):
+    """A batch launch whose ticket counter a previous launch left non-zero (that launch
+    stopped after its small kernel, so no compaction kernel reset it): the segmentation
+    kernel resets the counter, so modules handed out by ticket are still clustered."""
+    evs = [dict(synth.plain_event(20 + i, n_modules=6), n_modules=6) for i in range(4)]
+    # 24 present modules over a grid of 2 one-wave groups: the last rounds go by ticket
+    _check(emulator, evs, 6, wg=64, mpw=1, grids=(2, 2, 2, 2), header=True, stale_ticket=True)
+    _check(emulator, evs, 6, wg=256, mpw=2, grids=(2, 2, 1, 2), header=True, stale_ticket=True)

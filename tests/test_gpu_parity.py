@@ -218,14 +218,14 @@ def test_size_hint(px):
         px.wait(slot)
         return px.produce(slot).numpy()
 
-    d = px.Digis.from_numpy(big, "cuda")
+    d = px.Digis.from_numpy(big, "cuda", hint=True)
     assert d.max_module_digis == 3000
     compare(run(big, d), oracle.cluster_event(big, 2000), "hint above capacity")
     compare(run(big, px.Digis.from_numpy(big, "cuda", hint=False)), oracle.cluster_event(big, 2000), "no hint")
     d.max_module_digis = 100
     r = run(big, d)
     assert r["status"] == px.E_HINT and r["n_clusters"] <= big["module"].size
-    ds = px.Digis.from_numpy(small, "cuda")
+    ds = px.Digis.from_numpy(small, "cuda", hint=True)
     assert 0 < ds.max_module_digis <= 2048
     compare(run(small, ds), oracle.cluster_event(small, 2000), "hint within capacity")
     slot.close()

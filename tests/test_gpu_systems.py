@@ -305,3 +305,55 @@ def test_autotune_and_cache(px, batch_events, tmp_path):
         s.close()
     b.close()
     ctx.close()
+
+
+def _mutated(ev, **kw):
+    out = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
+    for k, (i, val) in kw.items():
+        out[k][i] = val
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_error_isolation(px, batch_events, graph):
+    """Errors travel with their own event: a batch holding one event with a pixel out
+    of range, one whose module ids decrease and one with a pixel fired twice, between
+    valid events.  Each bad event reports the oracle's status; every other event of the
+    batch is bit-exact; the batch callback reports the first event error."""
+    import torch
+    good = batch_events[:3]
+    n0 = batch_events[3]["module"].size
+    bad_range = _mutated(batch_events[3], row=(n0 // 2, 160))
+    n1 = batch_events[4]["module"].size
+    bad_order = _mutated(batch_events[4], module=(0, int(batch_events[4]["module"][-1])))
+    e5 = batch_events[5]
+    bad_dup = _mutated(e5, row=(1, int(e5["row"][0])), col=(1, int(e5["col"][0])), module=(1, int(e5["module"][0])))
+    evs = [good[0], bad_range, good[1], bad_order, bad_dup, good[2]]
+    refs = [oracle.cluster_event(e, 2000) for e in evs]
+    assert [r["status"] for r in refs] == [0, px.E_RANGE, 0, px.E_ORDER, px.E_DUP_PIXEL, 0], \
+        [r["status"] for r in refs]
+    ctx = px.Context(1856)
+    b = px.Batch(ctx, 8)
+    slots = [px.Event(ctx, max(e["module"].size for e in evs)) for _ in evs]
+    for rep in range(2):                                 # a second launch of the same slots
+        print(f"error isolation graph={graph} rep {rep}", flush=True)
+        f = px.Flag()
+        digis = [px.Digis.from_numpy(e, "cuda", hint=False) for e in evs]
+        px.acquire_batch(b, slots, digis, flag=f, graph=graph)
+        for s in slots:
+            px.wait(s)
+        t0 = time.time()
+        while f.fired == 0:
+            assert time.time() - t0 < 30
+        assert f.status == px.E_RANGE, "the batch reports the first event error"
+        for i, (s, r) in enumerate(zip(slots, refs)):
+            compare(px.produce(s).numpy(), r, f"graph={graph} rep {rep} event {i}")
+        torch.ones(1000, device="cuda").sum().item()
+    # the same slots with valid events afterwards
+    res = run_events(px, ctx, batch_events[:6], batch=b, graph=graph, slots=slots)
+    for i, (r, e) in enumerate(zip(res, batch_events[:6])):
+        compare(r, oracle.cluster_event(e, 2000), f"after errors, event {i}")
+    for s in slots:
+        s.close()
+    b.close()
+    ctx.close()
