@@ -547,6 +547,7 @@ def bench_serve(px, torch, args, evs):
                      "hbm_frac_whole_job": round(mean_b * rate / 1e9 / HBM_PEAK_GBS, 5)})
     for b in batches:
         b.close()
+    shape = list(ctx.kernel_config())
     ctx.close()
     mid = runs[1]
     return {
@@ -555,7 +556,7 @@ def bench_serve(px, torch, args, evs):
         "saturated_events_per_s": round(sat, 1), "runs": runs,
         "config": {"workload": "serve: Poisson arrivals, 10k-200k digis/event, 16 GB admission budget, "
                                "continuous batching over 8 streams, 16 CPU threads with 20 us synthetic tasks",
-                   "requests_per_run": SERVE_REQUESTS, "kernel_config": list(ctx.kernel_config()),
+                   "requests_per_run": SERVE_REQUESTS, "kernel_config": shape,
                    "autotune_us": tuned, "value_is": "the run at 0.7 of the saturated rate"},
     }
 
