@@ -375,6 +375,49 @@ int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void* h_pinned,
                void* d_results /* device, or NULL */,
                const uint64_t* result_offsets /* [n_requests] byte offsets, or NULL */);
 
+/* ---- allocation-free clustering of one event ------------------------------------ */
+/* For callers that cannot allocate device memory or bind a workspace: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The same
+ * kernels as pxcl_acquire cluster one event whose digis are in device memory, but
+ * their scratch (control words, per-module table and lists, cluster records before
+ * compaction) lives in a fixed device array of the library, one per GPU, held until
+ * the process ends: PXCL_NOALLOC_SCRATCH_BYTES, sized for events of at most
+ * PXCL_NOALLOC_MAX_DIGIS digis and PXCL_MAX_MODULES modules.  Nothing is allocated,
+ * freed or bound by the call; the array's address on each device is looked up once,
+ * by pxcl_ctx_create on that device.
+ *
+ * Stream-ordered, no callback: the work is queued on `stream` (hipStream_t) and the
+ * results are complete when the stream reaches that point (synchronise, record an
+ * event, or capture the call into a graph).  `in` must be device digis
+ * (PXCL_WHERE_DEVICE), grouped by module as for pxcl_acquire; max_module_digis is
+ * honoured the same way.  Outputs, caller-owned device memory:
+ *   digi_cluster [n]  per-digi cluster id, -1 if cut;
+ *   id, charge, size [n each]  kept clusters in ascending id in the first
+ *       n_clusters entries (all n entries may be written: they also hold
+ *       per-cluster temporaries of the largest modules);
+ *   status [16 words, 4-byte aligned]  written at the end of the work: word 0 the
+ *       call's launch tag (also returned in *tag), word 1 the PXCL_ERRBIT_* error bits
+ *       of the event, word 2 the number of kept clusters.
+ * A call with n = 0 writes only status.  Returns PXCL_E_CAPACITY if n exceeds
+ * PXCL_NOALLOC_MAX_DIGIS (nothing queued), PXCL_E_INVAL for a null or host input or
+ * a null output, PXCL_E_HIP if the device array could not be located or a launch
+ * failed.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads without ordering) race and give
+ * wrong results.  Calls in one stream, or otherwise ordered, are safe; after a
+ * failed launch the next call clears the control words with a kernel first. */
+#define PXCL_NOALLOC_MAX_DIGIS 262144u
+#define PXCL_NOALLOC_SCRATCH_BYTES 15972352u
+typedef struct {
+    int32_t* digi_cluster;
+    int32_t* id;
+    int32_t* charge;
+    int32_t* size;
+    uint32_t* status;
+} pxcl_noalloc_out;
+int pxcl_cluster_noalloc(pxcl_ctx* ctx, const pxcl_digis* in, const pxcl_noalloc_out* out,
+                         void* stream, uint32_t* tag);
+
 /* ---- misc --------------------------------------------------------------------- */
 const char* pxcl_strerror(int code);
 /* Library version string. */

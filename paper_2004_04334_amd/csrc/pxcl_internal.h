@@ -63,7 +63,7 @@ constexpr u32 LF_SEG_WIDE = 2;   // segmentation in wide chunks
 constexpr u32 LF_FUSED = 4;      // one event, no segmentation kernel: the small kernel
                                  // finds every module's digis by search
 constexpr u32 LF_NO_SCRATCH = 8; // the scratch-mode kernel is not launched (size hint)
-__host__ __device__ constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
+PXCL_HD constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
 // Event flags (EventDesc::flags).
 constexpr u32 EF_UNSORTED = 1;   // the digis are in any order: the grouping kernels read them
@@ -116,7 +116,7 @@ struct LaunchArgs {
     EventDesc single;
 };
 
-PXCL_HD inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+PXCL_HD constexpr size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte offsets of the arrays of an event workspace with capacity N digis and M
 // modules per event.
@@ -137,8 +137,8 @@ struct EvLayout {
     size_t total;
 };
 
-PXCL_HD inline EvLayout ev_layout(u32 N, u32 M) {
-    EvLayout L;
+PXCL_HD constexpr EvLayout ev_layout(u32 N, u32 M) {
+    EvLayout L{};
     size_t o = 0;
     const size_t n = N, m = M;
     L.ctl = o;        o = al256(o + CTL_WORDS * 4);

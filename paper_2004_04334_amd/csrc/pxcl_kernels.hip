@@ -1511,6 +1511,15 @@ __global__ __launch_bounds__(H_WG) void k_hits(LaunchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// fill: n words at p set to v (clears control words with a kernel node, which a
+// caller's graph capture may record, instead of a memset node)
+// ---------------------------------------------------------------------------
+constexpr u32 F_WG = 256;
+__global__ __launch_bounds__(F_WG) void k_fill(u32* p, u32 n, u32 v) {
+    for (u32 i = blockIdx.x * F_WG + threadIdx.x; i < n; i += gridDim.x * F_WG) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
 // host-side launch helpers
 // ---------------------------------------------------------------------------
 typedef void (*SmallKernel)(LaunchArgs);
@@ -1572,6 +1581,12 @@ hipError_t launch_big(const LaunchArgs& a, u32 grid, u32 grid_scratch, hipStream
 }
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(grid), dim3(C_WG), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_fill(u32* p, u32 n, u32 v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const u32 grid = std::min<u32>((n + F_WG - 1) / F_WG, 1024u);
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(F_WG), 0, s, p, n, v);
     return hipGetLastError();
 }
 int occupancy_hits() { return occ(reinterpret_cast<const void*>(k_hits), H_WG); }

@@ -41,6 +41,7 @@ int occupancy_scratch();
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
 int occupancy_hits();
 hipError_t launch_hits(const LaunchArgs& a, u32 grid, hipStream_t s);
+hipError_t launch_fill(u32* p, u32 n, u32 v, hipStream_t s);
 }  // namespace pxcl
 
 using namespace pxcl;
@@ -370,6 +371,52 @@ static void completer_post(pxcl_ctx* ctx, int kind, void* obj, hipEvent_t done) 
 }
 
 // ---------------------------------------------------------------------------
+// scratch of the allocation-free entry point: one fixed event workspace per GPU
+// (capacity PXCL_NOALLOC_MAX_DIGIS digis, PXCL_MAX_MODULES modules).  In host code
+// `scratch` is only a stand-in for the symbol: its device address on each GPU comes
+// from hipGetSymbolAddress, looked up once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr u32 NOALLOC_CAP = PXCL_NOALLOC_MAX_DIGIS;
+static_assert(ev_layout(NOALLOC_CAP, PXCL_MAX_MODULES).total == PXCL_NOALLOC_SCRATCH_BYTES,
+              "PXCL_NOALLOC_SCRATCH_BYTES matches the workspace layout");
+static __device__ __align__(256) u8 scratch[PXCL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_DEVICES = 64;
+struct NoAllocDevice {
+    std::once_flag once;
+    u8* ptr = nullptr;                  // device address of `scratch` on this device
+    std::atomic<u32> slot{0};           // launch parity of the calls on this device
+    std::atomic<bool> dirty{false};     // a launch failed: clear the control words first
+};
+NoAllocDevice g_noalloc[NOALLOC_DEVICES];
+
+// Once per device, with `device` current: locate the array and clear its control
+// words and module table (set-up time, so a blocking wait is allowed here).
+void noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_DEVICES) return;
+    NoAllocDevice& d = g_noalloc[device];
+    std::call_once(d.once, [&d] {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return;                           // the entry point then reports PXCL_E_HIP
+        }
+        u8* base = static_cast<u8*>(p);
+        const EvLayout L = ev_layout(NOALLOC_CAP, PXCL_MAX_MODULES);
+        hipError_t e = launch_fill(reinterpret_cast<u32*>(base + L.ctl), CTL_WORDS, 0u, nullptr);
+        if (e == hipSuccess) e = launch_fill(reinterpret_cast<u32*>(base + L.mtab), 4u * PXCL_MAX_MODULES, 0u, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        d.ptr = base;
+    });
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** out) {
@@ -399,6 +446,7 @@ extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** ou
     c->occ_x = occupancy_scratch();
     c->occ_c = occupancy_compact();
     c->occ_h = occupancy_hits();
+    noalloc_setup(device);
     hipSetDevice(prev);
     try {
         c->comp.th = std::thread(completer_loop, &c->comp, device);
@@ -667,6 +715,61 @@ extern "C" void pxcl_flag_cb(void* user, int32_t status) {
     if (!f) return;
     f->status = status;
     __atomic_fetch_add(&f->fired, 1u, __ATOMIC_RELEASE);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free clustering of one event: pxcl_acquire's kernels over the device's
+// fixed scratch array, with the caller's outputs; stream-ordered, no callback
+// ---------------------------------------------------------------------------
+extern "C" int pxcl_cluster_noalloc(pxcl_ctx* ctx, const pxcl_digis* in, const pxcl_noalloc_out* out,
+                                    void* stream, uint32_t* tag) {
+    if (!ctx || !digis_ok(in) || !out || !out->status) return PXCL_E_INVAL;
+    if (in->where != PXCL_WHERE_DEVICE) return PXCL_E_INVAL;
+    if (in->n && (!out->digi_cluster || !out->id || !out->charge || !out->size)) return PXCL_E_INVAL;
+    if (in->n > NOALLOC_CAP) return PXCL_E_CAPACITY;
+    if (ctx->device < 0 || ctx->device >= NOALLOC_DEVICES) return PXCL_E_HIP;
+    NoAllocDevice& d = g_noalloc[ctx->device];
+    u8* ws = d.ptr;
+    if (!ws) return PXCL_E_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const u32 wg = ctx->wg.load(), mpw = ctx->mpw.load();
+    const EvLayout L = ev_layout(NOALLOC_CAP, ctx->n_modules);
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ctr = reinterpret_cast<u32*>(ws + L.ctl) + CTL_CTR;
+    a.n_modules = ctx->n_modules;
+    a.charge_cut = ctx->charge_cut;
+    a.dcap = cluster_capacity(wg, mpw);
+    if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
+    if (in->max_module_digis && in->max_module_digis <= BIG_RCAP) a.flags |= LF_NO_SCRATCH;
+    a.flags |= LF_FUSED;
+    EventDesc& E = a.single;
+    E.module = in->module; E.row = in->row; E.col = in->col; E.adc = in->adc;
+    E.ws = ws;
+    E.hstat = out->status;
+    E.o_digi = out->digi_cluster;
+    E.o_id = out->id;
+    E.o_charge = out->charge;
+    E.o_size = out->size;
+    E.n = in->n;
+    E.cap = NOALLOC_CAP;
+    E.epoch = next_epoch();
+    E.slot = d.slot.fetch_add(1u, std::memory_order_relaxed) & 1u;
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    hipError_t e = hipSuccess;
+    if (d.dirty.exchange(false)) e = launch_fill(reinterpret_cast<u32*>(ws + L.ctl), CTL_WORDS, 0u, s);
+    const Grids g = grids_for(ctx, wg, mpw, in->n, in->n ? ctx->n_modules : 0u, 1, a.flags, false);
+    if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, nullptr);
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        d.dirty.store(true);
+        return PXCL_E_HIP;
+    }
+    if (tag) *tag = E.epoch;
+    return PXCL_OK;
 }
 
 // ---------------------------------------------------------------------------

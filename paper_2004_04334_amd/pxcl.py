@@ -65,6 +65,11 @@ class _Clusters(ctypes.Structure):
                 ("done_event", ctypes.c_void_p), ("device", ctypes.c_int32)]
 
 
+class _NoAllocOut(ctypes.Structure):
+    _fields_ = [("digi_cluster", ctypes.c_void_p), ("id", ctypes.c_void_p), ("charge", ctypes.c_void_p),
+                ("size", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
 class Flag(ctypes.Structure):
     """Host word pair written by the library's ready-made callback ``pxcl_flag_cb``."""
     _fields_ = [("status", ctypes.c_int32), ("fired", ctypes.c_uint32)]
@@ -145,6 +150,8 @@ _SIGS = {
                                   ctypes.POINTER(ServeOpts), ctypes.POINTER(RunStats),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32),
                                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "pxcl_cluster_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Digis), ctypes.POINTER(_NoAllocOut),
+                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "pxcl_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pxcl_version": (ctypes.c_char_p, []),
 }
@@ -571,3 +578,51 @@ def serve(ctx: Context, arena: torch.Tensor, pinned: torch.Tensor, batches: Sequ
                             (ctypes.c_uint64 * n_requests)(*result_offsets) if result_offsets is not None
                             else None), "serve")
     return st.as_dict(), list(rs), list(rn)
+
+
+NOALLOC_MAX_DIGIS = 262144
+ERRBIT_RANGE, ERRBIT_ORDER, ERRBIT_DUP, ERRBIT_INTERNAL, ERRBIT_HINT = 1, 2, 4, 8, 16
+
+
+def status_from_bits(bits: int) -> int:
+    """The status an event with these error bits reports (precedence RANGE, ORDER,
+    HINT, DUP, INTERNAL)."""
+    for bit, code in ((ERRBIT_RANGE, E_RANGE), (ERRBIT_ORDER, E_ORDER), (ERRBIT_HINT, E_HINT),
+                      (ERRBIT_DUP, E_DUP_PIXEL), (ERRBIT_INTERNAL, E_INTERNAL)):
+        if bits & bit:
+            return code
+    return OK
+
+
+class NoAllocOutputs:
+    """Caller-owned device outputs of ``cluster_noalloc`` for events of up to
+    `max_digis` digis (allocated here, once, by torch; the call itself allocates
+    nothing)."""
+
+    def __init__(self, max_digis: int, device: int = 0):
+        n = max(1, int(max_digis))
+        dev = f"cuda:{device}"
+        self.digi, self.id, self.charge, self.size = (torch.empty(n, dtype=torch.int32, device=dev) for _ in range(4))
+        self.status = torch.zeros(16, dtype=torch.int32, device=dev)
+        self.s = _NoAllocOut(self.digi.data_ptr(), self.id.data_ptr(), self.charge.data_ptr(),
+                             self.size.data_ptr(), self.status.data_ptr())
+
+    def numpy(self, n_digis: int, tag: int) -> dict:
+        """Results once the stream has passed the call."""
+        st = self.status.cpu().numpy().view(np.uint32)
+        bits = int(st[1]) | (ERRBIT_INTERNAL if int(st[0]) != tag else 0)
+        k = min(int(st[2]), n_digis)
+        return {"status": status_from_bits(bits), "err_bits": bits, "n_clusters": k,
+                "id": self.id[:k].cpu().numpy(), "charge": self.charge[:k].cpu().numpy(),
+                "size": self.size[:k].cpu().numpy(), "digi": self.digi[:n_digis].cpu().numpy()}
+
+
+def cluster_noalloc(ctx: Context, digis: Digis, out: NoAllocOutputs, stream=None) -> int:
+    """Queue the clustering of one device-resident event on ``stream`` with the
+    library's fixed per-device scratch (nothing allocated); returns the call's launch
+    tag.  Results are in ``out`` once the stream has passed this point."""
+    d = digis.struct()
+    tag = ctypes.c_uint32()
+    _check(lib().pxcl_cluster_noalloc(ctx.handle, ctypes.byref(d), ctypes.byref(out.s), _stream_ptr(stream),
+                                      ctypes.byref(tag)), "cluster_noalloc")
+    return int(tag.value)
