@@ -311,8 +311,18 @@ def tune(px, ctx, args, events, digis, slots=None, batch=None):
     return {f"{wg}x{mpw}": round(t, 1) for (wg, mpw), t in sorted(times.items())}
 
 
+def shuffled(evs, seed=2004):
+    """The same events with their digis in a seeded random order (every event's own
+    permutation): the input of the any-order form."""
+    out = []
+    for i, e in enumerate(evs):
+        p = np.random.default_rng([seed, i]).permutation(e["module"].size)
+        out.append({k: (v[p] if isinstance(v, np.ndarray) else v) for k, v in e.items()})
+    return out
+
+
 def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, steps, warmup, hint=False,
-             timed=True):
+             timed=True, any_order=False):
     """Graph-replayed batches over `n_copies` device-resident copies of the events (a
     working set larger than the 256 MB Infinity Cache); each copy has its own batch
     object and event slots, so the host only waits when it wraps around.  Then the
@@ -325,7 +335,7 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, steps, w
     cap = max(e["module"].size for e in evs)
     groups = []
     for c in range(n_copies if timed else 1):
-        digis = [px.Digis.from_numpy(e, "cuda", hint=hint) for e in evs]
+        digis = [px.Digis.from_numpy(e, "cuda", hint=hint, any_order=any_order) for e in evs]
         slots = [px.Event(ctx, cap) for _ in range(per_batch)]
         groups.append((px.Batch(ctx, per_batch), slots, digis, px.BatchInputs(slots, digis)))
     n_groups = len(groups)
@@ -386,7 +396,8 @@ def _batched(px, torch, args, evs, n_copies, per_batch, workload, desc, steps, w
     out.update({
         "config": {"workload": desc, "n_modules": 1856, "events_per_launch": per_batch,
                    "mean_digis": int(np.mean([e["module"].size for e in evs])), "device_copies": n_groups,
-                   "streams": N_STREAMS, "size_hint": bool(hint), "kernel_config": list(ctx.kernel_config()),
+                   "streams": N_STREAMS, "size_hint": bool(hint), "any_order": bool(any_order),
+                   "kernel_config": list(ctx.kernel_config()),
                    "autotune_us": tuned},
         "roofline": rl})
     ctx.close()
@@ -411,15 +422,21 @@ def bench_batch(px, torch, args, evs, steps, warmup, timed=True):
         r["with_size_hint"] = {"value": round(h["value"], 2), "digis_per_s": round(h["digis_per_s"], 1),
                                "note": "every event's largest module passed as max_module_digis (host-side "
                                        "bincount outside the timed region): the scratch-mode kernel is skipped"}
+        u = _batched(px, torch, args, shuffled(evs), 8, 64, "batch", BATCH_DESC, steps, warmup, any_order=True)
+        r["any_order"] = {"value": round(u["value"], 2), "digis_per_s": round(u["digis_per_s"], 1),
+                          "kernel_mean_us": u["roofline"]["kernel_mean_us"],
+                          "note": "the same events with their digis shuffled, grouped by module on the device "
+                                  "(counting sort: count, table, scatter) in the segment slot"}
     return r
 
 
-def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda", hint=False, shape=None):
+def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda", hint=False, shape=None,
+                any_order=False):
     """4 host threads, one event in flight each, synthetic 20 us CPU tasks while waiting;
     the rate is over the driver's own timed window (after its threads are ready)."""
     n_threads = 4
     ctx = px.Context(1856, 2000)
-    pool = [px.Digis.from_numpy(e, where, hint=hint) for e in evs]
+    pool = [px.Digis.from_numpy(e, where, hint=hint, any_order=any_order) for e in evs]
     cap = max(e["module"].size for e in evs)
     slots = [px.Event(ctx, cap) for _ in range(n_threads)]
     streams = [torch.cuda.Stream() for _ in range(n_threads)]
@@ -679,6 +696,11 @@ def main():
         a["host_staged"] = _round({k: hs[k] for k in ("value", "digis_per_s", "lat_p50_us", "lat_p99_us",
                                                       "host_blocked_us_per_event")})
         a["host_staged"]["note"] = "input in pinned host memory: a PCIe copy of 8 B/digi per event, never in value"
+        u = bench_async(px, torch, args, shuffled(evsets["async"]), SUB_STEPS["async"], shape=shape, any_order=True)
+        a["any_order"] = _round({k: u[k] for k in ("value", "digis_per_s", "lat_p50_us", "lat_p99_us")})
+        a["any_order"]["kernel_mean_us"] = u["roofline"]["kernel_mean_us"]
+        a["any_order"]["note"] = ("the same events with their digis shuffled, grouped by module on the device "
+                                  "(counting sort: count, table, scatter) in the segment slot")
         subs["async"] = sub_record(a, evsets["async"], args)
         print("bench: plain", file=sys.stderr, flush=True)
         subs["plain"] = sub_record(bench_plain(px, torch, args, evsets["plain"], SUB_STEPS["plain"]),

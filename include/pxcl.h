@@ -100,7 +100,13 @@ typedef struct {
 #define PXCL_WHERE_DEVICE 1   /* device memory on the context's device */
 
 /* Input digis: structure of arrays, grouped by non-decreasing module id, any order
- * within a module.  All four arrays hold n uint16 values and must stay valid and
+ * within a module -- or, with PXCL_DIGIS_ANY_ORDER in flags, in any order at all
+ * (the raw data of the paper's Figure 1 carries no grouping): the library then
+ * groups them by module on the device with a counting sort (per-chunk module
+ * histograms, a scan of the module totals, a scatter into a grouped copy in the
+ * event workspace) before the clustering, every per-digi output still goes to the
+ * digi's input position, and PXCL_E_ORDER cannot occur.  The result is the same as
+ * for the grouped digis.  All four arrays hold n uint16 values and must stay valid and
  * unmodified until the done callback has fired.
  * max_module_digis: optional upper bound on the digis of any one module (0 =
  * unknown).  When it is at most the small-module kernel's capacity (workgroup size /
@@ -115,7 +121,9 @@ typedef struct {
     uint32_t n;
     int32_t where;        /* PXCL_WHERE_HOST or PXCL_WHERE_DEVICE */
     uint32_t max_module_digis;
+    uint32_t flags;       /* 0 or PXCL_DIGIS_ANY_ORDER */
 } pxcl_digis;
+#define PXCL_DIGIS_ANY_ORDER 1u
 
 /* Completion callback.  Runs on the context's completion thread once the event's
  * (or batch's) device work and status write-back are complete; status = PXCL_OK or

@@ -63,12 +63,15 @@ constexpr u32 LF_SEG_WIDE = 2;   // segmentation in wide chunks
 constexpr u32 LF_FUSED = 4;      // one event, no segmentation kernel: the small kernel
                                  // finds every module's digis by search
 constexpr u32 LF_NO_SCRATCH = 8; // the scratch-mode kernel is not launched (size hint)
+constexpr u32 LF_GROUP = 16;     // some event is in any order: the grouping kernels run first
+constexpr u32 LF_NO_SEG = 32;    // no event is grouped by module: no segmentation kernel
 PXCL_HD constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
 // Event flags (EventDesc::flags).
 constexpr u32 EF_UNSORTED = 1;   // the digis are in any order: the grouping kernels read them
                                  // from r_*, write a copy grouped by module to the workspace
-                                 // (module..adc point there) and the permutation back
+                                 // (module..adc point there) and each grouped digi's input
+                                 // position (perm), where its per-digi output goes
 
 // One event as the kernels see it (144 bytes).
 struct EventDesc {

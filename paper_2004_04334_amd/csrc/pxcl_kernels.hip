@@ -152,8 +152,11 @@ __device__ __forceinline__ u32 find_slot(const u32* pref, u32 k, u32 t) {
     return lo;
 }
 
-// What event_prefix counts per event.
-constexpr u32 CNT_DIGIS = 0, CNT_MODULES = 0xFFFFFFFFu, CNT_UNITS = 0xFFFFFFFEu;
+// What event_prefix counts per event: its digis (CNT_DIGIS), the digis of an event
+// grouped by module (CNT_SORTED: zero for digis in any order) or in any order
+// (CNT_ANY: zero for grouped ones), the modules per event, its work units.
+constexpr u32 CNT_DIGIS = 0, CNT_MODULES = 0xFFFFFFFFu, CNT_UNITS = 0xFFFFFFFEu, CNT_SORTED = 0xFFFFFFFDu,
+              CNT_ANY = 0xFFFFFFFCu;
 
 // Modules on the event's present-module list.
 __device__ __forceinline__ u32 present_count(const LaunchArgs& a, const EventDesc& E) {
@@ -192,6 +195,8 @@ __device__ __forceinline__ u32 event_prefix(const LaunchArgs& a, u32 k, u32* pre
             u32 cnt = 0;
             if (E.n)
                 cnt = which == CNT_DIGIS     ? E.n
+                      : which == CNT_SORTED  ? ((E.flags & EF_UNSORTED) ? 0u : E.n)
+                      : which == CNT_ANY     ? ((E.flags & EF_UNSORTED) ? E.n : 0u)
                       : which == CNT_MODULES ? a.n_modules
                       : which == CNT_UNITS   ? unit_count(a, E)
                                              : min(ld_ag(ws_ptr<u32>(E, ev_layout(E.cap, a.n_modules).ctl) + which), a.n_modules);
@@ -273,6 +278,186 @@ __device__ __forceinline__ void link_right(u32* par, const u32* bm, const u16* r
 }
 
 // ---------------------------------------------------------------------------
+// group (digis in any order): a counting sort by module ahead of the clustering,
+// which then reads a grouped copy in the event workspace and writes every per-digi
+// output at the digi's input position (perm).  Three kernels:
+//   count    per chunk of G_CH digis an LDS histogram over the modules gives each
+//            digi its rank among the chunk's digis of its module; one device atomic
+//            per (chunk, module present in it) adds the chunk's count to the module's
+//            total and returns the chunk's base, so a digi's rank in its module is
+//            base + local rank.  The rank is parked in the per-digi output word (the
+//            clustering overwrites it).  Module ids at or above the module count set
+//            EB_RANGE and the digi takes no part.
+//   table    one workgroup per event: an exclusive scan of the module totals gives
+//            each module its first grouped position; module-table entries tagged with
+//            the launch, the present-module list in ascending module order, kept
+//            counts and totals cleared -- the segmentation kernel's outputs.
+//   scatter  every digi goes to first[module] + rank of the grouped copy, and its
+//            input position to perm.
+// A digi's place within its module is not fixed (chunks take their bases in any
+// order); the clustering does not depend on it.
+// ---------------------------------------------------------------------------
+constexpr u32 NOPIX = 0xFFFFFFFFu;          // no pixel / no index
+constexpr u32 G_WG = 256, G_PER = 16, G_CH = G_WG * G_PER, G_HMAX = 4096, G_TPM = 8;
+
+struct GroupArrays {
+    u16 *m, *r, *c, *a;
+    u32* perm;
+};
+__device__ __forceinline__ GroupArrays group_arrays(const EventDesc& E, const EvLayout& L) {
+    u16* g = ws_ptr<u16>(E, L.grp);
+    const size_t N = E.cap;
+    return GroupArrays{g, g + N, g + 2 * N, g + 3 * N, ws_ptr<u32>(E, L.perm)};
+}
+
+__global__ __launch_bounds__(G_WG) void k_group_count(LaunchArgs a) {
+    __shared__ u32 hist[G_HMAX];
+    __shared__ u32 s_pref[MAXB + 1];
+    __shared__ u32 s_wsum[G_WG / 64];
+    __shared__ u32 s_err;
+    const u32 tid = threadIdx.x, k = num_events(a), M = a.n_modules;
+    const bool lds = M <= G_HMAX;                 // else ranks straight from the totals
+    const u32 total = event_prefix<G_WG>(a, k, s_pref, s_wsum, CNT_ANY, G_CH, 0);
+    // the small kernel's ticket starts at zero (segmentation, which also resets it,
+    // is not launched when every event of the launch is in any order)
+    if (blockIdx.x == 0 && tid == 0) st_ag(&a.ctr[S_TICK], 0u);
+    for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
+        const u32 e = find_slot(s_pref, k, t), c = t - s_pref[e];
+        const EventDesc E = get_event(a, e);
+        const EvLayout L = ev_layout(E.cap, M);
+        u32* gcnt = ws_ptr<u32>(E, L.gcnt);
+        u32* rank = reinterpret_cast<u32*>(E.o_digi);
+        if (tid == 0) s_err = 0;
+        if (lds)
+            for (u32 m = tid; m < M; m += G_WG) hist[m] = 0u;
+        lds_barrier();
+        const u32 i0 = c * G_CH + tid;
+        u32 mm[G_PER], lr[G_PER];
+#pragma unroll
+        for (u32 q = 0; q < G_PER; ++q) {
+            const u32 i = i0 + q * G_WG;
+            mm[q] = i < E.n ? u32(E.r_module[i]) : NOPIX;
+        }
+        u32 err = 0;
+#pragma unroll
+        for (u32 q = 0; q < G_PER; ++q) {
+            lr[q] = 0u;
+            if (mm[q] == NOPIX) continue;
+            if (mm[q] >= M) {
+                err |= EB_RANGE;
+                mm[q] = NOPIX;
+            } else {
+                lr[q] = lds ? atomicAdd(&hist[mm[q]], 1u) : atomicAdd(&gcnt[mm[q]], 1u);
+            }
+        }
+        lds_barrier();
+        if (lds)
+            for (u32 m = tid; m < M; m += G_WG) {
+                const u32 h = hist[m];
+                if (h) hist[m] = atomicAdd(&gcnt[m], h);
+            }
+        lds_barrier();
+#pragma unroll
+        for (u32 q = 0; q < G_PER; ++q)
+            if (mm[q] != NOPIX) rank[i0 + q * G_WG] = (lds ? hist[mm[q]] : 0u) + lr[q];
+        if (err) atomicOr(&s_err, err);
+        lds_barrier();
+        if (tid == 0 && s_err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, s_err);
+        lds_barrier();                            // hist and s_err are reused by the next chunk
+    }
+}
+
+__global__ __launch_bounds__(G_WG) void k_group_table(LaunchArgs a) {
+    __shared__ u32 s_wsum[G_WG / 64];
+    const u32 tid = threadIdx.x, k = num_events(a), M = a.n_modules;
+    for (u32 e = blockIdx.x; e < k; e += gridDim.x) {
+        const EventDesc E = get_event(a, e);
+        if (!(E.flags & EF_UNSORTED)) continue;  // the same event for the whole workgroup
+        const EvLayout L = ev_layout(E.cap, M);
+        u32* gcnt = ws_ptr<u32>(E, L.gcnt);
+        u32* kept = ws_ptr<u32>(E, L.kept);
+        u32* present = ws_ptr<u32>(E, L.present);
+        u32* ctl = ws_ptr<u32>(E, L.ctl);
+        ModRange* mt = ws_ptr<ModRange>(E, L.mtab);
+        const u64 tag = u64(E.epoch) << 32;
+        u32 carry = 0, pcarry = 0;
+        for (u32 base = 0; base < M; base += G_WG * G_TPM) {
+            const u32 m0 = base + tid * G_TPM;   // this thread's G_TPM consecutive modules
+            u32 cnt[G_TPM], sum = 0, pres = 0;
+#pragma unroll
+            for (u32 j = 0; j < G_TPM; ++j) {
+                cnt[j] = (m0 + j < M && E.n) ? gcnt[m0 + j] : 0u;
+                sum += cnt[j];
+                pres += cnt[j] ? 1u : 0u;
+            }
+            u32 tot, ptot;
+            const u32 ex = group_excl_scan<G_WG>(sum, tid, s_wsum, tot);
+            const u32 pex = group_excl_scan<G_WG>(pres, tid, s_wsum, ptot);
+            u32 pos = carry + ex, pp = pcarry + pex;
+#pragma unroll
+            for (u32 j = 0; j < G_TPM; ++j) {
+                const u32 m = m0 + j;
+                if (m >= M) break;
+                if (cnt[j]) {
+                    const u32 end = pos + cnt[j];
+                    if (end <= E.n) mt[m] = ModRange{tag | pos, tag | end};
+                    else atomicOr(&ctl[CTL_ERR], EB_INTERNAL);   // totals left by a launch that did not finish
+                    if (pp < M) present[pp] = m;
+                    ++pp;
+                    gcnt[m] = 0u;
+                }
+                kept[m] = 0u;
+                pos += cnt[j];
+            }
+            carry += tot;
+            pcarry += ptot;
+        }
+        if (tid == 0) {
+            const u32 slot = E.slot & 1u;
+            ctl[CTL_BIG] = 0u;
+            ctl[CTL_SCR] = 0u;
+            ctl[CTL_PRESENT + slot] = pcarry;
+            ctl[CTL_PRESENT + (slot ^ 1u)] = 0u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(G_WG) void k_group_scatter(LaunchArgs a) {
+    __shared__ u32 s_pref[MAXB + 1];
+    __shared__ u32 s_wsum[G_WG / 64];
+    const u32 tid = threadIdx.x, k = num_events(a), M = a.n_modules;
+    const u32 total = event_prefix<G_WG>(a, k, s_pref, s_wsum, CNT_ANY, G_CH, 0);
+    for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
+        const u32 e = find_slot(s_pref, k, t), c = t - s_pref[e];
+        const EventDesc E = get_event(a, e);
+        const EvLayout L = ev_layout(E.cap, M);
+        const ModRange* mt = ws_ptr<const ModRange>(E, L.mtab);
+        const u32* rank = reinterpret_cast<const u32*>(E.o_digi);
+        const GroupArrays G = group_arrays(E, L);
+        const u32 i0 = c * G_CH + tid;
+        u32 mm[G_PER];
+#pragma unroll
+        for (u32 q = 0; q < G_PER; ++q) {
+            const u32 i = i0 + q * G_WG;
+            mm[q] = i < E.n ? u32(E.r_module[i]) : NOPIX;
+        }
+#pragma unroll
+        for (u32 q = 0; q < G_PER; ++q) {
+            const u32 i = i0 + q * G_WG;
+            if (mm[q] >= M) continue;            // past the end, or out of range (flagged by count)
+            const ModRange r = mt[mm[q]];
+            const u32 p = u32(r.first) + rank[i];
+            if (u32(r.first >> 32) != E.epoch || p >= u32(r.end)) continue;   // only after an internal error
+            G.m[p] = u16(mm[q]);
+            G.r[p] = E.r_row[i];
+            G.c[p] = E.r_col[i];
+            G.a[p] = E.r_adc[i];
+            G.perm[p] = i;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // segment: every digi at a module boundary writes the module's entry of the module
 // table (first digi, one past the last), tagged with the launch, and the digi that
 // starts a module appends it to the present-module list (one atomic per chunk for
@@ -288,7 +473,7 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
     __shared__ u32 s_err, s_base;
     const u32 tid = threadIdx.x;
     const u32 k = num_events(a);
-    const u32 total = event_prefix<A_WG>(a, k, s_pref, s_wsum, CNT_DIGIS, CH, 0);
+    const u32 total = event_prefix<A_WG>(a, k, s_pref, s_wsum, CNT_SORTED, CH, 0);
     // The small kernel's ticket starts at zero in every launch: the compaction kernel
     // of a finished launch resets it, and this reset also covers a launch whose later
     // kernels were never queued.
@@ -374,7 +559,6 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
 // ---------------------------------------------------------------------------
 // clustering of one module with its digis in registers (K per thread, group of G)
 // ---------------------------------------------------------------------------
-constexpr u32 NOPIX = 0xFFFFFFFFu;
 
 constexpr u32 CMW = (COLS + 31) / 32;   // words of a per-module column mask
 
@@ -1560,6 +1744,22 @@ int occupancy_big() { return occ(reinterpret_cast<const void*>(k_big), B_WG); }
 int occupancy_scratch() { return occ(reinterpret_cast<const void*>(k_scratch), S_WG); }
 int occupancy_compact() { return occ(reinterpret_cast<const void*>(k_compact), C_WG); }
 
+int occupancy_group() {
+    return std::min(occ(reinterpret_cast<const void*>(k_group_count), G_WG),
+                    occ(reinterpret_cast<const void*>(k_group_scatter), G_WG));
+}
+u32 group_chunk() { return G_CH; }
+// The grouping kernels of the events in any order: count over `grid` workgroups,
+// the table over `grid_events`, scatter over `grid`.
+hipError_t launch_group(const LaunchArgs& a, u32 grid, u32 grid_events, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_count, dim3(grid), dim3(G_WG), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_group_table, dim3(grid_events), dim3(G_WG), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_group_scatter, dim3(grid), dim3(G_WG), 0, s, a);
+    return hipGetLastError();
+}
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s) {
     if (a.flags & LF_SEG_WIDE) hipLaunchKernelGGL(k_segment<A_PER_W>, dim3(grid), dim3(A_WG), 0, s, a);
     else hipLaunchKernelGGL(k_segment<A_PER_N>, dim3(grid), dim3(A_WG), 0, s, a);

@@ -42,6 +42,9 @@ hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
 int occupancy_hits();
 hipError_t launch_hits(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_fill(u32* p, u32 n, u32 v, hipStream_t s);
+int occupancy_group();
+u32 group_chunk();
+hipError_t launch_group(const LaunchArgs& a, u32 grid, u32 grid_events, hipStream_t s);
 }  // namespace pxcl
 
 using namespace pxcl;
@@ -100,7 +103,7 @@ struct pxcl_ctx {
     u32 n_cu = 0;
     std::string arch;
     std::atomic<u32> wg{256}, mpw{1};
-    int occ_a = 1, occ_l = 1, occ_c = 1, occ_h = 1, occ_x = 1;
+    int occ_a = 1, occ_l = 1, occ_c = 1, occ_h = 1, occ_x = 1, occ_g = 1;
     int occ_s[4][5] = {};               // small kernel per shape [log2(wg) - 6][mpw], queried once
     std::atomic<int> bound{0};
     std::atomic<int> timing{0};
@@ -170,9 +173,11 @@ struct pxcl_batch {
     hipEvent_t done_ev = nullptr;
     hipStream_t cap_stream = nullptr;
     // captured pipelines, one per combination of the launch flags that change it
-    // (LF_NO_BIG, LF_SEG_WIDE, LF_NO_SCRATCH), all for the kernel shape g_wg x g_mpw
-    hipGraphExec_t gexec[8] = {};
-    hipGraph_t graph[8] = {};
+    // (LF_NO_BIG, LF_SEG_WIDE, LF_NO_SCRATCH, LF_GROUP, LF_NO_SEG), all for the kernel
+    // shape g_wg x g_mpw
+    static constexpr int N_GRAPHS = 32;
+    hipGraphExec_t gexec[N_GRAPHS] = {};
+    hipGraph_t graph[N_GRAPHS] = {};
     u32 g_wg = 0, g_mpw = 0;
     u32 launches = 0;
     u32 timed_flags = 0;
@@ -187,6 +192,7 @@ namespace {
 
 struct Grids {
     u32 a, b, s, c, x;   // segment, big, small, compact, scratch
+    u32 g, ge;           // grouping of digis in any order: count/scatter, table
 };
 
 // Wide segmentation chunks once a launch holds at least one of them per compute
@@ -199,7 +205,8 @@ static u32 seg_flag(const pxcl_ctx* ctx, u64 digis) {
 // modules present (at most min(digis, modules) per event); with `full` (a captured
 // graph replays with any input)
 // every kernel gets what fits on the device at once.
-Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u32 k, u32 flags, bool full) {
+Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u32 k, u32 flags, bool full,
+                u64 any_digis = 0, u32 any_events = 0) {
     Grids g;
     const u64 ncu = ctx->n_cu;
     const u64 fa = ncu * (u64)ctx->occ_a;
@@ -210,10 +217,15 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
     // kernel's workgroups, each holding a whole compute unit's LDS, are capped at a
     // quarter of the chip, the rest loop
     const u64 fx = std::min<u64>(ncu * (u64)ctx->occ_x, std::max<u64>(ncu / 4, 1));
+    const u64 fg = ncu * (u64)ctx->occ_g;
     if (full) {
         g.a = u32(fa); g.b = u32(fb); g.s = u32(fs); g.c = u32(fc); g.x = u32(fx);
+        g.g = u32(fg); g.ge = u32(std::min<u64>(ncu, MAXB));
         return g;
     }
+    const u64 gch = group_chunk();
+    g.g = u32(std::max<u64>(1, std::min<u64>(fg, (any_digis + gch - 1) / gch + any_events)));
+    g.ge = std::max<u32>(1u, any_events);
     const u32 dcap = cluster_capacity(wg, mpw);
     const u64 ch = seg_chunk(flags);
     g.a = u32(std::max<u64>(1, std::min<u64>(fa, (digis + ch - 1) / ch + k)));
@@ -228,7 +240,8 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
 hipError_t launch_all(const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipStream_t s, hipEvent_t* tev) {
     hipError_t e;
     if (tev && (e = hipEventRecord(tev[0], s)) != hipSuccess) return e;
-    if (!(a.flags & LF_FUSED) && (e = launch_segment(a, g.a, s)) != hipSuccess) return e;
+    if ((a.flags & LF_GROUP) && (e = launch_group(a, g.g, g.ge, s)) != hipSuccess) return e;
+    if (!(a.flags & (LF_FUSED | LF_NO_SEG)) && (e = launch_segment(a, g.a, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
     if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;   // lists the big modules
     if (tev && (e = hipEventRecord(tev[2], s)) != hipSuccess) return e;
@@ -243,6 +256,7 @@ bool digis_ok(const pxcl_digis* in) {
     if (!in) return false;
     if (in->where != PXCL_WHERE_HOST && in->where != PXCL_WHERE_DEVICE) return false;
     if (in->n && (!in->module || !in->row || !in->col || !in->adc)) return false;
+    if (in->flags & ~PXCL_DIGIS_ANY_ORDER) return false;
     return true;
 }
 
@@ -253,7 +267,8 @@ bool digis_ok(const pxcl_digis* in) {
 hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventDesc* d) {
     const EvLayout L = ev_layout(ev->cap, ev->ctx->n_modules);
     if (ev->dirty) {
-        const hipError_t e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
+        hipError_t e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
+        if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.gcnt, 0, size_t(4) * ev->ctx->n_modules, s);
         if (e != hipSuccess) return e;
         ev->dirty = false;
     }
@@ -269,15 +284,25 @@ hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventD
     d->cap = ev->cap;
     d->epoch = ev->epoch;
     d->slot = ev->slot;
+    // digis in any order: the kernels read them through r_* and cluster the grouped
+    // copy the grouping kernels write to the workspace
+    const bool any = (in->flags & PXCL_DIGIS_ANY_ORDER) != 0;
+    const u16** dst[4] = {&d->module, &d->row, &d->col, &d->adc};
+    if (any) {
+        d->flags = EF_UNSORTED;
+        u16* g = reinterpret_cast<u16*>(ev->ws + L.grp);
+        for (int i = 0; i < 4; ++i) *dst[i] = g + size_t(i) * ev->cap;
+        dst[0] = &d->r_module; dst[1] = &d->r_row; dst[2] = &d->r_col; dst[3] = &d->r_adc;
+    }
     if (in->where == PXCL_WHERE_DEVICE) {
-        d->module = in->module; d->row = in->row; d->col = in->col; d->adc = in->adc;
+        *dst[0] = in->module; *dst[1] = in->row; *dst[2] = in->col; *dst[3] = in->adc;
         return hipSuccess;
     }
     u16* m = reinterpret_cast<u16*>(ev->ws + L.in_mod);
     u16* r = reinterpret_cast<u16*>(ev->ws + L.in_row);
     u16* c = reinterpret_cast<u16*>(ev->ws + L.in_col);
     u16* a = reinterpret_cast<u16*>(ev->ws + L.in_adc);
-    d->module = m; d->row = r; d->col = c; d->adc = a;
+    *dst[0] = m; *dst[1] = r; *dst[2] = c; *dst[3] = a;
     const size_t b = size_t(in->n) * 2;
     if (!b) return hipSuccess;
     hipError_t e;
@@ -446,6 +471,7 @@ extern "C" int pxcl_ctx_create(const pxcl_config* cfg, int device, pxcl_ctx** ou
     c->occ_x = occupancy_scratch();
     c->occ_c = occupancy_compact();
     c->occ_h = occupancy_hits();
+    c->occ_g = occupancy_group();
     noalloc_setup(device);
     hipSetDevice(prev);
     try {
@@ -545,6 +571,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev->tev[i]);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.mtab, 0, size_t(16) * ctx->n_modules, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.gcnt, 0, size_t(4) * ctx->n_modules, s);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (ev->done_ev) hipEventDestroy(ev->done_ev);
@@ -618,10 +645,14 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     a.dcap = cluster_capacity(wg, mpw);
     if (in->max_module_digis && in->max_module_digis <= a.dcap) a.flags |= LF_NO_BIG;
     if (in->max_module_digis && in->max_module_digis <= BIG_RCAP) a.flags |= LF_NO_SCRATCH;
-    a.flags |= LF_FUSED;                       // one event: ranges by search, no segmentation kernel
+    const bool any = (in->flags & PXCL_DIGIS_ANY_ORDER) != 0;
+    // one event grouped by module: ranges by search, no segmentation kernel; in any
+    // order: the grouping kernels build the module table instead
+    a.flags |= any ? (LF_GROUP | LF_NO_SEG) : LF_FUSED;
     hipError_t e = make_desc(ev, in, s, &a.single);
     ev->desc = a.single;
-    const Grids g = grids_for(ctx, wg, mpw, in->n, in->n ? ctx->n_modules : 0u, 1, a.flags, false);   // every module a unit
+    const Grids g = grids_for(ctx, wg, mpw, in->n, in->n ? ctx->n_modules : 0u, 1, a.flags, false,
+                              any ? in->n : 0u, any ? 1u : 0u);
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) {
@@ -663,6 +694,7 @@ static void add_timing(pxcl_ctx* ctx, hipEvent_t* tev, u32 flags) {
     std::lock_guard<std::mutex> g(ctx->tmu);
     for (int i = 0; i < 4; ++i) {
         if ((slot[i] == 1 && (flags & LF_NO_BIG)) || (slot[i] == 0 && (flags & LF_FUSED))) continue;
+        if (slot[i] == 0 && (flags & LF_NO_SEG) && !(flags & LF_GROUP)) continue;
         ctx->tsum[slot[i]] += ms[i];
         ctx->tcnt[slot[i]] += 1;
     }
@@ -724,7 +756,7 @@ extern "C" void pxcl_flag_cb(void* user, int32_t status) {
 extern "C" int pxcl_cluster_noalloc(pxcl_ctx* ctx, const pxcl_digis* in, const pxcl_noalloc_out* out,
                                     void* stream, uint32_t* tag) {
     if (!ctx || !digis_ok(in) || !out || !out->status) return PXCL_E_INVAL;
-    if (in->where != PXCL_WHERE_DEVICE) return PXCL_E_INVAL;
+    if (in->where != PXCL_WHERE_DEVICE || in->flags) return PXCL_E_INVAL;
     if (in->n && (!out->digi_cluster || !out->id || !out->charge || !out->size)) return PXCL_E_INVAL;
     if (in->n > NOALLOC_CAP) return PXCL_E_CAPACITY;
     if (ctx->device < 0 || ctx->device >= NOALLOC_DEVICES) return PXCL_E_HIP;
@@ -1080,7 +1112,7 @@ extern "C" int pxcl_batch_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
 }
 
 static void drop_graphs(pxcl_batch* b) {
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < pxcl_batch::N_GRAPHS; ++i) {
         if (b->gexec[i]) hipGraphExecDestroy(b->gexec[i]);
         if (b->graph[i]) hipGraphDestroy(b->graph[i]);
         b->gexec[i] = nullptr;
@@ -1089,7 +1121,8 @@ static void drop_graphs(pxcl_batch* b) {
 }
 
 static u32 graph_slot(u32 flags) {
-    return ((flags & LF_NO_BIG) ? 1u : 0u) | ((flags & LF_SEG_WIDE) ? 2u : 0u) | ((flags & LF_NO_SCRATCH) ? 4u : 0u);
+    return ((flags & LF_NO_BIG) ? 1u : 0u) | ((flags & LF_SEG_WIDE) ? 2u : 0u) | ((flags & LF_NO_SCRATCH) ? 4u : 0u) |
+           ((flags & LF_GROUP) ? 8u : 0u) | ((flags & LF_NO_SEG) ? 16u : 0u);
 }
 
 extern "C" int pxcl_batch_unbind(pxcl_batch* b) {
@@ -1188,7 +1221,8 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     *reinterpret_cast<u32*>(b->hp) = k;
     EventDesc* hd = reinterpret_cast<EventDesc*>(b->hp + HDR_EV_OFFSET);
     hipError_t e = hipSuccess;
-    u64 digis = 0, present = 0;
+    u64 digis = 0, present = 0, sorted_digis = 0, any_digis = 0;
+    u32 any_events = 0;
     const u32 dcap = cluster_capacity(wg, mpw);
     u32 lflags = LF_NO_BIG | LF_NO_SCRATCH;     // unless an event may hold a big module
     for (u32 i = 0; i < k && e == hipSuccess; ++i) {
@@ -1210,8 +1244,16 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         ev->desc = hd[i];
         digis += ins[i].n;
         present += std::min<u64>(ins[i].n, (u64)ctx->n_modules);
+        if (ins[i].flags & PXCL_DIGIS_ANY_ORDER) {
+            any_digis += ins[i].n;
+            ++any_events;
+        } else {
+            sorted_digis += ins[i].n;
+        }
     }
-    lflags |= seg_flag(ctx, digis);
+    if (any_events) lflags |= LF_GROUP;
+    if (any_events == k) lflags |= LF_NO_SEG;
+    lflags |= seg_flag(ctx, sorted_digis);
     if (e == hipSuccess) {
         if (flags & PXCL_BATCH_GRAPH) {
             hipGraphExec_t exec = nullptr;
@@ -1221,7 +1263,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
             LaunchArgs a = batch_args(b, wg, mpw);
             a.flags = lflags;
             e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
-            const Grids g = grids_for(ctx, wg, mpw, digis, present, k, lflags, false);
+            const Grids g = grids_for(ctx, wg, mpw, digis, present, k, lflags, false, any_digis, any_events);
             if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? b->tev : nullptr);
         }
     }

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libpxcl.so")
 OK, E_INVAL, E_CAPACITY, E_BUSY, E_NOT_READY = 0, -1, -2, -3, -4
 E_DUP_PIXEL, E_RANGE, E_ORDER, E_HIP, E_INTERNAL, E_NOTFOUND, E_HINT = -5, -6, -7, -8, -10, -11, -12
 WHERE_HOST, WHERE_DEVICE = 0, 1
+DIGIS_ANY_ORDER = 1
 BATCH_GRAPH = 1
 MAX_BATCH = 128
 ROWS, COLS, PIXELS_PER_MODULE = 160, 416, 66560
@@ -43,7 +44,7 @@ class _Config(ctypes.Structure):
 class _Digis(ctypes.Structure):
     _fields_ = [("module", ctypes.c_void_p), ("row", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("adc", ctypes.c_void_p), ("n", ctypes.c_uint32), ("where", ctypes.c_int32),
-                ("max_module_digis", ctypes.c_uint32)]
+                ("max_module_digis", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class _Hits(ctypes.Structure):
@@ -201,7 +202,8 @@ def flag_cb_ptr() -> int:
 @dataclass
 class Digis:
     """Digis of one event as four uint16 tensors (CUDA or pinned CPU), grouped by
-    non-decreasing module.  Keep the object alive until the done callback.
+    non-decreasing module, or in any order with ``any_order`` (the library then
+    groups them on the device).  Keep the object alive until the done callback.
     max_module_digis: an upper bound on the digis of any one module, or 0 (unknown);
     a small bound lets the library skip its big-module kernel."""
     module: torch.Tensor
@@ -209,6 +211,7 @@ class Digis:
     col: torch.Tensor
     adc: torch.Tensor
     max_module_digis: int = 0
+    any_order: bool = False
 
     @property
     def n(self) -> int:
@@ -226,12 +229,13 @@ class Digis:
             if t.is_cuda != self.module.is_cuda or (not t.is_cuda and not t.is_pinned()):
                 raise ValueError("digis must all be on the device or all in pinned host memory")
         return _Digis(*(t.data_ptr() if self.n else None for t in ts), self.n, self.where,
-                      int(self.max_module_digis))
+                      int(self.max_module_digis), DIGIS_ANY_ORDER if self.any_order else 0)
 
     @staticmethod
-    def from_numpy(ev, device: str = "cuda", hint: bool = False) -> "Digis":
+    def from_numpy(ev, device: str = "cuda", hint: bool = False, any_order: bool = False) -> "Digis":
         """Copy a numpy event; with `hint`, the largest number of digis sharing a
-        module id (a host-side count over the event) is passed as max_module_digis."""
+        module id (a host-side count over the event) is passed as max_module_digis;
+        with `any_order` the digis are flagged as being in any order."""
         ts = []
         for k in ("module", "row", "col", "adc"):
             t = torch.from_numpy(ev[k].astype("uint16", copy=True))
@@ -241,7 +245,7 @@ class Digis:
                 t = t.pin_memory()
             ts.append(t.contiguous())
         mx = int(np.bincount(ev["module"]).max()) if (hint and ev["module"].size) else 0
-        return Digis(*ts, max_module_digis=mx)
+        return Digis(*ts, max_module_digis=mx, any_order=any_order)
 
 
 @dataclass

@@ -35,7 +35,7 @@ def build(force: bool = False, sanitizer: str = "address") -> str:
 
 def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, grids=(2, 2, 2, 2), caps=None,
         header: bool = False, sanitizer: str = "address", no_big: bool = False, hits: bool = False,
-        seg_wide: bool = False, fused: bool = False, stale_ticket: bool = False):
+        seg_wide: bool = False, fused: bool = False, stale_ticket: bool = False, any_order=None):
     """Cluster `events` (list of dicts of uint16 arrays) as one launch; returns a list
     of result dicts like the oracle's (status from the error bits).  With `header` the
     events are passed through a batch header even when there is only one; with
@@ -44,17 +44,23 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
     `seg_wide` segments in wide chunks (the launch form of many digis); with `fused`
     (one event) there is no segmentation kernel and the small kernel finds the
     module ranges by search (the single-event launch form); with `stale_ticket` the
-    launch counters hold a ticket a launch that stopped after its small kernel left."""
+    launch counters hold a ticket a launch that stopped after its small kernel left.
+    `any_order` (one bool per event) flags events whose digis are in any order: the
+    grouping kernels run first, and segmentation only if some event is grouped."""
+    any_order = [False] * len(events) if any_order is None else list(any_order)
+    lflags = int(no_big) | (int(seg_wide) << 1) | (int(fused) << 2) | (int(stale_ticket) << 31)
+    if any(any_order):
+        lflags |= 16 | (32 if all(any_order) else 0)        # LF_GROUP, LF_NO_SEG
     exe = build(sanitizer=sanitizer)
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
         with open(fin, "wb") as f:
-            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), int(no_big) | (int(seg_wide) << 1) | (int(fused) << 2) | (int(stale_ticket) << 31), int(hits)],
+            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), lflags, int(hits)],
                      dtype=np.uint32).tofile(f)
             for i, ev in enumerate(events):
                 n = ev["module"].size
                 cap = max(1, n) if caps is None else caps[i]
-                np.array([n, cap], dtype=np.uint32).tofile(f)
+                np.array([n, cap, int(any_order[i])], dtype=np.uint32).tofile(f)
                 for key in ("module", "row", "col", "adc"):
                     np.ascontiguousarray(ev[key], dtype=np.uint16).tofile(f)
         env = dict(os.environ)

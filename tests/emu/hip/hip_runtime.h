@@ -14,6 +14,7 @@
 #include <functional>
 #include <memory>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #define __global__
@@ -128,8 +129,9 @@ inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const voi
 }
 
 // Run a kernel: workgroups one after another, each as blockDim host threads.
-template <typename Args>
-inline void emu_launch(void (*k)(Args), dim3 grid, dim3 block, Args args) {
+template <typename... P, typename... A>
+inline void emu_launch(void (*k)(P...), dim3 grid, dim3 block, A... args_in) {
+    const std::tuple<P...> args(static_cast<P>(args_in)...);
     for (uint32_t b = 0; b < grid.x; ++b) {
         EmuWG wg;
         wg.bar = std::make_unique<std::barrier<>>(block.x);
@@ -143,7 +145,7 @@ inline void emu_launch(void (*k)(Args), dim3 grid, dim3 block, Args args) {
                 blockDim = {block.x, 1, 1};
                 gridDim = {grid.x, 1, 1};
                 emu_wg = &wg;
-                k(args);
+                std::apply(k, args);
             });
         for (auto& x : th) x.join();
     }

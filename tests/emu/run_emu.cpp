@@ -7,7 +7,8 @@
 //         (LF_NO_BIG: the big-module kernel is not run; LF_SEG_WIDE: segmentation in
 //         wide chunks; LF_FUSED: no segmentation kernel; bit 31: the ticket counter
 //         starts non-zero), hits (1: run the hits kernel after the launch);
-//         per event: u32 n, u32 cap, u16 module[n], row[n], col[n], adc[n]
+//         per event: u32 n, u32 cap, u32 flags (1: digis in any order), u16 module[n],
+//         row[n], col[n], adc[n]
 // output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
 //         (with hits: then f32 x[nc], y[nc])
 #include "../../paper_2004_04334_amd/csrc/pxcl_kernels.hip"
@@ -35,9 +36,10 @@ int main(int argc, char** argv) {
     std::vector<u32*> hs(k);
     std::mt19937 rng(7);
     for (u32 e = 0; e < k; ++e) {
-        u32 nc[2];
-        rd(f, nc, 8);
+        u32 nc[3];
+        rd(f, nc, 12);
         const u32 n = nc[0], cap = nc[1];
+        const bool any = (nc[2] & 1u) != 0;
         in[e].resize(4 * size_t(n) + 4);
         rd(f, in[e].data(), 8 * size_t(n));
         const EvLayout L = ev_layout(cap, M);
@@ -55,6 +57,7 @@ int main(int argc, char** argv) {
             mt[m].end = old_tag | (rng() % (n + 1));
         }
         if (!(h[10] & LF_FUSED)) reinterpret_cast<u32*>(ws[e] + L.ctl)[CTL_BIG] = 3;
+        memset(ws[e] + L.gcnt, 0, size_t(4) * M);                          // what binding clears
         hs[e] = static_cast<u32*>(aligned_alloc(64, HS_BYTES));
         memset(hs[e], 0, HS_BYTES);
         EventDesc& d = evs[e];
@@ -62,6 +65,12 @@ int main(int argc, char** argv) {
         d.row = in[e].data() + n;
         d.col = in[e].data() + 2 * size_t(n);
         d.adc = in[e].data() + 3 * size_t(n);
+        if (any) {                        // the kernels read the raw digis and cluster a grouped copy
+            d.flags = EF_UNSORTED;
+            d.r_module = d.module; d.r_row = d.row; d.r_col = d.col; d.r_adc = d.adc;
+            const u16* g = reinterpret_cast<const u16*>(ws[e] + L.grp);
+            d.module = g; d.row = g + cap; d.col = g + 2 * size_t(cap); d.adc = g + 3 * size_t(cap);
+        }
         d.ws = ws[e];
         d.hstat = hs[e];
         d.o_digi = reinterpret_cast<int32_t*>(ws[e] + L.digi);
@@ -98,7 +107,8 @@ int main(int argc, char** argv) {
         memset(a.ctr, 0, 64);
     }
     if (stale_ticket) a.ctr[S_TICK] = 1000003u;
-    if ((!(a.flags & LF_FUSED) && launch_segment(a, h[5], nullptr)) || launch_small(h[3], h[4], a, h[7], nullptr) ||
+    if (((a.flags & LF_GROUP) && launch_group(a, h[5], h[5], nullptr)) ||
+        (!(a.flags & (LF_FUSED | LF_NO_SEG)) && launch_segment(a, h[5], nullptr)) || launch_small(h[3], h[4], a, h[7], nullptr) ||
         (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], h[6], nullptr)) || launch_compact(a, h[8], nullptr)) {
         fprintf(stderr, "launch failed\n");
         return 3;

@@ -232,3 +232,81 @@ def test_batch_launch_after_one_that_stopped_early(emulator):
     # 24 present modules over a grid of 2 one-wave groups: the last rounds go by ticket
     _check(emulator, evs, 6, wg=64, mpw=1, grids=(2, 2, 2, 2), header=True, stale_ticket=True)
     _check(emulator, evs, 6, wg=256, mpw=2, grids=(2, 2, 1, 2), header=True, stale_ticket=True)
+
+
+# ---------------------------------------------------------------------------
+# digis in any order: the grouping kernels (count, table, scatter) ahead of the
+# clustering; per-digi outputs at the input positions
+# ---------------------------------------------------------------------------
+def _shuffled(ev, seed):
+    p = np.random.default_rng(seed).permutation(ev["module"].size)
+    out = {k: (v[p] if isinstance(v, np.ndarray) else v) for k, v in ev.items()}
+    return out
+
+
+def _check_any(oracle_mod, events, n_modules, any_order, hits=False, **kw):
+    res = emu.run(events, n_modules, any_order=any_order, hits=hits, **kw)
+    for i, (r, e, a) in enumerate(zip(res, events, any_order)):
+        ref = oracle_mod.hits(e, 2000, any_order=True) if hits else oracle_mod.cluster_event(e, 2000, any_order=a)
+        compare(r, ref, f"event {i}")
+        if hits and ref["status"] == 0:
+            assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"]), f"hits of event {i}"
+    return res
+
+
+@pytest.mark.parametrize("sanitizer", ["address", "thread"])
+def test_any_order_single_event(emulator, sanitizer):
+    """One shuffled event alone: grouping builds the module table, no segmentation."""
+    ev = _shuffled(dict(synth.plain_event(3, n_modules=8), n_modules=8), 1)
+    assert np.any(np.diff(ev["module"].astype(np.int64)) < 0)
+    _check_any(emulator, [ev], 8, [True], wg=256, mpw=2, grids=(2, 2, 3, 2), sanitizer=sanitizer)
+
+
+@pytest.mark.parametrize("wg,mpw", [(64, 1), (256, 1), (512, 4)])
+def test_any_order_mixed_batch(emulator, wg, mpw):
+    """A batch mixing grouped and shuffled events (one empty, one holding a module
+    above the small kernel's capacity for narrow groups), with capacities larger than
+    the events, through a header."""
+    evs = _mixed_events()
+    evs = [evs[0], _shuffled(evs[1], 2), _shuffled(evs[2], 3), evs[3], _shuffled(evs[3], 4)]
+    flags = [False, True, True, False, True]
+    _check_any(emulator, evs, 6, flags, wg=wg, mpw=mpw, grids=(3, 2, 3, 2), header=True,
+               caps=[max(1, e["module"].size) + 7 for e in evs])
+
+
+def test_any_order_scratch_mode_and_hits(emulator):
+    """A shuffled serpentine (scratch mode) and column track, with the hits after."""
+    sr, sc = synth.serpentine(row_wise=False)
+    tr, tc = synth.column_track(9)
+    m = np.concatenate([np.ones(tr.size, np.int64), np.zeros(sr.size, np.int64)])
+    ev = _shuffled(synth.from_pixels(m, np.concatenate([tr, sr]), np.concatenate([tc, sc]), n_modules=3, seed=5), 5)
+    _check_any(emulator, [ev], 3, [True], hits=True, grids=(2, 2, 2, 2))
+
+
+def test_any_order_many_modules_without_lds_histogram(emulator):
+    """More modules than the count kernel's LDS histogram holds (4,096): ranks come
+    from device atomics on the module totals directly."""
+    mods, rows, cols = [], [], []
+    for m, npx in ((0, 5), (4095, 40), (4096, 600), (4097, 3), (4999, 12)):
+        lin = (np.arange(npx) * 37 + m) % (160 * 416)
+        mods.append(np.full(npx, m))
+        rows.append(lin % 160)
+        cols.append(lin // 160)
+    ev = _shuffled(synth.from_pixels(np.concatenate(mods), np.concatenate(rows), np.concatenate(cols),
+                                     n_modules=5000, seed=8), 6)
+    _check_any(emulator, [ev, ev], 5000, [True, True], wg=64, mpw=1, grids=(2, 2, 3, 2))
+
+
+def test_any_order_errors(emulator):
+    """Shuffled events with a module id out of range and with a pixel fired twice
+    report the oracle's status; their neighbours in the batch are exact."""
+    base = _mixed_events()[3]
+    rng_bad = _shuffled(base, 7)
+    rng_bad["module"] = rng_bad["module"].copy()
+    rng_bad["module"][11] = 6
+    dup = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in _shuffled(base, 8).items()}
+    j = int(np.nonzero(dup["module"] == dup["module"][0])[0][1])
+    dup["row"][j], dup["col"][j] = dup["row"][0], dup["col"][0]
+    good = _shuffled(_mixed_events()[0], 9)
+    res = _check_any(emulator, [rng_bad, good, dup], 6, [True, True, True], grids=(2, 2, 3, 2))
+    assert [r["status"] for r in res] == [-6, 0, -5]
