@@ -212,6 +212,8 @@ __device__ __forceinline__ u32 event_prefix(const LaunchArgs& a, u32 k, u32* pre
     return pref[k];
 }
 
+constexpr u32 NOPIX = 0xFFFFFFFFu;          // no pixel / no index
+
 // ---------------------------------------------------------------------------
 // bitmap helpers (column-major: 5 words per column; bit b of word w is row
 // (w % 5)*32 + b of column w / 5)
@@ -261,20 +263,104 @@ __device__ __forceinline__ void uf_unite(u32* par, u32 a, u32 b) {
     }
 }
 
-// Links of fired pixel lin (row, col, run r) to the next column.  Pixel (row, col)
-// touches (row-1..row+1, col+1).  If (row, col+1) is fired its run contains the other
-// two when they are fired; a pixel whose upper neighbour (row-1, col) is fired leaves
-// (row-1, col+1) and (row, col+1) to that neighbour.
-__device__ __forceinline__ void link_right(u32* par, const u32* bm, const u16* rpre, u32 lin, u32 row, u32 col,
-                                           u32 r) {
-    if (col + 1 >= COLS) return;
-    const bool up = row > 0 && fired(bm, lin - 1);
-    if (fired(bm, lin + ROWS)) {
-        if (!up) uf_unite(par, r, run_of(bm, rpre, lin + ROWS));
-        return;
+// Run index of row bit j of word w (fired), given the word's run starts s and the run
+// starts before it r0: runs are numbered in column-major order of their first pixel.
+__device__ __forceinline__ u32 run_at(u32 r0, u32 s, u32 j) { return r0 + __popc(s & ((2u << j) - 1u)) - 1u; }
+
+// Links between the runs of columns c and c+1 that meet rows 32k..32k+31 of them (both
+// columns hold a fired pixel, their run prefixes are set).  Rule B: every run start of
+// column c+1 is linked to the run of column c that holds the first fired pixel of the
+// start's rows -1..+1.  Rule A: every run start q of column c is linked to the run of
+// column c+1 holding the first fired pixel of rows q-1..q+1, when rule B does not
+// already make that link, which is when that pixel is at row q-1 and row q-2 is fired
+// in either column.  Every pair of touching runs X (column c+1), Y (column c) is linked
+// this way: if X's start lies within Y's rows widened by one, rule B links X to Y, or
+// to a run of column c ending right above X's start, and then Y starts just below
+// X's start, within one row of it, and rule A links Y to X; otherwise Y starts inside
+// X's rows widened by one, and rule A (or rule B for X, when X starts one row below
+// Y's start) links them.  Everything about the two columns comes from six bitmap
+// words and four run prefixes read once; only the unions touch the parents.
+__device__ __forceinline__ void link_word(u32* par, const u32* bm, const u16* rpre, u32 c, u32 k) {
+    const u32 wa = c * WPC + k, wb = wa + WPC;
+    const bool has_prev = k > 0, has_next = k + 1 < WPC;
+    const u32 a = bm[wa], b = bm[wb];
+    const u32 pa = has_prev ? bm[wa - 1] : 0u, pb = has_prev ? bm[wb - 1] : 0u;   // rows 32k-32..32k-1
+    const u32 ap = pa >> 31, bp = pb >> 31;                                        // row 32k-1
+    const u32 an = has_next ? bm[wa + 1] & 1u : 0u;                                // row 32k+32
+    const u32 sa = a & ~((a << 1) | ap), sb = b & ~((b << 1) | bp);
+    // bit i of x_up / x_up2 / x_dn: the column fired at row i-1 / i-2 / i+1 of this word
+    const u32 a_up = (a << 1) | ap, a_dn = (a >> 1) | (an << 31), a_up2 = (a << 2) | (pa >> 30);
+    const u32 b_up = (b << 1) | bp, b_up2 = (b << 2) | (pb >> 30);
+    u32 ma = sa & b_up & (a_up2 | b_up2), mb = sb & (a_up | a | a_dn);
+    if (!(ma | mb)) return;
+    const u32 ra0 = rpre[wa], rb0 = rpre[wb];
+    const u32 ra1 = has_next ? rpre[wa + 1] : 0u;
+    // run of the other column (bits x, starts s, prefixes r0 / r1 of this word and the
+    // next) holding its first fired pixel among rows i-1, i, i+1
+    auto first_run = [](u32 i, u32 x, u32 x_up, u32 s, u32 r0, u32 r1) -> u32 {
+        if ((x_up >> i) & 1u) return i ? run_at(r0, s, i - 1) : r0 - 1u;   // row 32k-1: the last run before the word
+        if ((x >> i) & 1u) return run_at(r0, s, i);
+        return i < 31 ? run_at(r0, s, i + 1) : r1;   // row 32k+32 starts a run (row 32k+31 is empty)
+    };
+    while (mb) {                                     // starts in column c+1
+        const u32 i = __builtin_ctz(mb);
+        mb &= mb - 1u;
+        uf_unite(par, run_at(rb0, sb, i), first_run(i, a, a_up, sa, ra0, ra1));
     }
-    if (row + 1 < ROWS && fired(bm, lin + ROWS + 1)) uf_unite(par, r, run_of(bm, rpre, lin + ROWS + 1));
-    if (!up && row > 0 && fired(bm, lin + ROWS - 1)) uf_unite(par, r, run_of(bm, rpre, lin + ROWS - 1));
+    while (ma) {                                     // starts in column c (row i-1 fired in c+1)
+        const u32 i = __builtin_ctz(ma);
+        ma &= ma - 1u;
+        uf_unite(par, run_at(ra0, sa, i), i ? run_at(rb0, sb, i - 1) : rb0 - 1u);
+    }
+}
+
+// The same two rules for one column pair (c, c+1) by one wave, a lane per row (rows
+// lane, lane + 64, lane + 128): the scratch mode's walk over the columns.  The ten
+// words of the two columns and their run prefixes are read once per step (load_pair,
+// issued one step ahead), the rest is register work and the unions.
+struct ColPair {
+    u32 A[WPC], B[WPC], RA[WPC], RB[WPC];
+};
+__device__ __forceinline__ void load_pair(ColPair& P, const u32* bm, const u16* rpre, u32 c) {
+#pragma unroll
+    for (u32 k = 0; k < WPC; ++k) {
+        P.A[k] = bm[c * WPC + k];
+        P.B[k] = bm[(c + 1) * WPC + k];
+        P.RA[k] = rpre[c * WPC + k];
+        P.RB[k] = rpre[(c + 1) * WPC + k];
+    }
+}
+__device__ __forceinline__ u32 sel5(const u32 (&v)[WPC], u32 k) {
+    return k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : k == 3 ? v[3] : v[4];
+}
+__device__ __forceinline__ void link_pair(u32* par, const ColPair& P, u32 lane) {
+    u32 any = 0;
+#pragma unroll
+    for (u32 k = 0; k < WPC; ++k) any |= P.A[k] | P.B[k];
+    if (!any) return;                                // the same for the whole wave
+    u32 SA[WPC], SB[WPC];
+#pragma unroll
+    for (u32 k = 0; k < WPC; ++k) {
+        SA[k] = P.A[k] & ~((P.A[k] << 1) | (k ? P.A[k - 1] >> 31 : 0u));
+        SB[k] = P.B[k] & ~((P.B[k] << 1) | (k ? P.B[k - 1] >> 31 : 0u));
+    }
+    auto bit = [](const u32 (&W)[WPC], u32 row) -> u32 {   // fired at row (any u32: out of range = 0)
+        return row < ROWS ? (sel5(W, row >> 5) >> (row & 31u)) & 1u : 0u;
+    };
+    auto run = [](const u32 (&S)[WPC], const u32 (&R)[WPC], u32 row) -> u32 {
+        return run_at(sel5(R, row >> 5), sel5(S, row >> 5), row & 31u);
+    };
+#pragma unroll
+    for (u32 j = 0; j < 3; ++j) {
+        const u32 p = lane + 64u * j;
+        if (p >= ROWS) break;
+        if (bit(SB, p)) {                            // rule B
+            const u32 f = bit(P.A, p - 1u) ? p - 1u : bit(P.A, p) ? p : bit(P.A, p + 1u) ? p + 1u : NOPIX;
+            if (f != NOPIX) uf_unite(par, run(SB, P.RB, p), run(SA, P.RA, f));
+        }
+        if (bit(SA, p) && bit(P.B, p - 1u) && (bit(P.A, p - 2u) | bit(P.B, p - 2u)))   // rule A
+            uf_unite(par, run(SA, P.RA, p), run(SB, P.RB, p - 1u));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -297,7 +383,6 @@ __device__ __forceinline__ void link_right(u32* par, const u32* bm, const u16* r
 // A digi's place within its module is not fixed (chunks take their bases in any
 // order); the clustering does not depend on it.
 // ---------------------------------------------------------------------------
-constexpr u32 NOPIX = 0xFFFFFFFFu;          // no pixel / no index
 constexpr u32 G_WG = 256, G_PER = 16, G_CH = G_WG * G_PER, G_HMAX = 4096, G_TPM = 8;
 
 struct GroupArrays {
@@ -616,27 +701,26 @@ __device__ __forceinline__ EventDesc wave_uniform(const EventDesc& E) {
     return U;
 }
 
-// Issue the loads of the module's digis j = lt + q*G < n (raw row, col, adc); the
+// Issue the loads of the module's digis j = lt + q*G < n: row and column packed in
+// one register (row | col << 16, half-word loads into each half), adc in another; the
 // values are only used when the module is clustered, so the loads stay in flight
 // meanwhile.  With few slots per thread, slots past the module's end are not
 // loaded; with many (the big-module kernel) every slot loads a digi of the module
 // (unconditional loads keep that kernel's register allocation within bounds).
 template <u32 G, u32 K>
-__device__ __forceinline__ void fetch_digis(const EventDesc& E, const Item& I, u32 lt, u32* R, u32* C, u32* A) {
+__device__ __forceinline__ void fetch_digis(const EventDesc& E, const Item& I, u32 lt, u32* RC, u32* A) {
 #pragma unroll
     for (u32 q = 0; q < K; ++q) {
         const u32 j = lt + q * G;
         if constexpr (K <= 8) {
-            R[q] = C[q] = A[q] = 0u;
+            RC[q] = A[q] = 0u;
             if (q * G < I.n && j < I.n) {
-                R[q] = E.row[I.st + j];
-                C[q] = E.col[I.st + j];
+                RC[q] = u32(E.row[I.st + j]) | (u32(E.col[I.st + j]) << 16);
                 A[q] = E.adc[I.st + j];
             }
         } else {
             const u32 i = I.st + (j < I.n ? j : 0u);     // always inside the module
-            R[q] = E.row[i];
-            C[q] = E.col[i];
+            RC[q] = u32(E.row[i]) | (u32(E.col[i]) << 16);
             A[q] = E.adc[i];
         }
     }
@@ -657,16 +741,19 @@ __device__ __forceinline__ void for_slots(u32 nq, F f) {
     }
 }
 
-// Cluster module I (n <= G*K) whose raw digis are in R/C/A (fetch_digis).  Every
+// Cluster module I (n <= G*K) whose raw digis are in RC/A (fetch_digis).  Every
 // thread of the group calls it; with G > 64 all groups of the workgroup call it
 // together.  `mid(stage)` runs at the end of phase 1, at the start of phase 3, at
 // the end of phase 5 and at the end of phase 8 (the next module's prefetch).
 template <u32 G, u32 K, typename Mid>
 __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDesc& E, const EvLayout& L,
-                                             const Item& I, RegModuleSmem<G, K>& gp, u32 lt, const u32* R,
-                                             const u32* C, const u32* A, Mid mid) {
+                                             const Item& I, RegModuleSmem<G, K>& gp, u32 lt, const u32* RC,
+                                             const u32* A, Mid mid) {
     static_assert(G * K <= 65536, "run indices are kept in 16 bits");
     constexpr u32 KBW = G * K / 32, CPT = (COLS + G - 1) / G;
+    // dense modules (the big-module kernel): unions per (column, word) of the bitmap
+    // and roots per run; sparse ones: unions and roots per digi
+    constexpr bool WORD_LINKS = K > 8;
     u32* par = reinterpret_cast<u32*>(gp.acc);
     const bool act = I.ok;
     const u32 nq = act ? min((I.n + G - 1) / G, K) : 0u;   // slots that may hold a digi
@@ -680,11 +767,12 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
         LIN[q] = NOPIX;
         AR[q] = A[q] & 0xFFFFu;
         if (q < nq && j < I.n) {
-            if (R[q] < ROWS && C[q] < COLS) {
-                const u32 lin = C[q] * ROWS + R[q];
+            const u32 rq = RC[q] & 0xFFFFu, cq = RC[q] >> 16;
+            if (rq < ROWS && cq < COLS) {
+                const u32 lin = cq * ROWS + rq;
                 const u32 bit = 1u << (lin & 31u);
                 if (atomicOr(&gp.bm[lin >> 5], bit) & bit) err |= EB_DUP;
-                atomicOr(&gp.cm[C[q] >> 5], 1u << (C[q] & 31u));
+                atomicOr(&gp.cm[cq >> 5], 1u << (cq & 31u));
                 LIN[q] = lin;
             } else {
                 err |= EB_RANGE;
@@ -734,29 +822,91 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
         for (u32 r = lt; r < nruns; r += G) par[r] = r;
     gsync<G>();
     mid(1);
-    // P3: unions with the next column
-    for_slots<K>(nq, [&](u32 q) {
-        const u32 lin = LIN[q];
-        if (lin != NOPIX) {
+    u32 starts = 0;
+    if constexpr (WORD_LINKS) {
+        // P3: unions between adjacent fired columns, one (column, word) unit at a time
+        if (act)
+            for (u32 u = lt; u < (COLS - 1) * WPC; u += G) {
+                const u32 c = u / WPC, k = u - c * WPC;
+                if (((gp.cm[c >> 5] >> (c & 31u)) & 1u) && ((gp.cm[(c + 1) >> 5] >> ((c + 1) & 31u)) & 1u))
+                    link_word(par, gp.bm, gp.rpre, c, k);
+            }
+        gsync<G>();
+        // P4: every run points at its root (walks only read; each store writes a root,
+        // so a walk through a stored entry still ends at the same root)
+        if (act)
+            for (u32 r = lt; r < nruns; r += G) {
+                u32 x = ld_wg(&par[r]);
+                for (u32 it = 0; it < MAX_RUNS; ++it) {
+                    const u32 y = ld_wg(&par[x]);
+                    if (y == x) break;
+                    x = y;
+                }
+                st_wg(&par[r], x);
+            }
+        gsync<G>();
+        // each digi's run and root; the digi that starts its root's run speaks for the cluster
+        u32 RN[K];
+#pragma unroll
+        for (u32 q = 0; q < K; ++q) RN[q] = (q < nq && LIN[q] != NOPIX) ? run_of(gp.bm, gp.rpre, LIN[q]) : 0u;
+#pragma unroll
+        for (u32 q = 0; q < K; ++q)
+            if (q < nq && LIN[q] != NOPIX) {
+                const u32 lin = LIN[q], root = ld_wg(&par[RN[q]]);
+                if (root == RN[q] && !((lin % ROWS) > 0 && fired(gp.bm, lin - 1))) starts |= 1u << q;
+                AR[q] = (AR[q] & 0xFFFFu) | (root << 16);
+            }
+        gsync<G>();
+    } else {
+        // P3: the two rules of link_word, from the digi that starts each run: rule B
+        // links the run to the run of the column on its left holding the first fired
+        // pixel of rows -1..+1, rule A to the run of the column on its right at row -1
+        // when row -2 is fired in either column.
+        u32 RS = 0;                                  // slots whose digi starts its run
+        for_slots<K>(nq, [&](u32 q) {
+            const u32 lin = LIN[q];
+            if (lin == NOPIX) return;
             const u32 col = lin / ROWS, row = lin - col * ROWS;
             const u32 r = run_of(gp.bm, gp.rpre, lin);
             AR[q] |= r << 16;
-            link_right(par, gp.bm, gp.rpre, lin, row, col, r);
-        }
-    });
-    gsync<G>();
-    // P4: roots; the digi that starts its root's run speaks for the cluster
-    u32 starts = 0;
-    for_slots<K>(nq, [&](u32 q) {
-        const u32 lin = LIN[q];
-        if (lin != NOPIX) {
-            const u32 run = AR[q] >> 16;
-            const u32 root = uf_find(par, run);
-            if (root == run && !((lin % ROWS) > 0 && fired(gp.bm, lin - 1))) starts |= 1u << q;
-            AR[q] = (AR[q] & 0xFFFFu) | (root << 16);
-        }
-    });
-    gsync<G>();
+            if (row > 0 && fired(gp.bm, lin - 1)) return;
+            RS |= 1u << q;
+            if (col > 0) {
+                const u32 lf = lin - ROWS;
+                const u32 f = (row > 0 && fired(gp.bm, lf - 1)) ? lf - 1
+                              : fired(gp.bm, lf)                  ? lf
+                              : (row + 1 < ROWS && fired(gp.bm, lf + 1)) ? lf + 1
+                                                                  : NOPIX;
+                if (f != NOPIX) uf_unite(par, r, run_of(gp.bm, gp.rpre, f));
+            }
+            const u32 rt = lin + ROWS;
+            if (col + 1 < COLS && row > 1 && fired(gp.bm, rt - 1) && (fired(gp.bm, lin - 2) || fired(gp.bm, rt - 2)))
+                uf_unite(par, r, run_of(gp.bm, gp.rpre, rt - 1));
+        });
+        gsync<G>();
+        // P4: every run points at its root (read-only walks, each store a root), then
+        // each digi's root in one load; the digi that starts its root's run speaks for
+        // the cluster
+        if (act)
+            for (u32 r = lt; r < nruns; r += G) {
+                u32 x = ld_wg(&par[r]);
+                for (u32 it = 0; it < MAX_RUNS; ++it) {
+                    const u32 y = ld_wg(&par[x]);
+                    if (y == x) break;
+                    x = y;
+                }
+                st_wg(&par[r], x);
+            }
+        gsync<G>();
+#pragma unroll
+        for (u32 q = 0; q < K; ++q)
+            if (q < nq && LIN[q] != NOPIX) {
+                const u32 run = AR[q] >> 16, root = ld_wg(&par[run]);
+                if (root == run && ((RS >> q) & 1u)) starts |= 1u << q;
+                AR[q] = (AR[q] & 0xFFFFu) | (root << 16);
+            }
+        gsync<G>();
+    }
     if (act) {
         for (u32 r = lt; r < nruns; r += G) gp.acc[r] = 0ull;
         for (u32 w = lt; w < KBW; w += G) gp.kb[w] = 0u;
@@ -956,8 +1106,17 @@ struct SmallSmem {
     u32 tick[2];
 };
 
+// Waves per SIMD the shape's LDS allows, at most four (at most 128 registers):
+// modules in flight bound throughput, so registers should not bound them first.
 template <u32 WG, u32 MPW, u32 K>
-__global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
+constexpr u32 small_waves_per_simd() {
+    constexpr u32 lds_groups = 163840u / u32(sizeof(SmallSmem<WG, MPW, K>));
+    constexpr u32 w = lds_groups * (WG / 64) / 4;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+template <u32 WG, u32 MPW, u32 K>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(small_waves_per_simd<WG, MPW, K>())))
+void k_small(LaunchArgs a) {
     using S = SmallSmem<WG, MPW, K>;
     constexpr u32 G = S::G;
     constexpr bool WAVE = (G == 64);          // groups of one wave run independently
@@ -1056,7 +1215,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
     u32 base = xcd_order(blockIdx.x, gridDim.x) * MPW + (WAVE ? g : 0u);
     EventDesc E{};
     Item I{0, 0, 0, 0, 0, false};
-    u32 R[K], C[K], A[K];
+    u32 RC[K], A[K];
     {
         const u32 t = base + gofs;
         if (t < total) {
@@ -1066,7 +1225,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         }
         I = wave_uniform(I);                      // one module per wave (or per group of waves)
         E = wave_uniform(E);
-        if (I.ok) fetch_digis<G, K>(E, I, lt, R, C, A);
+        if (I.ok) fetch_digis<G, K>(E, I, lt, RC, A);
     }
     if (fused) id_check_finish<WG>(a, get_event(a, 0), idc);
     const u32 nrounds = per_round < total ? max(1u, u32((3ull * total) / (4ull * per_round))) : 1u;   // static
@@ -1082,7 +1241,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         bool have = false;
         ModRange ent{0, 0};
         Item In{0, 0, 0, 0, 0, false};
-        u32 NR[K], NC[K], NA[K];
+        u32 NRC[K], NA[K];
         auto issue_entry = [&]() {
             const u32 t = nbase + gofs;
             if (t < total) {
@@ -1112,13 +1271,13 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
             } else if (stage == 2) {
                 In = wave_uniform(make_item(ent, En, ne, nmod, have));
                 En = wave_uniform(En);
-                if (In.ok) fetch_digis<G, K>(En, In, lt, NR, NC, NA);
+                if (In.ok) fetch_digis<G, K>(En, In, lt, NRC, NA);
             }
         };
         if (base + gofs < total && !I.ok && lt == 0) skip(E, I);
         if (!WAVE || I.ok) {
             const EvLayout L = ev_layout(E.cap, a.n_modules);
-            cluster_regs<G, K>(a, E, L, I, gp, lt, R, C, A, mid);
+            cluster_regs<G, K>(a, E, L, I, gp, lt, RC, A, mid);
         } else {
             mid(0);
             mid(1);
@@ -1131,7 +1290,7 @@ __global__ __launch_bounds__(WG) void k_small(LaunchArgs a) {
         nv = nv2;
         ++round;
 #pragma unroll
-        for (u32 q = 0; q < K; ++q) { R[q] = NR[q]; C[q] = NC[q]; A[q] = NA[q]; }
+        for (u32 q = 0; q < K; ++q) { RC[q] = NRC[q]; A[q] = NA[q]; }
     }
 }
 
@@ -1178,43 +1337,20 @@ __device__ __forceinline__ void wave_add(u32* base, u32 key, u32 val, bool valid
     }
 }
 
-// Last row of the run that starts at row r0 of column col.
-__device__ __forceinline__ u32 run_end(const u32* bm, u32 col, u32 r0) {
-    const u32 lin = col * ROWS + r0;
-    u32 w = lin >> 5;
-    u32 x = ~bm[w] & (0xFFFFFFFFu << (lin & 31u));
-    while (x == 0 && (w % WPC) != WPC - 1) x = ~bm[++w];
-    if (x == 0) return ROWS - 1;
-    return (w << 5) + (__ffs(x) - 1) - col * ROWS - 1;
-}
-
-// Links of run r (rows r0..r1 of column col) to the runs of column col+1 it touches
-// (rows r0-1..r1+1): the run holding the first fired pixel of that range and every
-// run that starts inside it.
-__device__ __forceinline__ void link_run(u32* par, const u32* bm, const u16* rpre, u32 r, u32 col, u32 r0,
-                                         u32 r1) {
-    if (col + 1 >= COLS) return;
-    const u32 lo = (r0 > 0 ? r0 - 1 : 0u), hi = min(r1 + 1, ROWS - 1);
-    const u32 base = (col + 1) * ROWS;
-    bool first = true;
-    for (u32 row = lo; row <= hi;) {
-        const u32 lin = base + row, w = lin >> 5, b = lin & 31u;
-        const u32 span = min(32u - b, hi - row + 1);                 // rows left in this word
-        const u32 mask = (span == 32u ? 0xFFFFFFFFu : ((1u << span) - 1u)) << b;
-        u32 bits = bm[w] & mask;
-        if (first && bits) {                                           // run holding the first fired pixel
-            const u32 fb = __ffs(bits) - 1;
-            uf_unite(par, r, run_of(bm, rpre, (w << 5) + fb));
-            first = false;
-            bits &= ~(1u << fb);
-        }
-        u32 sb = run_starts(bm, w) & bits;                             // runs starting later in the range
-        while (sb) {
-            const u32 fb = __ffs(sb) - 1;
-            sb &= sb - 1;
-            uf_unite(par, r, run_of(bm, rpre, (w << 5) + fb));
-        }
-        row += span;
+// The same for 64-bit sums in LDS.
+__device__ __forceinline__ void wave_add_lds64(u64* base, u32 key, u64 val, bool valid) {
+    const u64 vm = __ballot(valid);
+    if (!vm) return;
+    const u32 first = __ffsll((unsigned long long)vm) - 1;
+    const u32 lead = __shfl(key, first, 64);
+    const u64 same = __ballot(valid && key == lead);
+    if (same == vm) {
+        u64 sum = valid ? val : 0ull;
+#pragma unroll
+        for (u32 d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+        if ((threadIdx.x & 63u) == first) atomicAdd(&base[lead], sum);
+    } else if (valid) {
+        atomicAdd(&base[key], val);
     }
 }
 
@@ -1296,20 +1432,22 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     for (u32 r = tid; r < nruns; r += BW) s.par[r] = r;
     lds_barrier();
     // Unions from the bitmap only.  Wave v links the runs of its block of columns to the
-    // next column, one column at a time from left to right, a lane per run start row.
+    // next column, one column at a time from left to right, a lane per row.
     // A run of the next column is then hooked straight under a root found in an earlier
     // column, so the trees stay shallow even along chains that cross the module (a
     // serpentine); unordered unions would build paths as long as the chain.
     {
         constexpr u32 NWV = BW / 64;
         const u32 c0 = wv * COLS / NWV, c1 = (wv + 1) * COLS / NWV;
-        for (u32 col = c0; col < c1; ++col) {
-            for (u32 r0 = lane; r0 < ROWS; r0 += 64) {
-                const u32 lin = col * ROWS + r0;
-                if ((run_starts(s.bm, lin >> 5) >> (lin & 31u)) & 1u)
-                    link_run(s.par, s.bm, s.rpre, run_of(s.bm, s.rpre, lin), col, r0, run_end(s.bm, col, r0));
-            }
+        ColPair cur;
+        if (c0 < c1 && c0 + 1 < COLS) load_pair(cur, s.bm, s.rpre, c0);
+        for (u32 col = c0; col < c1 && col + 1 < COLS; ++col) {
+            ColPair nxt;
+            const bool more = col + 1 < c1 && col + 2 < COLS;
+            if (more) load_pair(nxt, s.bm, s.rpre, col + 1);   // the bitmap is read-only here
+            link_pair(s.par, cur, lane);
             gsync<64>();                                        // this column's hooks before the next
+            if (more) cur = nxt;
         }
     }
     lds_barrier();
@@ -1346,7 +1484,32 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
         }
     }
     lds_barrier();
+    // Every run's cluster as a u16 over the first half of the parents (each thread reads
+    // its RPT consecutive runs before any is written); the second half then holds the
+    // first LCAP clusters' charge | size << 44 (LDS atomics), the others' sums go to
+    // device memory.
+    constexpr u32 RPT = (MAX_RUNS + BW - 1) / BW, LCAP = MAX_RUNS * 2 / 8;
+    u16* cl = reinterpret_cast<u16*>(s.par);
+    u64* acc = reinterpret_cast<u64*>(reinterpret_cast<u8*>(s.par) + size_t(MAX_RUNS) * 2);
+    {
+        u32 cv[(RPT + 1) / 2];
+#pragma unroll
+        for (u32 i = 0; i < RPT; ++i) {
+            const u32 r = tid * RPT + i;
+            const u32 c = r < nruns ? cluster_of(r) : 0u;
+            if (i & 1u) cv[i / 2] |= c << 16;
+            else cv[i / 2] = c;
+        }
+        lds_barrier();
+#pragma unroll
+        for (u32 i = 0; i < RPT; ++i) {
+            const u32 r = tid * RPT + i;
+            if (r < nruns) cl[r] = u16(cv[i / 2] >> (16 * (i & 1u)));
+        }
+    }
+    lds_barrier();
     // per cluster: id from the start of its root run; zero the sums
+    for (u32 c = tid; c < min(ncl, LCAP); c += BW) acc[c] = 0ull;
     for (u32 w = tid; w < WORDS; w += BW) {
         u32 sb = run_starts(s.bm, w);
         u32 r = s.rpre[w];
@@ -1356,8 +1519,10 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             if (s.rootb[r >> 5] & (1u << (r & 31u))) {
                 const u32 c = u32(s.rootp[r >> 5]) + __popc(s.rootb[r >> 5] & ((1u << (r & 31u)) - 1u));
                 cid[c] = I.mod * PIX + (w << 5) + b;
-                cch[c] = 0u;
-                csz[c] = 0u;
+                if (c >= LCAP) {
+                    cch[c] = 0u;
+                    csz[c] = 0u;
+                }
             }
             ++r;
         }
@@ -1367,18 +1532,21 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     for (u32 base = 0; base < n; base += SPAN) {               // pass 2: charge and size
         u32 lin[UNR], adc[UNR];
         fetch(base, lin, adc);
+        u32 c[UNR];
+#pragma unroll
+        for (u32 u = 0; u < UNR; ++u) c[u] = lin[u] != NOPIX ? u32(cl[run_of(s.bm, s.rpre, lin[u])]) : 0u;
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
             const bool v = lin[u] != NOPIX;
-            const u32 c = v ? cluster_of(run_of(s.bm, s.rpre, lin[u])) : 0u;
-            wave_add(cch, c, adc[u], v);
-            wave_add(csz, c, 1u, v);
+            wave_add_lds64(acc, c[u], (1ull << 44) | adc[u], v && c[u] < LCAP);
+            wave_add(cch, c[u], adc[u], v && c[u] >= LCAP);
+            wave_add(csz, c[u], 1u, v && c[u] >= LCAP);
         }
     }
     wait_all_mem();
     lds_barrier();
     // cut; kept clusters -> staging records in cluster (= ascending id) order
-    set_bits([&](u32 c) { return c < ncl && ld_ag(&cch[c]) >= a.charge_cut; });   // kept clusters
+    set_bits([&](u32 c) { return c < ncl && (c < LCAP ? u32(acc[c]) : ld_ag(&cch[c])) >= a.charge_cut; });
     lds_barrier();
     u32 Kc;
     {
@@ -1407,11 +1575,17 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             for (u32 b = 0; b < 32; ++b) {
                 const u32 c = w * 32 + b;
                 if (c >= ncl) break;
+                const bool lds = c < LCAP;
                 if (s.rootb[w] & (1u << b)) {
-                    tid_[st + pos] = int32_t(ld_ag(&cid[c]));
-                    tch[st + pos] = int32_t(ld_ag(&cch[c]));
-                    tsz[st + pos] = int32_t(ld_ag(&csz[c]));
+                    const u32 id = ld_ag(&cid[c]);
+                    const u64 v = lds ? acc[c] : 0ull;
+                    tid_[st + pos] = int32_t(id);
+                    tch[st + pos] = int32_t(lds ? u32(v) : ld_ag(&cch[c]));
+                    tsz[st + pos] = int32_t(lds ? u32(v >> 44) : ld_ag(&csz[c]));
                     ++pos;
+                    if (lds) acc[c] = u64(id);                  // for the per-digi ids
+                } else if (lds) {
+                    acc[c] = u64(NOPIX);
                 } else {
                     st_ag(&cid[c], NOPIX);
                 }
@@ -1421,36 +1595,17 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     }
     wait_all_mem();
     lds_barrier();
-    // the kept bits replaced the root bits: rebuild the roots for the last pass
-    set_bits([&](u32 r) { return r < nruns && ld_wg(&s.par[r]) == r; });
-    lds_barrier();
-    {
-        u32 sw[KPT], cnt = 0, tot;
-#pragma unroll
-        for (u32 i = 0; i < KPT; ++i) {
-            const u32 w = tid * KPT + i;
-            sw[i] = w < KW ? __popc(s.rootb[w]) : 0u;
-            cnt += sw[i];
-        }
-        u32 run = group_excl_scan<BW>(cnt, tid, s.wsum, tot);
-#pragma unroll
-        for (u32 i = 0; i < KPT; ++i) {
-            const u32 w = tid * KPT + i;
-            if (w < KW) s.rootp[w] = u16(run);
-            run += sw[i];
-        }
-    }
-    lds_barrier();
     for (u32 base = 0; base < n; base += SPAN) {               // pass 3: per-digi ids
         u32 lin[UNR];
         fetch(base, lin, nullptr);
         u32 c[UNR];
 #pragma unroll
-        for (u32 u = 0; u < UNR; ++u) c[u] = lin[u] != NOPIX ? cluster_of(run_of(s.bm, s.rpre, lin[u])) : 0u;
+        for (u32 u = 0; u < UNR; ++u) c[u] = lin[u] != NOPIX ? u32(cl[run_of(s.bm, s.rpre, lin[u])]) : 0u;
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) {
             const u32 j = base + u * BW + tid;
-            if (j < n) od[out_pos(perm, st + j)] = lin[u] != NOPIX ? int32_t(ld_ag(&cid[c[u]])) : -1;
+            const u32 id = c[u] < LCAP ? u32(acc[c[u]]) : ld_ag(&cid[c[u]]);
+            if (j < n) od[out_pos(perm, st + j)] = lin[u] != NOPIX ? int32_t(id) : -1;
         }
     }
     if (err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, err);
@@ -1497,9 +1652,9 @@ __global__ __launch_bounds__(B_WG) void k_big(LaunchArgs a) {
         if (!I.ok) continue;
         const EventDesc E = get_event(a, I.e);
         const EvLayout L = ev_layout(E.cap, a.n_modules);
-        u32 R[K_BIG], C[K_BIG], A[K_BIG];
-        fetch_digis<B_WG, K_BIG>(E, I, tid, R, C, A);
-        cluster_regs<B_WG, K_BIG>(a, E, L, I, s, tid, R, C, A, [](int) {});
+        u32 RC[K_BIG], A[K_BIG];
+        fetch_digis<B_WG, K_BIG>(E, I, tid, RC, A);
+        cluster_regs<B_WG, K_BIG>(a, E, L, I, s, tid, RC, A, [](int) {});
     }
 }
 
@@ -1523,18 +1678,28 @@ __global__ __launch_bounds__(S_WG) void k_scratch(LaunchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// compact: one wave per block of C_BLK consecutive modules of an event (every module,
-// present or not: an absent module keeps nothing).  The block's first output position
-// is the sum of the kept counts of the modules before it, which the wave adds up
-// (PS_UNR loads per lane in flight); a wave scan over the block's 64 counts gives
-// every module its position, and the wave copies the block's records 64 at a time,
-// each lane finding its record's module by a search over that scan.  The wave of an
-// event's last block has the event's total and writes the status back to the host.
-// Loads per event grow as (modules / 64)^2 * 64, not modules^2.
+// compact: S waves per block of C_BLK consecutive modules of an event (every module,
+// present or not: an absent module keeps nothing).  The block's first output
+// position is the sum of the kept counts of the modules before it, which each of its
+// waves adds up (PS_UNR loads per lane in flight); a wave scan over the block's 64
+// counts gives every module its position, and wave s of the block copies the s-th
+// of S equal shares of the block's records, 64 at a time, each lane finding its
+// record's module by a search over that scan.  S (a power of two, at most C_SPLIT)
+// follows from the grid: launches of few blocks (one event of few modules) spread
+// each block's copy over many waves, launches of many blocks keep one wave per
+// block.  Wave 0 of an event's last block has the event's total and writes the
+// status back to the host.  Loads per event grow as (modules / 64)^2 * 64 * S.
 // ---------------------------------------------------------------------------
-constexpr u32 CP_UNR = 4, PS_UNR = 16, C_WAVES = C_WG / 64, C_BLK = 64;
+constexpr u32 CP_UNR = 4, PS_UNR = 16, C_WAVES = C_WG / 64, C_BLK = 64, C_SPLIT = 32;
 
 __device__ __forceinline__ u32 compact_blocks(u32 n_modules) { return (n_modules + C_BLK - 1) / C_BLK; }
+
+// Waves per block for a launch of `waves` waves over `blocks` blocks.
+__host__ __device__ __forceinline__ u32 compact_split(u32 waves, u32 blocks) {
+    u32 sp = 1;
+    while (sp < C_SPLIT && u64(sp) * 2 * blocks <= waves) sp *= 2;
+    return sp;
+}
 
 // Sum of kept[0, end) over the wave (end a multiple of 64).
 __device__ __forceinline__ u32 kept_before(const u32* kept, u32 end, u32 lane) {
@@ -1556,9 +1721,11 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
     const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const u32 k = num_events(a), M = a.n_modules, nblk = compact_blocks(M);
     if (blockIdx.x == 0 && tid == 0) st_ag(&a.ctr[S_TICK], 0u);   // the small kernel has finished
-    const u32 total = k * nblk;
+    const u32 sp = compact_split(gridDim.x * C_WAVES, k * nblk);
+    const u32 total = k * nblk * sp;
     for (u32 u = wave_uniform(xcd_order(blockIdx.x, gridDim.x) * C_WAVES + wv); u < total; u += gridDim.x * C_WAVES) {
-        const u32 e = u / nblk, b = u - e * nblk;
+        const u32 eb = u / sp, part = u - eb * sp;
+        const u32 e = eb / nblk, b = eb - e * nblk;
         const EventDesc E = wave_uniform(get_event(a, e));
         const EvLayout L = ev_layout(E.cap, M);
         u32* ctl = ws_ptr<u32>(E, L.ctl);
@@ -1573,7 +1740,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         const u32 incl = wave_incl_scan(cnt), excl = incl - cnt;
         const u32 T = wave_uniform(__shfl(incl, 63, 64));
         const bool fits = base <= E.n && T <= E.n - base;  // every position below n
-        if (b + 1 == nblk && lane == 0) {                  // the event's status
+        if (b + 1 == nblk && part == 0 && lane == 0) {     // the event's status
             const u32 ncl = fits ? base + T : E.n;
             const u32 err = ctl[CTL_ERR];
             ctl[CTL_ERR] = 0u;
@@ -1586,7 +1753,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             st_sys(&hs[HS_EPOCH], E.epoch);
         }
         if (!fits || T == 0) continue;
-        if (cnt) ws_ptr<u32>(E, L.off)[m] = base + excl;
+        if (cnt && part == 0) ws_ptr<u32>(E, L.off)[m] = base + excl;
         const bool src_ok = cnt == 0 || src <= E.n - cnt;
         const int32_t* tid_ = ws_ptr<const int32_t>(E, L.tid);
         const int32_t* tch = ws_ptr<const int32_t>(E, L.tcharge);
@@ -1595,7 +1762,8 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         int32_t* och = E.o_charge;
         int32_t* osz = E.o_size;
         const u32 mod_src = src_ok ? src : NOPIX;          // a record of a bad module is skipped
-        for (u32 j0 = 0; j0 < T; j0 += 64 * CP_UNR) {
+        const u32 j_lo = u32(u64(T) * part / sp), j_hi = u32(u64(T) * (part + 1) / sp);
+        for (u32 j0 = j_lo; j0 < j_hi; j0 += 64 * CP_UNR) {
             int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
             u32 from[CP_UNR];
 #pragma unroll
@@ -1607,7 +1775,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
                 for (u32 step = 32; step; step >>= 1)
                     if (__shfl(incl, lo + step - 1, 64) <= j) lo += step;
                 const u32 s0 = __shfl(mod_src, lo, 64), x0 = __shfl(excl, lo, 64);
-                from[q] = (j < T && s0 != NOPIX) ? s0 + (j - x0) : NOPIX;
+                from[q] = (j < j_hi && s0 != NOPIX) ? s0 + (j - x0) : NOPIX;
                 const u32 fs = from[q] != NOPIX ? from[q] : 0u;
                 r0[q] = tid_[fs];
                 r1[q] = tch[fs];
@@ -1779,6 +1947,7 @@ hipError_t launch_big(const LaunchArgs& a, u32 grid, u32 grid_scratch, hipStream
     hipLaunchKernelGGL(k_scratch, dim3(grid_scratch), dim3(S_WG), 0, s, a);
     return hipGetLastError();
 }
+u32 compact_waves_per_block(u32 waves, u32 blocks) { return compact_split(waves, blocks); }
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(grid), dim3(C_WG), 0, s, a);
     return hipGetLastError();

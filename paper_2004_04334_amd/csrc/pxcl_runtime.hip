@@ -39,6 +39,7 @@ hipError_t launch_small(u32 wg, u32 mpw, const LaunchArgs& a, u32 grid, hipStrea
 hipError_t launch_big(const LaunchArgs& a, u32 grid, u32 grid_scratch, hipStream_t s);
 int occupancy_scratch();
 hipError_t launch_compact(const LaunchArgs& a, u32 grid, hipStream_t s);
+u32 compact_waves_per_block(u32 waves, u32 blocks);
 int occupancy_hits();
 hipError_t launch_hits(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_fill(u32* p, u32 n, u32 v, hipStream_t s);
@@ -232,8 +233,11 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
     g.b = u32(std::max<u64>(1, std::min<u64>(fb, digis / (dcap + 1))));
     g.x = u32(std::max<u64>(1, std::min<u64>(fx, digis / (BIG_RCAP + 1))));
     g.s = u32(std::max<u64>(1, std::min<u64>(fs, (present + mpw - 1) / mpw)));
-    const u64 blocks = u64(k) * ((ctx->n_modules + 63) / 64);       // compaction: a wave per 64 modules
-    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (blocks + C_WG / 64 - 1) / (C_WG / 64))));
+    // compaction: a wave per 64 modules, or several when that fills less than the device
+    const u64 blocks = u64(k) * ((ctx->n_modules + 63) / 64);
+    const u64 split = compact_waves_per_block(u32(std::min<u64>(fc * (C_WG / 64), 0xFFFFFFFFull)),
+                                              u32(std::min<u64>(blocks, 0xFFFFFFFFull)));
+    g.c = u32(std::max<u64>(1, std::min<u64>(fc, (blocks * split + C_WG / 64 - 1) / (C_WG / 64))));
     return g;
 }
 

@@ -310,3 +310,36 @@ def test_any_order_errors(emulator):
     good = _shuffled(_mixed_events()[0], 9)
     res = _check_any(emulator, [rng_bad, good, dup], 6, [True, True, True], grids=(2, 2, 3, 2))
     assert [r["status"] for r in res] == [-6, 0, -5]
+
+
+@pytest.mark.parametrize("grid_c", [1, 3, 16])
+def test_compaction_split_over_waves(emulator, grid_c):
+    """The compaction of launches of few blocks spreads each block's copy over several
+    waves (up to 32 per block): one event of 64 modules with ~11,000 kept clusters,
+    and a batch of four events, on compaction grids of 1, 3 and 16 workgroups."""
+    ev = dict(synth.plain_event(6), n_modules=64)
+    _check(emulator, [ev], 64, grids=(2, 2, 3, grid_c), fused=True)
+    evs = [dict(synth.plain_event(7 + i, n_modules=8), n_modules=8) for i in range(4)]
+    _check(emulator, evs, 8, grids=(2, 2, 3, grid_c), header=True)
+
+
+def test_big_module_word_links(emulator):
+    """The big-module kernel's unions per (column, word) and roots per run, on dense
+    modules above the 64-thread groups' capacity: a hot module of the high-pileup
+    configuration (20 % occupancy, mean-40 clusters), 20 % uniform random pixels
+    (components of every shape, touching across word and column boundaries), and
+    diagonal stripes crossing every word boundary; under both sanitizers."""
+    st = synth.stress_event(0)
+    ids, cnt = np.unique(st["module"], return_counts=True)
+    hot = int(ids[np.argsort(-cnt, kind="stable")[1]])
+    assert 8192 < cnt[ids == hot][0] <= 16384
+    hm = st["module"] == hot
+    rng = np.random.default_rng(4)
+    lin = rng.choice(160 * 416, size=13000, replace=False)
+    diag = np.array([(r, c) for c in range(416) for r in range(160) if (r + 3 * c) % 7 == 0])
+    m = np.concatenate([np.zeros(hm.sum(), np.int64), np.ones(lin.size, np.int64), np.full(len(diag), 2)])
+    r = np.concatenate([st["row"][hm], lin % 160, diag[:, 0]])
+    c = np.concatenate([st["col"][hm], lin // 160, diag[:, 1]])
+    ev = synth.from_pixels(m, r, c, n_modules=3, seed=13)
+    for san in ("address", "thread"):
+        _check(emulator, [ev], 3, wg=64, mpw=1, grids=(2, 3, 2, 2), sanitizer=san)
