@@ -263,6 +263,15 @@ __device__ __forceinline__ void uf_unite(u32* par, u32 a, u32 b) {
     }
 }
 
+// Links (pairs of runs to unite) found by a group are listed in LDS first and united
+// afterwards, evenly over the group: a lane that finds several would otherwise unite
+// them one after another while the rest of its wave waits.  A link that does not fit
+// the list (capacity cap) is united at once.
+__device__ __forceinline__ void put_link(u32* list, u32 cap, u32* par, u32 pos, u32 a, u32 b) {
+    if (pos < cap) list[pos] = (a << 16) | b;
+    else uf_unite(par, a, b);
+}
+
 // Run index of row bit j of word w (fired), given the word's run starts s and the run
 // starts before it r0: runs are numbered in column-major order of their first pixel.
 __device__ __forceinline__ u32 run_at(u32 r0, u32 s, u32 j) { return r0 + __popc(s & ((2u << j) - 1u)) - 1u; }
@@ -280,7 +289,8 @@ __device__ __forceinline__ u32 run_at(u32 r0, u32 s, u32 j) { return r0 + __popc
 // X's rows widened by one, and rule A (or rule B for X, when X starts one row below
 // Y's start) links them.  Everything about the two columns comes from six bitmap
 // words and four run prefixes read once; only the unions touch the parents.
-__device__ __forceinline__ void link_word(u32* par, const u32* bm, const u16* rpre, u32 c, u32 k) {
+__device__ __forceinline__ void link_word(u32* par, u32* list, u32 cap, u32* nlink, const u32* bm, const u16* rpre,
+                                          u32 c, u32 k) {
     const u32 wa = c * WPC + k, wb = wa + WPC;
     const bool has_prev = k > 0, has_next = k + 1 < WPC;
     const u32 a = bm[wa], b = bm[wb];
@@ -302,15 +312,16 @@ __device__ __forceinline__ void link_word(u32* par, const u32* bm, const u16* rp
         if ((x >> i) & 1u) return run_at(r0, s, i);
         return i < 31 ? run_at(r0, s, i + 1) : r1;   // row 32k+32 starts a run (row 32k+31 is empty)
     };
+    u32 pos = atomicAdd(nlink, u32(__popc(mb) + __popc(ma)));
     while (mb) {                                     // starts in column c+1
         const u32 i = __builtin_ctz(mb);
         mb &= mb - 1u;
-        uf_unite(par, run_at(rb0, sb, i), first_run(i, a, a_up, sa, ra0, ra1));
+        put_link(list, cap, par, pos++, run_at(rb0, sb, i), first_run(i, a, a_up, sa, ra0, ra1));
     }
     while (ma) {                                     // starts in column c (row i-1 fired in c+1)
         const u32 i = __builtin_ctz(ma);
         ma &= ma - 1u;
-        uf_unite(par, run_at(ra0, sa, i), i ? run_at(rb0, sb, i - 1) : rb0 - 1u);
+        put_link(list, cap, par, pos++, run_at(ra0, sa, i), i ? run_at(rb0, sb, i - 1) : rb0 - 1u);
     }
 }
 
@@ -652,12 +663,15 @@ struct RegModuleSmem {
     static constexpr u32 RCAP = G * K, KBW = RCAP / 32;
     u32 bm[WORDS];     // fired-pixel bitmap (clear between modules)
     u32 cm[CMW];       // columns holding a fired pixel (clear between modules)
-    u64 acc[RCAP];     // union-find parents (as u32, first half), then charge | size << 44
+    u64 acc[RCAP];     // union-find parents (u32, first half) and the links found (u32,
+                       // second half), then charge | size << 44
     u32 kb[KBW];       // kept-root bits over run index
     u16 rpre[WORDS];   // run starts before each word
     u16 kpre[KBW];     // kept roots before each kb word
     u32 wsum[G / 64];
+    u32 nlink;         // links found (entries of the link list)
 };
+
 
 // A module as a group sees it.
 struct Item {
@@ -820,17 +834,32 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
     }
     if (act)
         for (u32 r = lt; r < nruns; r += G) par[r] = r;
+    if (lt == 0) gp.nlink = 0u;
     gsync<G>();
     mid(1);
     u32 starts = 0;
+    constexpr u32 LCAPL = G * K;                     // link list capacity
+    u32* links = reinterpret_cast<u32*>(gp.acc) + G * K;
+    // unite the listed links, evenly over the group
+    auto unite_links = [&]() {
+        gsync<G>();
+        if (act) {
+            const u32 nl = min(ld_wg(&gp.nlink), LCAPL);
+            for (u32 t = lt; t < nl; t += G) {
+                const u32 l = links[t];
+                uf_unite(par, l >> 16, l & 0xFFFFu);
+            }
+        }
+    };
     if constexpr (WORD_LINKS) {
-        // P3: unions between adjacent fired columns, one (column, word) unit at a time
+        // P3: links between adjacent fired columns, one (column, word) unit at a time
         if (act)
             for (u32 u = lt; u < (COLS - 1) * WPC; u += G) {
                 const u32 c = u / WPC, k = u - c * WPC;
                 if (((gp.cm[c >> 5] >> (c & 31u)) & 1u) && ((gp.cm[(c + 1) >> 5] >> ((c + 1) & 31u)) & 1u))
-                    link_word(par, gp.bm, gp.rpre, c, k);
+                    link_word(par, links, LCAPL, &gp.nlink, gp.bm, gp.rpre, c, k);
             }
+        unite_links();
         gsync<G>();
         // P4: every run points at its root (walks only read; each store writes a root,
         // so a walk through a stored entry still ends at the same root)
@@ -863,26 +892,62 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
         // pixel of rows -1..+1, rule A to the run of the column on its right at row -1
         // when row -2 is fired in either column.
         u32 RS = 0;                                  // slots whose digi starts its run
-        for_slots<K>(nq, [&](u32 q) {
+        const u32 lane = lt & 63u;
+        const u64 below = (1ull << lane) - 1ull;
+        for_slots<K>(nq, [&](u32 q) {                // every lane of the group runs every slot
             const u32 lin = LIN[q];
-            if (lin == NOPIX) return;
-            const u32 col = lin / ROWS, row = lin - col * ROWS;
-            const u32 r = run_of(gp.bm, gp.rpre, lin);
-            AR[q] |= r << 16;
-            if (row > 0 && fired(gp.bm, lin - 1)) return;
-            RS |= 1u << q;
-            if (col > 0) {
-                const u32 lf = lin - ROWS;
-                const u32 f = (row > 0 && fired(gp.bm, lf - 1)) ? lf - 1
-                              : fired(gp.bm, lf)                  ? lf
-                              : (row + 1 < ROWS && fired(gp.bm, lf + 1)) ? lf + 1
-                                                                  : NOPIX;
-                if (f != NOPIX) uf_unite(par, r, run_of(gp.bm, gp.rpre, f));
+            u32 r = 0, ob = NOPIX, oa = NOPIX;       // the run, its links' other runs
+            if (lin != NOPIX) {
+                const u32 col = lin / ROWS, row = lin - col * ROWS;
+                // every bitmap word the rules look at, read at once: rows -2..+1 of
+                // this column and of the columns on either side (clamped into the
+                // module; out-of-module rows and columns are masked off below)
+                const u32 lo = row >= 2 ? lin - 2 : lin - row, hi = row + 1 < ROWS ? lin + 1 : lin;
+                const u32 lcol = col > 0 ? ROWS : 0u, rcol = col + 1 < COLS ? ROWS : 0u;
+                const u32 w0 = lo >> 5, w1 = hi >> 5;                      // this column
+                const u32 l0 = (lo - lcol) >> 5, l1 = (hi - lcol) >> 5;    // left
+                const u32 r0 = (lo + rcol) >> 5, r1 = (hi + rcol) >> 5;    // right
+                const u32 bw0 = gp.bm[w0], bw1 = gp.bm[w1], bl0 = gp.bm[l0], bl1 = gp.bm[l1];
+                const u32 br0 = gp.bm[r0], br1 = gp.bm[r1];
+                const u32 bp = gp.bm[w0 ? w0 - 1 : 0u], rp = gp.rpre[lin >> 5];
+                // fired(pixel at this column's row `rr`, column offset d in {-1, 0, +1})
+                auto at = [&](u32 rr, int d) -> u32 {
+                    if (rr >= ROWS) return 0u;
+                    if ((d < 0 && !col) || (d > 0 && col + 1 >= COLS)) return 0u;
+                    const u32 x = lin - row + rr + (d < 0 ? 0u - ROWS : d > 0 ? ROWS : 0u);
+                    const u32 base = d < 0 ? l0 : d > 0 ? r0 : w0;
+                    const u32 word = (x >> 5) == base ? (d < 0 ? bl0 : d > 0 ? br0 : bw0) : (d < 0 ? bl1 : d > 0 ? br1 : bw1);
+                    return (word >> (x & 31u)) & 1u;
+                };
+                {   // own run: run starts in this word up to this row
+                    const u32 w = lin >> 5, b = lin & 31u;
+                    const u32 bwd = (w == w0) ? bw0 : bw1;
+                    const u32 carry = (w % WPC) ? (((w == w0) ? bp : bw0) >> 31) : 0u;
+                    const u32 st = bwd & ~((bwd << 1) | carry);
+                    r = u32(rp) + __popc(st & ((2u << b) - 1u)) - 1u;
+                }
+                AR[q] |= r << 16;
+                if (!at(row - 1u, 0)) {                      // the digi starts its run
+                    RS |= 1u << q;
+                    const u32 f = at(row - 1u, -1) ? row - 1u : at(row, -1) ? row : at(row + 1u, -1) ? row + 1u : NOPIX;
+                    const bool la = at(row - 1u, 1) && (at(row - 2u, 0) || at(row - 2u, 1));
+                    // run lookups (independent of each other)
+                    if (f != NOPIX) ob = run_of(gp.bm, gp.rpre, lin - row + f - ROWS);
+                    if (la) oa = run_of(gp.bm, gp.rpre, lin + ROWS - 1u);
+                }
             }
-            const u32 rt = lin + ROWS;
-            if (col + 1 < COLS && row > 1 && fired(gp.bm, rt - 1) && (fired(gp.bm, lin - 2) || fired(gp.bm, rt - 2)))
-                uf_unite(par, r, run_of(gp.bm, gp.rpre, rt - 1));
+            // places in the list: one LDS atomic per wave
+            const u64 mb = __ballot(ob != NOPIX), ma = __ballot(oa != NOPIX);
+            const u32 nb = u32(__popcll(mb)), na = u32(__popcll(ma));
+            if (nb + na) {
+                u32 base = 0;
+                if (lane == 0) base = atomicAdd(&gp.nlink, nb + na);
+                base = __shfl(base, 0, 64);
+                if (ob != NOPIX) put_link(links, LCAPL, par, base + u32(__popcll(mb & below)), r, ob);
+                if (oa != NOPIX) put_link(links, LCAPL, par, base + nb + u32(__popcll(ma & below)), r, oa);
+            }
         });
+        unite_links();
         gsync<G>();
         // P4: every run points at its root (read-only walks, each store a root), then
         // each digi's root in one load; the digi that starts its root's run speaks for
@@ -1114,9 +1179,11 @@ constexpr u32 small_waves_per_simd() {
     constexpr u32 w = lds_groups * (WG / 64) / 4;
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
+#ifndef PXCL_WAVES_PER_EU
+#define PXCL_WAVES_PER_EU(...) __attribute__((amdgpu_waves_per_eu(__VA_ARGS__)))
+#endif
 template <u32 WG, u32 MPW, u32 K>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(small_waves_per_simd<WG, MPW, K>())))
-void k_small(LaunchArgs a) {
+__global__ __launch_bounds__(WG) PXCL_WAVES_PER_EU(small_waves_per_simd<WG, MPW, K>()) void k_small(LaunchArgs a) {
     using S = SmallSmem<WG, MPW, K>;
     constexpr u32 G = S::G;
     constexpr bool WAVE = (G == 64);          // groups of one wave run independently

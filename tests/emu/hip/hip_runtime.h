@@ -22,6 +22,7 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define PXCL_WAVES_PER_EU(...)
 #define __shared__ static
 #define __HIPCC__ 1
 
@@ -67,6 +68,7 @@ template <typename T> inline T __shfl_up(T v, unsigned d, int = 64) {
     return r;
 }
 template <typename T> inline T __shfl_xor(T v, int m, int = 64) { return emu_read_lane(v, emu_lane() ^ uint32_t(m)); }
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline uint64_t __ballot(int pred) {
     EmuWave& w = emu_wave();
     w.slot[emu_lane()] = pred ? 1u : 0u;

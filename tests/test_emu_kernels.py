@@ -343,3 +343,18 @@ def test_big_module_word_links(emulator):
     ev = synth.from_pixels(m, r, c, n_modules=3, seed=13)
     for san in ("address", "thread"):
         _check(emulator, [ev], 3, wg=64, mpw=1, grids=(2, 3, 2, 2), sanitizer=san)
+
+
+def test_link_list_overflow(emulator):
+    """More links than a group's link list holds (its run capacity): checkerboards, where
+    every pixel is a run with a link to each neighbouring column, so links are twice the
+    runs; the excess is united at once.  512 pixels in one 64-thread group (list of
+    512), and 16,320 pixels in the big-module kernel (list of 16,384)."""
+    r1, c1 = np.nonzero((np.add.outer(np.arange(32), np.arange(32)) % 2) == 0)
+    r2, c2 = np.nonzero((np.add.outer(np.arange(160), np.arange(204)) % 2) == 0)
+    m = np.concatenate([np.zeros(r1.size, np.int64), np.ones(r2.size, np.int64)])
+    ev = synth.from_pixels(m, np.concatenate([r1 + 50, r2]), np.concatenate([c1 + 100, c2 + 3]), n_modules=2,
+                           seed=14)
+    assert np.bincount(ev["module"]).tolist() == [512, 16320]
+    _check(emulator, [ev], 2, wg=64, mpw=1, grids=(2, 2, 2, 2))
+    _check(emulator, [ev], 2, wg=64, mpw=1, grids=(2, 2, 2, 2), sanitizer="thread")
