@@ -330,6 +330,13 @@ typedef struct {
     uint32_t max_inflight;       /* largest number of events in flight at once */
     uint64_t peak_resident_bytes;/* largest sum of the workspace bytes of occupied slots */
     uint64_t batches;            /* device launches (pxcl_acquire_batch calls) */
+    /* serving form only: median and 99th percentile of the time requests spend in each
+     * stage, in microseconds: [0] arrival -> admission (a free slot), [1] admission ->
+     * launch (batching), [2] launch -> completion callback (device and completion
+     * thread), [3] callback -> produce returned (a CPU thread picking it up) */
+    double stage_p50_us[4];
+    double stage_p99_us[4];
+    double cpu_tasks_per_s_idle; /* serving form: the same CPU threads' task rate with no requests */
 } pxcl_run_stats;
 
 /* Asynchronous form: n_threads host threads, each owning evs[t] and stream
@@ -355,7 +362,9 @@ int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
  * requests that need each class; a request is admitted, in arrival order, when a slot
  * of its class is free, so admission neither allocates nor clears memory.  Every tick
  * the admitted requests not yet launched go to the device as one batch on a free batch
- * object (continuous batching: batches on different streams overlap).  n_cpu_threads
+ * object (continuous batching: batches on different streams overlap), at most
+ * max_inflight of them on the device at once: while they run, arrivals accumulate, so
+ * batches grow with the load instead of the latency.  n_cpu_threads
  * threads run synthetic CPU tasks (cpu_task_ns each) and the produce work.
  * Latency = arrival -> produce returned.  h_pinned must hold n_slots event status
  * blocks (pxcl_event_pinned_bytes each).
@@ -373,6 +382,10 @@ typedef struct {
     uint32_t cpu_task_ns;
     uint32_t flags;              /* PXCL_BATCH_GRAPH */
     uint64_t seed;
+    uint32_t max_inflight;       /* batches on the device at once (0 = n_batches) */
+    uint32_t batch_delay_us;     /* 0: a batch starts as soon as fewer than max_inflight are on
+                                    the device; else, while others run, it waits to be half
+                                    full or for its oldest request to have waited this long */
 } pxcl_serve_opts;
 int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void* h_pinned,
                size_t pinned_bytes, pxcl_batch* const* batches, void* const* streams,

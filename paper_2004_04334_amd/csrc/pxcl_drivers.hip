@@ -25,6 +25,10 @@
 #include <random>
 #include <sstream>
 #include <string>
+#include <sys/prctl.h>
+#include <sys/resource.h>
+#include <sys/syscall.h>
+#include <unistd.h>
 #include <thread>
 #include <vector>
 
@@ -69,6 +73,12 @@ double percentile(std::vector<double>& v, double p) {
 }
 
 std::atomic<u64> g_sink{0};   // keeps the CPU tasks' results alive
+
+// CPU worker threads of the serving form run at a lower priority (nice 10) than the
+// dispatcher and the completion thread: with as many busy workers as cores, those two
+// would otherwise wait for whole scheduler time slices (milliseconds).  Raising a
+// thread's niceness needs no privileges.
+void lower_priority() { (void)setpriority(PRIO_PROCESS, id_t(syscall(SYS_gettid)), 10); }
 
 }  // namespace
 
@@ -180,6 +190,7 @@ namespace {
 
 struct Request {
     double arrival_us;
+    double admit_us, launch_us, done_us, produce_us;   // stage ends
     u32 pool_idx;
     u32 cls;      // size class
     u32 slot;     // event slot while admitted
@@ -207,7 +218,6 @@ struct SlotPool {
 
 struct ServeState;
 
-constexpr double BATCH_DELAY_US = 300.0;   // longest wait for a fuller batch while others run
 
 struct BatchCtx {
     ServeState* S;
@@ -222,14 +232,22 @@ struct ServeState {
     std::deque<u32> produce_q;          // requests whose batch completed
     std::atomic<u32> done{0};
     std::atomic<u32> batch_free_mask{0};
+    Request* req = nullptr;
+    clk::time_point t0;
+    std::atomic<int> dispatch_wake{0};  // a batch completed: the dispatcher may launch
 };
 
 void serve_batch_done(void* user, int32_t) {
     BatchCtx* bc = static_cast<BatchCtx*>(user);
     ServeState* S = bc->S;
+    S->dispatch_wake.store(1, std::memory_order_release);
+    const double now = us_since(S->t0, clk::now());
     {
         std::lock_guard<std::mutex> g(S->mu);
-        for (u32 i = 0; i < bc->k; ++i) S->produce_q.push_back(bc->req[i]);
+        for (u32 i = 0; i < bc->k; ++i) {
+            S->req[bc->req[i]].done_us = now;
+            S->produce_q.push_back(bc->req[i]);
+        }
     }
     S->batch_free_mask.fetch_or(1u << bc->bi, std::memory_order_acq_rel);
     S->cv.notify_one();
@@ -321,8 +339,30 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         }
     }
 
+    // the CPU threads' task rate with no requests (the reference for the rate while serving)
+    double idle_rate = 0.0;
+    if (o->cpu_task_ns) {
+        const u32 nt = std::max<u32>(1, o->n_cpu_threads);
+        std::atomic<u64> n_idle{0};
+        std::vector<std::thread> it;
+        const auto i0 = clk::now();
+        for (u32 t = 0; t < nt; ++t)
+            it.emplace_back([&, t] {
+                lower_priority();
+                u64 k = 0;
+                while (us_since(i0, clk::now()) < 50000.0) {
+                    g_sink.fetch_add(cpu_task(o->cpu_task_ns, k + t), std::memory_order_relaxed);
+                    ++k;
+                }
+                n_idle.fetch_add(k);
+            });
+        for (auto& x : it) x.join();
+        idle_rate = double(n_idle.load()) / (us_since(i0, clk::now()) * 1e-6);
+    }
+
     std::mutex amu;                       // free slots
     ServeState S;
+    S.req = req.data();
     S.batch_free_mask.store((n_batches >= 32 ? 0xFFFFFFFFu : ((1u << n_batches) - 1u)));
     std::vector<BatchCtx> bctx(n_batches);
     for (u32 b = 0; b < n_batches; ++b) { bctx[b].S = &S; bctx[b].bi = b; bctx[b].k = 0; }
@@ -331,11 +371,14 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     std::atomic<u32> errors{0}, inflight{0}, max_inflight{0};
     std::atomic<bool> stop{false};
     std::atomic<int> err_rc{PXCL_OK};
-    const auto t0 = clk::now();
+    // the arrival clock starts once the CPU threads exist (they read it only for
+    // requests, which come after it starts; the hand-over goes through S.mu)
+    clk::time_point t0;
 
     // CPU threads: produce first, else a synthetic task
     auto cpu_worker = [&](u32 t) {
         hipSetDevice(dev);
+        lower_priority();
         u64 local_tasks = 0;
         for (;;) {
             u32 r = 0xFFFFFFFFu;
@@ -352,7 +395,8 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
                 const int st = pxcl_produce(slot_ev[q.slot], &res);
                 const auto p1 = clk::now();
                 blocked_ns.fetch_add(u64(std::chrono::duration_cast<std::chrono::nanoseconds>(p1 - p0).count()));
-                lat[r] = us_since(t0, p1) - q.arrival_us;
+                q.produce_us = us_since(t0, p1);
+                lat[r] = q.produce_us - q.arrival_us;
                 if (d_results && result_offsets) {   // verification mode: copy out, then release
                     u8* dst = static_cast<u8*>(d_results) + result_offsets[r];
                     const size_t nb = size_t(res.n_digis) * 4, cb = size_t(res.n_clusters) * 4;
@@ -387,8 +431,14 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     const u32 ncpu = std::max<u32>(1, o->n_cpu_threads);
     std::vector<std::thread> th;
     for (u32 t = 0; t < ncpu; ++t) th.emplace_back(cpu_worker, t);
+    t0 = clk::now();
+    S.t0 = t0;
 
-    // dispatcher: arrivals -> admission -> batches
+    // dispatcher: arrivals -> admission -> batches.  Its waits are short sleeps; the
+    // thread's timer slack is cut to 1 us meanwhile (the default 50 us would be the
+    // granularity of every wait), and restored at the end.
+    const int old_slack = prctl(PR_GET_TIMERSLACK, 0, 0, 0, 0);
+    prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
     std::deque<u32> arrived, admitted;
     u32 next_arrival = 0;
     std::vector<pxcl_event*> bev(MAXB);
@@ -404,6 +454,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
                 if (fr.empty()) break;
                 q.slot = fr.back();
                 fr.pop_back();
+                q.admit_us = now;
                 P.in_use += P.bytes[q.cls];
                 P.peak = std::max(P.peak, P.in_use);
                 admitted.push_back(arrived.front());
@@ -411,13 +462,16 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
             }
         }
         u32 mask = S.batch_free_mask.load(std::memory_order_acquire);
-        // While other batches are in flight, a batch waits to be half full or for its
-        // oldest request to have waited BATCH_DELAY_US: larger batches are what keeps
-        // up with arrivals; with nothing in flight it starts at once.
+        // At most max_inflight batches on the device: while they run, arrivals
+        // accumulate, so batches grow with the load.  With a batching delay, a batch
+        // also waits, while others run, to be half full or for its oldest request to
+        // have waited that long; with nothing in flight it starts at once.
         const u32 all = n_batches >= 32 ? 0xFFFFFFFFu : ((1u << n_batches) - 1u);
-        const bool ready = !admitted.empty() &&
-                           (mask == all || admitted.size() >= std::max<u32>(1, o->max_batch / 2) ||
-                            now - req[admitted.front()].arrival_us >= BATCH_DELAY_US);
+        const u32 busy = u32(__builtin_popcount(all & ~mask));
+        const u32 limit = o->max_inflight ? std::min(o->max_inflight, n_batches) : n_batches;
+        const bool ready = !admitted.empty() && busy < limit &&
+                           (busy == 0 || !o->batch_delay_us || admitted.size() >= std::max<u32>(1, o->max_batch / 2) ||
+                            now - req[admitted.front()].arrival_us >= double(o->batch_delay_us));
         if (ready && mask) {
             const u32 b = __builtin_ctz(mask);
             S.batch_free_mask.fetch_and(~(1u << b), std::memory_order_acq_rel);
@@ -435,6 +489,8 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
                 ++k;
             }
             bc.k = k;
+            const double lnow = us_since(t0, a0);
+            for (u32 i = 0; i < k; ++i) req[bc.req[i]].launch_us = lnow;
             const int r = pxcl_acquire_batch(batches[b], bev.data(), bin.data(), k, s, serve_batch_done, &bc,
                                              o->flags);
             blocked_ns.fetch_add(u64(std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - a0).count()));
@@ -444,9 +500,15 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
             u32 m = max_inflight.load();
             while (now_in > m && !max_inflight.compare_exchange_weak(m, now_in)) {}
         } else {
-            std::this_thread::sleep_for(std::chrono::microseconds(2));
+            // nothing to launch: sleep until the next arrival or a batch completion,
+            // checking every 5 us at most
+            const double next = next_arrival < o->n_requests ? req[next_arrival].arrival_us : now + 5.0;
+            const double wait = std::min(5.0, std::max(0.0, next - now));
+            if (!S.dispatch_wake.exchange(0, std::memory_order_acq_rel) && wait > 0.5)
+                std::this_thread::sleep_for(std::chrono::nanoseconds(u64(wait * 1000.0)));
         }
     }
+    if (old_slack > 0) prctl(PR_SET_TIMERSLACK, u64(old_slack), 0, 0, 0);
     stop.store(true);
     S.cv.notify_all();
     for (auto& x : th) x.join();
@@ -471,6 +533,17 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     out->max_inflight = max_inflight.load();
     out->peak_resident_bytes = P.peak;
     out->batches = batches_launched.load();
+    std::vector<double> st(o->n_requests);
+    for (int k = 0; k < 4; ++k) {
+        for (u32 i = 0; i < o->n_requests; ++i) {
+            const Request& q = req[i];
+            const double a[5] = {q.arrival_us, q.admit_us, q.launch_us, q.done_us, q.produce_us};
+            st[i] = a[k + 1] - a[k];
+        }
+        out->stage_p50_us[k] = percentile(st, 0.50);
+        out->stage_p99_us[k] = percentile(st, 0.99);
+    }
+    out->cpu_tasks_per_s_idle = idle_rate;
     return err_rc.load();
 }
 

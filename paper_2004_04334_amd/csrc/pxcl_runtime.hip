@@ -1257,7 +1257,9 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     }
     if (any_events) lflags |= LF_GROUP;
     if (any_events == k) lflags |= LF_NO_SEG;
-    lflags |= seg_flag(ctx, sorted_digis);
+    // a captured graph replays with any input: its segmentation always takes wide
+    // chunks (correct for any size), so batches of varying size share one graph
+    lflags |= (flags & PXCL_BATCH_GRAPH) ? LF_SEG_WIDE : seg_flag(ctx, sorted_digis);
     if (e == hipSuccess) {
         if (flags & PXCL_BATCH_GRAPH) {
             hipGraphExec_t exec = nullptr;

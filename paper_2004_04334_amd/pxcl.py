@@ -81,16 +81,23 @@ class RunStats(ctypes.Structure):
                 ("lat_p50_us", ctypes.c_double), ("lat_p99_us", ctypes.c_double), ("lat_max_us", ctypes.c_double),
                 ("blocked_us_per_event", ctypes.c_double), ("cpu_tasks_per_s", ctypes.c_double),
                 ("cpu_tasks", ctypes.c_uint64), ("errors", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
-                ("peak_resident_bytes", ctypes.c_uint64), ("batches", ctypes.c_uint64)]
+                ("peak_resident_bytes", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("stage_p50_us", ctypes.c_double * 4), ("stage_p99_us", ctypes.c_double * 4),
+                ("cpu_tasks_per_s_idle", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 class ServeOpts(ctypes.Structure):
     _fields_ = [("rate_hz", ctypes.c_double), ("n_requests", ctypes.c_uint32), ("budget_bytes", ctypes.c_uint64),
                 ("n_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("n_cpu_threads", ctypes.c_uint32),
-                ("cpu_task_ns", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+                ("cpu_task_ns", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint32), ("batch_delay_us", ctypes.c_uint32)]
 
 
 DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32)
@@ -562,7 +569,8 @@ def run_async(ctx: Context, events: Sequence[Event], streams, pool: Sequence[Dig
 def serve(ctx: Context, arena: torch.Tensor, pinned: torch.Tensor, batches: Sequence[Batch], streams,
           pool: Sequence[Digis], rate_hz: float, n_requests: int, budget_bytes: int, n_slots: int,
           max_batch: int, n_cpu_threads: int = 16, cpu_task_ns: int = 20000, graph: bool = True,
-          seed: int = 1, results: Optional[torch.Tensor] = None, result_offsets: Optional[Sequence[int]] = None):
+          seed: int = 1, results: Optional[torch.Tensor] = None, result_offsets: Optional[Sequence[int]] = None,
+          max_inflight: int = 0, batch_delay_us: int = 0):
     """Serving form; returns (stats dict, per-request status, per-request n_clusters).
     With ``results`` (a device uint8 tensor) and ``result_offsets`` every request's
     outputs are copied there (verification mode)."""
@@ -571,7 +579,8 @@ def serve(ctx: Context, arena: torch.Tensor, pinned: torch.Tensor, batches: Sequ
     sts = (ctypes.c_void_p * nb)(*[int(s.cuda_stream) for s in streams])
     ins = (_Digis * len(pool))(*[d.struct() for d in pool])
     o = ServeOpts(float(rate_hz), int(n_requests), int(budget_bytes), int(n_slots), int(max_batch),
-                  int(n_cpu_threads), int(cpu_task_ns), BATCH_GRAPH if graph else 0, int(seed))
+                  int(n_cpu_threads), int(cpu_task_ns), BATCH_GRAPH if graph else 0, int(seed), int(max_inflight),
+                  int(batch_delay_us))
     st = RunStats()
     rs = (ctypes.c_int32 * n_requests)()
     rn = (ctypes.c_uint32 * n_requests)()

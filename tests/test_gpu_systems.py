@@ -249,10 +249,14 @@ def test_async_driver(px):
 def test_serving_mix_identical_to_alone(px):
     import torch
     pool_np = [synth.serve_event(i) for i in range(12)]
-    refs = [oracle.cluster_event(e, 2000) for e in pool_np]
+    # half the pool in any order (grouped on the device), mixed into the same batches
+    for i in range(0, 12, 2):
+        p = np.random.default_rng(40 + i).permutation(pool_np[i]["module"].size)
+        pool_np[i] = {k: (v[p] if isinstance(v, np.ndarray) else v) for k, v in pool_np[i].items()}
+    refs = [oracle.cluster_event(e, 2000, any_order=(i % 2 == 0)) for i, e in enumerate(pool_np)]
     ctx = px.Context(1856)
-    pool = [px.Digis.from_numpy(e, "cuda") for e in pool_np]
-    n_req = 48
+    pool = [px.Digis.from_numpy(e, "cuda", any_order=(i % 2 == 0)) for i, e in enumerate(pool_np)]
+    n_req = 240
     budget = 64 << 20                                 # small, so that admission binds
     arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     pinned = torch.empty(32 * 64, dtype=torch.uint8, pin_memory=True)
@@ -264,7 +268,7 @@ def test_serving_mix_identical_to_alone(px):
     st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=20000.0, n_requests=n_req,
                                budget_bytes=budget, n_slots=32, max_batch=16, n_cpu_threads=4,
                                cpu_task_ns=10000, graph=True, seed=3, results=results,
-                               result_offsets=offs[:-1].tolist())
+                               result_offsets=offs[:-1].tolist(), max_inflight=2)
     assert st["errors"] == 0 and st["events"] == n_req
     assert st["peak_resident_bytes"] <= budget
     assert st["max_inflight"] > 1, "requests overlap on the device"
