@@ -433,12 +433,13 @@ def bench_batch(px, torch, args, evs, steps, warmup, timed=True):
 
 
 def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda", hint=False, shape=None,
-                any_order=False):
+                any_order=False, fused_hits=False):
     """4 host threads, one event in flight each, synthetic 20 us CPU tasks while waiting;
     the rate is over the driver's own timed window (after its threads are ready)."""
     n_threads = 4
     ctx = px.Context(1856, 2000)
-    pool = [px.Digis.from_numpy(e, where, hint=hint, any_order=any_order) for e in evs]
+    pool = [px.Digis.from_numpy(e, where, hint=hint, any_order=any_order, hits=fused_hits) for e in evs]
+    hits = hits or fused_hits
     cap = max(e["module"].size for e in evs)
     slots = [px.Event(ctx, cap) for _ in range(n_threads)]
     streams = [torch.cuda.Stream() for _ in range(n_threads)]
@@ -485,7 +486,8 @@ def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda
         "errors": st["errors"], "hbm_frac_whole_job": round(b_mean * rate / 1e9 / HBM_PEAK_GBS, 5),
         "config": {"workload": "async: 1856 modules x 160x416, ~50k digis/event, 4 host threads x 1 event "
                                "in flight, synthetic 20 us CPU tasks while waiting" +
-                               (", hits queued behind every event" if hits else "") +
+                               (", hits fused into the clustering" if fused_hits else
+                                ", hits queued behind every event" if hits else "") +
                                (", input in pinned host memory (PCIe copy per event)" if where == "pinned" else ""),
                    "mean_digis": int(np.mean([e["module"].size for e in evs])), "input": where,
                    "size_hint": bool(hint), "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
@@ -612,7 +614,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed batch launches of the headline workload")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["all", "stress", "batch", "serve", "async", "plain", "hits"], default="all")
+    ap.add_argument("--workload", choices=["all", "stress", "batch", "serve", "async", "plain", "hits", "fusedhits"],
+                    default="all")
     ap.add_argument("--cpu-task-ns", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="oracle baseline of the headline, per thread count")
     ap.add_argument("--sub-cpu-seconds", type=float, default=2.0, help="oracle rates of the sub-records")
@@ -638,7 +641,7 @@ def main():
     wl = args.workload
     head = "stress" if wl == "all" else wl
     need = {"stress": ("stress", 16), "batch": ("batch", 64), "serve": ("serve", 32), "async": ("async", 32),
-            "hits": ("async", 32), "plain": ("plain", 32)}
+            "hits": ("async", 32), "fusedhits": ("async", 32), "plain": ("plain", 32)}
     kinds = [head] if wl != "all" else ["stress", "batch", "serve", "async", "plain"]
     evsets = {}
     if not args.copy_calibration:             # drawn before the GPU is touched
@@ -671,8 +674,9 @@ def main():
         r = bench_batch(px, torch, args, evsets["batch"], args.steps, args.warmup)
     elif head == "serve":
         r = bench_serve(px, torch, args, evsets["serve"])
-    elif head in ("async", "hits"):
-        r = bench_async(px, torch, args, evsets[head], args.steps, hits=(head == "hits"))
+    elif head in ("async", "hits", "fusedhits"):
+        r = bench_async(px, torch, args, evsets[head], args.steps, hits=(head == "hits"),
+                        fused_hits=(head == "fusedhits"))
     else:
         r = bench_plain(px, torch, args, evsets["plain"], args.steps)
     if "roofline" in r:
@@ -705,6 +709,11 @@ def main():
         a["host_staged"] = _round({k: hs[k] for k in ("value", "digis_per_s", "lat_p50_us", "lat_p99_us",
                                                       "host_blocked_us_per_event")})
         a["host_staged"]["note"] = "input in pinned host memory: a PCIe copy of 8 B/digi per event, never in value"
+        fh = bench_async(px, torch, args, evsets["async"], SUB_STEPS["async"], shape=shape, fused_hits=True)
+        a["with_fused_hits"] = _round({k: fh[k] for k in ("value", "digis_per_s", "lat_p50_us", "lat_p99_us")})
+        a["with_fused_hits"]["kernel_mean_us"] = fh["roofline"]["kernel_mean_us"]
+        a["with_fused_hits"]["note"] = ("every event asks for its hits (charge-weighted centroids), computed inside the "
+                                        "clustering and compaction kernels and collected through the hits call")
         u = bench_async(px, torch, args, shuffled(evsets["async"]), SUB_STEPS["async"], shape=shape, any_order=True)
         a["any_order"] = _round({k: u[k] for k in ("value", "digis_per_s", "lat_p50_us", "lat_p99_us")})
         a["any_order"]["kernel_mean_us"] = u["roofline"]["kernel_mean_us"]
@@ -717,7 +726,7 @@ def main():
         line["workloads"] = subs
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(evsets[kinds[0] if head != "hits" else "async"], args.cpu_seconds, head)
+        line["cpu_baseline"] = cpu_baseline(evsets[kinds[0]], args.cpu_seconds, head)
     print(json.dumps(line), flush=True)
 
 

@@ -121,9 +121,15 @@ typedef struct {
     uint32_t n;
     int32_t where;        /* PXCL_WHERE_HOST or PXCL_WHERE_DEVICE */
     uint32_t max_module_digis;
-    uint32_t flags;       /* 0 or PXCL_DIGIS_ANY_ORDER */
+    uint32_t flags;       /* PXCL_DIGIS_ANY_ORDER | PXCL_DIGIS_HITS, or 0 */
 } pxcl_digis;
 #define PXCL_DIGIS_ANY_ORDER 1u
+/* Hits fused into the clustering (Figure 1's GPU chain goes from raw data to hits): the
+ * clustering kernels add every kept digi's adc*col and adc*row to exact 64-bit sums of
+ * its cluster, and the compaction writes each cluster's hit beside its record, so the
+ * hits are complete when the event is (pxcl_hits_enqueue then queues no kernel, only
+ * the completion on its stream).  Same values as the hits kernel. */
+#define PXCL_DIGIS_HITS 2u
 
 /* Completion callback.  Runs on the context's completion thread once the event's
  * (or batch's) device work and status write-back are complete; status = PXCL_OK or
@@ -232,6 +238,8 @@ void pxcl_flag_cb(void* user, int32_t status);
  * divided in double precision and rounded to float (NaN for zero charge), one per
  * kept cluster in the clusters' order.
  * pxcl_hits_enqueue queues the hits of the event's last acquire on `stream`
+ * (a kernel over the event's clusters; for an event acquired with PXCL_DIGIS_HITS the
+ * hits were computed with the clusters and only the completion is queued)
  * (hipStream_t) as a consumer of its clusters in the way Sec. 4.2 describes: when
  * `stream` is not the stream the event's work went to and that work may still be
  * running, `stream` first waits for the event's completion event; on the same

@@ -72,6 +72,9 @@ constexpr u32 EF_UNSORTED = 1;   // the digis are in any order: the grouping ker
                                  // from r_*, write a copy grouped by module to the workspace
                                  // (module..adc point there) and each grouped digi's input
                                  // position (perm), where its per-digi output goes
+constexpr u32 EF_HITS = 2;       // hits fused into the clustering: every kept digi adds
+                                 // adc*col and adc*row to its cluster's staging sums (hsum),
+                                 // the compaction writes x and y beside each record
 
 // One event as the kernels see it (144 bytes).
 struct EventDesc {
@@ -137,6 +140,7 @@ struct EvLayout {
     size_t perm;                             // digis in any order: input index of each grouped digi
     size_t grp;                              // digis in any order: the grouped copy (4 x u16[N])
     size_t gcnt;                             // digis in any order: per module, digis counted (zero between launches)
+    size_t hsum;                             // fused hits: per staged record, sum(adc*col), sum(adc*row) (u64)
     size_t total;
 };
 
@@ -167,6 +171,7 @@ PXCL_HD constexpr EvLayout ev_layout(u32 N, u32 M) {
     L.perm = o;       o = al256(o + 4 * n);
     L.grp = o;        o = al256(o + 8 * n);
     L.gcnt = o;       o = al256(o + 4 * m);
+    L.hsum = o;       o = al256(o + 16 * n);
     L.total = o;
     return L;
 }

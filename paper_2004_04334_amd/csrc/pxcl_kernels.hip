@@ -768,6 +768,8 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
     // dense modules (the big-module kernel): unions per (column, word) of the bitmap
     // and roots per run; sparse ones: unions and roots per digi
     constexpr bool WORD_LINKS = K > 8;
+    const bool hits = (E.flags & EF_HITS) != 0;
+    u64* hs = ws_ptr<u64>(E, L.hsum);
     u32* par = reinterpret_cast<u32*>(gp.acc);
     const bool act = I.ok;
     const u32 nq = act ? min((I.n + G - 1) / G, K) : 0u;   // slots that may hold a digi
@@ -1011,24 +1013,43 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
                 const u32 r = AR[q] >> 16;
                 const u64 v = gp.acc[r];
                 const u32 charge = u32(v), size = u32(v >> 44);
-                u32 id = NOPIX;
+                u32 id = NOPIX, pos = 0;
                 if (charge >= a.charge_cut) {
-                    const u32 pos = gp.kpre[r >> 5] + __popc(gp.kb[r >> 5] & ((1u << (r & 31u)) - 1u));
+                    pos = gp.kpre[r >> 5] + __popc(gp.kb[r >> 5] & ((1u << (r & 31u)) - 1u));
                     id = idbase + LIN[q];
                     tid_[I.st + pos] = int32_t(id);
                     tch[I.st + pos] = int32_t(charge);
                     tsz[I.st + pos] = int32_t(size);
+                    if (hits) {
+                        hs[2 * (I.st + pos)] = 0ull;
+                        hs[2 * (I.st + pos) + 1] = 0ull;
+                    }
                 }
-                gp.acc[r] = u64(id);
+                gp.acc[r] = u64(id) | (u64(pos) << 32);        // id (or -1) and record for P9
             }
         if (lt == 0) ws_ptr<u32>(E, L.kept)[I.it] = Kc;
+        if (hits) wait_all_mem();            // the zeroed sums reach memory before P9 adds to them
     }
     mid(3);
     gsync<G>();
-    // P9: per-digi cluster id; clear the bitmap words used
+    // P9: per-digi cluster id (and, with fused hits, its weighted coordinates added
+    // to its cluster's sums); clear the bitmap words used
     if (act) {
         int32_t* od = E.o_digi;
         const u32* perm = perm_of(E, L);
+        if (hits) {
+#pragma unroll
+            for (u32 q = 0; q < K; ++q)
+                if (q < nq && LIN[q] != NOPIX) {
+                    const u64 v = gp.acc[AR[q] >> 16];
+                    if (u32(v) != NOPIX) {
+                        const u32 p = I.st + u32(v >> 32), lin = LIN[q], col = lin / ROWS;
+                        const u64 w = AR[q] & 0xFFFFu;
+                        atomicAdd(&hs[2 * p], w * col);
+                        atomicAdd(&hs[2 * p + 1], w * (lin - col * ROWS));
+                    }
+                }
+        }
 #pragma unroll
         for (u32 q = 0; q < K; ++q) {
             const u32 j = lt + q * G;
@@ -1433,6 +1454,8 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     u32* csz = reinterpret_cast<u32*>(E.o_size) + st;     // per cluster: size
     int32_t* od = E.o_digi;
     const u32* perm = perm_of(E, L);
+    const bool hits = (E.flags & EF_HITS) != 0;
+    u64* hs = ws_ptr<u64>(E, L.hsum);
     u32 err = 0;
     // UNR digis' linear index (NOPIX when absent or out of range), loads first
     auto fetch = [&](u32 base, u32* lin, u32* adc) {
@@ -1639,6 +1662,14 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             const u32 w = tid * KPT + i;
             if (w >= KW) continue;
             u32 pos = keep_pre[i];
+            s.rootp[w] = u16(pos);                              // kept clusters before word w
+            if (hits)
+                for (u32 b = 0; b < 32 && w * 32 + b < ncl; ++b)
+                    if (s.rootb[w] & (1u << b)) {
+                        const u32 q = st + keep_pre[i] + __popc(s.rootb[w] & ((1u << b) - 1u));
+                        hs[2 * q] = 0ull;
+                        hs[2 * q + 1] = 0ull;
+                    }
             for (u32 b = 0; b < 32; ++b) {
                 const u32 c = w * 32 + b;
                 if (c >= ncl) break;
@@ -1663,8 +1694,8 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
     wait_all_mem();
     lds_barrier();
     for (u32 base = 0; base < n; base += SPAN) {               // pass 3: per-digi ids
-        u32 lin[UNR];
-        fetch(base, lin, nullptr);
+        u32 lin[UNR], adc3[UNR];
+        fetch(base, lin, hits ? adc3 : nullptr);
         u32 c[UNR];
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) c[u] = lin[u] != NOPIX ? u32(cl[run_of(s.bm, s.rpre, lin[u])]) : 0u;
@@ -1673,6 +1704,12 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             const u32 j = base + u * BW + tid;
             const u32 id = c[u] < LCAP ? u32(acc[c[u]]) : ld_ag(&cid[c[u]]);
             if (j < n) od[out_pos(perm, st + j)] = lin[u] != NOPIX ? int32_t(id) : -1;
+            if (hits && lin[u] != NOPIX && id != NOPIX) {           // kept: add to its record's sums
+                const u32 cw = c[u] >> 5, q = st + s.rootp[cw] + __popc(s.rootb[cw] & ((1u << (c[u] & 31u)) - 1u));
+                const u64 w = adc3[u], col = lin[u] / ROWS;
+                atomicAdd(&hs[2 * q], w * col);
+                atomicAdd(&hs[2 * q + 1], w * (lin[u] - col * ROWS));
+            }
         }
     }
     if (err) atomicOr(ws_ptr<u32>(E, L.ctl) + CTL_ERR, err);
@@ -1828,10 +1865,15 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         int32_t* oid = E.o_id;
         int32_t* och = E.o_charge;
         int32_t* osz = E.o_size;
+        const bool hits = (E.flags & EF_HITS) != 0;
+        const u64* hsm = ws_ptr<const u64>(E, L.hsum);
+        float* hx = ws_ptr<float>(E, L.hit_x);
+        float* hy = ws_ptr<float>(E, L.hit_y);
         const u32 mod_src = src_ok ? src : NOPIX;          // a record of a bad module is skipped
         const u32 j_lo = u32(u64(T) * part / sp), j_hi = u32(u64(T) * (part + 1) / sp);
         for (u32 j0 = j_lo; j0 < j_hi; j0 += 64 * CP_UNR) {
             int32_t r0[CP_UNR], r1[CP_UNR], r2[CP_UNR];
+            u64 sx[CP_UNR], sy[CP_UNR];
             u32 from[CP_UNR];
 #pragma unroll
             for (u32 q = 0; q < CP_UNR; ++q) {
@@ -1847,6 +1889,11 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
                 r0[q] = tid_[fs];
                 r1[q] = tch[fs];
                 r2[q] = tsz[fs];
+                sx[q] = sy[q] = 0ull;
+                if (hits) {
+                    sx[q] = hsm[2 * fs];
+                    sy[q] = hsm[2 * fs + 1];
+                }
             }
 #pragma unroll
             for (u32 q = 0; q < CP_UNR; ++q) {
@@ -1855,6 +1902,11 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
                     oid[base + j] = r0[q];
                     och[base + j] = r1[q];
                     osz[base + j] = r2[q];
+                    if (hits) {                            // the centroid, as the hits kernel computes it
+                        const u32 ch = u32(r1[q]);
+                        hx[base + j] = ch ? float(double(sx[q]) / double(ch)) : __int_as_float(0x7FC00000);
+                        hy[base + j] = ch ? float(double(sy[q]) / double(ch)) : __int_as_float(0x7FC00000);
+                    }
                 }
             }
         }

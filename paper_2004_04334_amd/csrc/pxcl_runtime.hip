@@ -260,7 +260,7 @@ bool digis_ok(const pxcl_digis* in) {
     if (!in) return false;
     if (in->where != PXCL_WHERE_HOST && in->where != PXCL_WHERE_DEVICE) return false;
     if (in->n && (!in->module || !in->row || !in->col || !in->adc)) return false;
-    if (in->flags & ~PXCL_DIGIS_ANY_ORDER) return false;
+    if (in->flags & ~(PXCL_DIGIS_ANY_ORDER | PXCL_DIGIS_HITS)) return false;
     return true;
 }
 
@@ -291,9 +291,10 @@ hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventD
     // digis in any order: the kernels read them through r_* and cluster the grouped
     // copy the grouping kernels write to the workspace
     const bool any = (in->flags & PXCL_DIGIS_ANY_ORDER) != 0;
+    if (in->flags & PXCL_DIGIS_HITS) d->flags |= EF_HITS;
     const u16** dst[4] = {&d->module, &d->row, &d->col, &d->adc};
     if (any) {
-        d->flags = EF_UNSORTED;
+        d->flags |= EF_UNSORTED;
         u16* g = reinterpret_cast<u16*>(ev->ws + L.grp);
         for (int i = 0; i < 4; ++i) *dst[i] = g + size_t(i) * ev->cap;
         dst[0] = &d->r_module; dst[1] = &d->r_row; dst[2] = &d->r_col; dst[3] = &d->r_adc;
@@ -406,7 +407,9 @@ static void completer_post(pxcl_ctx* ctx, int kind, void* obj, hipEvent_t done) 
 // from hipGetSymbolAddress, looked up once per device with that device current.
 // ---------------------------------------------------------------------------
 constexpr u32 NOALLOC_CAP = PXCL_NOALLOC_MAX_DIGIS;
-static_assert(ev_layout(NOALLOC_CAP, PXCL_MAX_MODULES).total == PXCL_NOALLOC_SCRATCH_BYTES,
+// The entry point takes no input flags, so its kernels never reach the fused-hit sums
+// at the end of the layout: the array ends where they would begin.
+static_assert(ev_layout(NOALLOC_CAP, PXCL_MAX_MODULES).hsum == PXCL_NOALLOC_SCRATCH_BYTES,
               "PXCL_NOALLOC_SCRATCH_BYTES matches the workspace layout");
 static __device__ __align__(256) u8 scratch[PXCL_NOALLOC_SCRATCH_BYTES];
 
@@ -870,15 +873,18 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
     ev->hits_stream = s;
     ev->hits_status = PXCL_OK;
     ev->hits_n = 0;
-    LaunchArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.single = ev->desc;
-    a.n_modules = ctx->n_modules;
-    a.charge_cut = ctx->charge_cut;
-    const u32 grid = u32(std::max<u64>(1, std::min<u64>((u64)ctx->n_cu * ctx->occ_h, ctx->n_modules)));
-    if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[0], s);
-    if (e == hipSuccess) e = launch_hits(a, grid, s);
-    if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[1], s);
+    const bool fused = (ev->desc.flags & EF_HITS) != 0;   // computed with the clusters
+    if (!fused) {
+        LaunchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.single = ev->desc;
+        a.n_modules = ctx->n_modules;
+        a.charge_cut = ctx->charge_cut;
+        const u32 grid = u32(std::max<u64>(1, std::min<u64>((u64)ctx->n_cu * ctx->occ_h, ctx->n_modules)));
+        if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[0], s);
+        if (e == hipSuccess) e = launch_hits(a, grid, s);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[1], s);
+    }
     if (e == hipSuccess) e = hipEventRecord(ev->hits_ev, s);
     if (e == hipSuccess) {
         ev->hits_pending.fetch_add(1, std::memory_order_acq_rel);
@@ -890,7 +896,7 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
         ev->hstate.store(ST_IDLE, std::memory_order_release);
         return PXCL_E_HIP;
     }
-    ev->hits_timed = timed;
+    ev->hits_timed = timed && !fused;
     return PXCL_OK;
 }
 

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libpxcl.so")
 OK, E_INVAL, E_CAPACITY, E_BUSY, E_NOT_READY = 0, -1, -2, -3, -4
 E_DUP_PIXEL, E_RANGE, E_ORDER, E_HIP, E_INTERNAL, E_NOTFOUND, E_HINT = -5, -6, -7, -8, -10, -11, -12
 WHERE_HOST, WHERE_DEVICE = 0, 1
-DIGIS_ANY_ORDER = 1
+DIGIS_ANY_ORDER, DIGIS_HITS = 1, 2
 BATCH_GRAPH = 1
 MAX_BATCH = 128
 ROWS, COLS, PIXELS_PER_MODULE = 160, 416, 66560
@@ -219,6 +219,7 @@ class Digis:
     adc: torch.Tensor
     max_module_digis: int = 0
     any_order: bool = False
+    hits: bool = False           # hits fused into the clustering
 
     @property
     def n(self) -> int:
@@ -236,10 +237,12 @@ class Digis:
             if t.is_cuda != self.module.is_cuda or (not t.is_cuda and not t.is_pinned()):
                 raise ValueError("digis must all be on the device or all in pinned host memory")
         return _Digis(*(t.data_ptr() if self.n else None for t in ts), self.n, self.where,
-                      int(self.max_module_digis), DIGIS_ANY_ORDER if self.any_order else 0)
+                      int(self.max_module_digis),
+                      (DIGIS_ANY_ORDER if self.any_order else 0) | (DIGIS_HITS if self.hits else 0))
 
     @staticmethod
-    def from_numpy(ev, device: str = "cuda", hint: bool = False, any_order: bool = False) -> "Digis":
+    def from_numpy(ev, device: str = "cuda", hint: bool = False, any_order: bool = False,
+                   hits: bool = False) -> "Digis":
         """Copy a numpy event; with `hint`, the largest number of digis sharing a
         module id (a host-side count over the event) is passed as max_module_digis;
         with `any_order` the digis are flagged as being in any order."""
@@ -252,7 +255,7 @@ class Digis:
                 t = t.pin_memory()
             ts.append(t.contiguous())
         mx = int(np.bincount(ev["module"]).max()) if (hint and ev["module"].size) else 0
-        return Digis(*ts, max_module_digis=mx, any_order=any_order)
+        return Digis(*ts, max_module_digis=mx, any_order=any_order, hits=hits)
 
 
 @dataclass

@@ -35,7 +35,8 @@ def build(force: bool = False, sanitizer: str = "address") -> str:
 
 def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, grids=(2, 2, 2, 2), caps=None,
         header: bool = False, sanitizer: str = "address", no_big: bool = False, hits: bool = False,
-        seg_wide: bool = False, fused: bool = False, stale_ticket: bool = False, any_order=None):
+        seg_wide: bool = False, fused: bool = False, stale_ticket: bool = False, any_order=None,
+        fused_hits: bool = False):
     """Cluster `events` (list of dicts of uint16 arrays) as one launch; returns a list
     of result dicts like the oracle's (status from the error bits).  With `header` the
     events are passed through a batch header even when there is only one; with
@@ -46,7 +47,9 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
     module ranges by search (the single-event launch form); with `stale_ticket` the
     launch counters hold a ticket a launch that stopped after its small kernel left.
     `any_order` (one bool per event) flags events whose digis are in any order: the
-    grouping kernels run first, and segmentation only if some event is grouped."""
+    grouping kernels run first, and segmentation only if some event is grouped.
+    `fused_hits`: every event asks for hits fused into the clustering (no hits kernel;
+    the results carry "x" and "y")."""
     any_order = [False] * len(events) if any_order is None else list(any_order)
     lflags = int(no_big) | (int(seg_wide) << 1) | (int(fused) << 2) | (int(stale_ticket) << 31)
     if any(any_order):
@@ -55,12 +58,13 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
         with open(fin, "wb") as f:
-            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), lflags, int(hits)],
+            np.array([len(events), n_modules, cut, wg, mpw, *grids, int(header), lflags,
+                      2 if fused_hits else int(hits)],
                      dtype=np.uint32).tofile(f)
             for i, ev in enumerate(events):
                 n = ev["module"].size
                 cap = max(1, n) if caps is None else caps[i]
-                np.array([n, cap, int(any_order[i])], dtype=np.uint32).tofile(f)
+                np.array([n, cap, int(any_order[i]) | (2 if fused_hits else 0)], dtype=np.uint32).tofile(f)
                 for key in ("module", "row", "col", "adc"):
                     np.ascontiguousarray(ev[key], dtype=np.uint16).tofile(f)
         env = dict(os.environ)
@@ -80,7 +84,7 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
         chg = raw[p:p + ncl]; p += ncl
         siz = raw[p:p + ncl]; p += ncl
         hx = hy = None
-        if hits:
+        if hits or fused_hits:
             hx = raw[p:p + ncl].view(np.float32); p += ncl
             hy = raw[p:p + ncl].view(np.float32); p += ncl
         st = 0
@@ -98,7 +102,7 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
             st = -10
         r = {"status": st, "err_bits": err, "n_clusters": ncl, "digi": digi.copy(), "id": cid.copy(),
              "charge": chg.copy(), "size": siz.copy()}
-        if hits:
+        if hits or fused_hits:
             r["x"], r["y"] = hx.copy(), hy.copy()
         out.append(r)
     return out

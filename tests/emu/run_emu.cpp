@@ -40,6 +40,7 @@ int main(int argc, char** argv) {
         rd(f, nc, 12);
         const u32 n = nc[0], cap = nc[1];
         const bool any = (nc[2] & 1u) != 0;
+        const bool fused_hits = (nc[2] & 2u) != 0;
         in[e].resize(4 * size_t(n) + 4);
         rd(f, in[e].data(), 8 * size_t(n));
         const EvLayout L = ev_layout(cap, M);
@@ -65,8 +66,9 @@ int main(int argc, char** argv) {
         d.row = in[e].data() + n;
         d.col = in[e].data() + 2 * size_t(n);
         d.adc = in[e].data() + 3 * size_t(n);
+        if (fused_hits) d.flags |= EF_HITS;
         if (any) {                        // the kernels read the raw digis and cluster a grouped copy
-            d.flags = EF_UNSORTED;
+            d.flags |= EF_UNSORTED;
             d.r_module = d.module; d.r_row = d.row; d.r_col = d.col; d.r_adc = d.adc;
             const u16* g = reinterpret_cast<const u16*>(ws[e] + L.grp);
             d.module = g; d.row = g + cap; d.col = g + 2 * size_t(cap); d.adc = g + 3 * size_t(cap);
@@ -113,7 +115,7 @@ int main(int argc, char** argv) {
         fprintf(stderr, "launch failed\n");
         return 3;
     }
-    if (h[11] && launch_hits(a, h[8], nullptr)) {
+    if (h[11] == 1 && launch_hits(a, h[8], nullptr)) {
         fprintf(stderr, "hits launch failed\n");
         return 3;
     }

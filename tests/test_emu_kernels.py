@@ -358,3 +358,32 @@ def test_link_list_overflow(emulator):
     assert np.bincount(ev["module"]).tolist() == [512, 16320]
     _check(emulator, [ev], 2, wg=64, mpw=1, grids=(2, 2, 2, 2))
     _check(emulator, [ev], 2, wg=64, mpw=1, grids=(2, 2, 2, 2), sanitizer="thread")
+
+
+@pytest.mark.parametrize("sanitizer", ["address", "thread"])
+def test_fused_hits(emulator, sanitizer):
+    """Hits fused into the clustering (every kept digi adds its weighted coordinates to
+    its cluster's record, the compaction divides): bit-exact against the oracle's hits
+    for several events through a header (one with a module for the big-module kernel
+    at narrow shapes), a single fused-form event, a scratch-mode serpentine beside a
+    lattice with more clusters than scratch mode keeps in LDS, and shuffled digis."""
+    evs = _mixed_events()
+    for wg, mpw, fused, ev_list, m in ((64, 1, False, evs, 6), (256, 2, True, [evs[0]], 6)):
+        res = emu.run(ev_list, m, wg=wg, mpw=mpw, grids=(2, 2, 3, 2), header=not fused, fused=fused,
+                      fused_hits=True, sanitizer=sanitizer)
+        for i, (r, e) in enumerate(zip(res, ev_list)):
+            ref = emulator.hits(e, 2000)
+            compare(r, ref, f"event {i}")
+            assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"]), f"hits of event {i}"
+    if sanitizer == "address":
+        sr, sc = synth.serpentine(row_wise=True)
+        lr, lc = np.meshgrid(np.arange(0, 160, 2), np.arange(0, 416, 2), indexing="ij")
+        mm = np.concatenate([np.zeros(sr.size, np.int64), np.ones(lr.size, np.int64)])
+        big = synth.from_pixels(mm, np.concatenate([sr, lr.ravel()]), np.concatenate([sc, lc.ravel()]),
+                                n_modules=2, seed=6)
+        shuf = _shuffled(dict(synth.plain_event(8, n_modules=4), n_modules=4), 3)
+        for ev, m, any_o in ((big, 2, False), (shuf, 4, True)):
+            (r,) = emu.run([ev], m, grids=(2, 2, 2, 2), fused_hits=True, any_order=[any_o])
+            ref = emulator.hits(ev, 2000, any_order=any_o)
+            compare(r, ref, "fused hits")
+            assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])

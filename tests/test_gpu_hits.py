@@ -207,3 +207,61 @@ def test_copy_to_host_on_demand(px):
     px.hits_wait(slot)
     slot.close()
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# hits fused into the clustering (PXCL_DIGIS_HITS): no hits kernel; the same values
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("wg,mpw", [(64, 1), (256, 4), (512, 1)])
+def test_fused_hits_single_events(px, wg, mpw):
+    import torch
+    evs = [dict(synth.plain_event(2), n_modules=1856), synth.async_event(9), synth.stress_event(5)]
+    ctx = px.Context(1856, 2000)
+    ctx.set_kernel_config(wg, mpw)
+    for i, ev in enumerate(evs):
+        print(f"fused hits, shape {wg}x{mpw}, event {i}", flush=True)
+        slot = px.Event(ctx, ev["module"].size)
+        s, other = torch.cuda.Stream(), torch.cuda.Stream()
+        px.acquire(slot, px.Digis.from_numpy(ev, "cuda", hits=True), s)
+        px.hits_enqueue(slot, other)               # another stream: waits, queues no kernel
+        px.hits_wait(slot)
+        px.wait(slot)
+        _check_hits(px, slot, ev, f"fused, event {i}")
+        slot.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_fused_hits_batch_mixed(px, graph):
+    """A batch mixing events with fused hits, events without them and shuffled events
+    with fused hits; then the hits of every event with fused hits."""
+    import torch
+    base = [synth.batch_event(50 + i) for i in range(8)]
+    flags = [(i % 2 == 0, i % 4 == 2) for i in range(8)]          # (fused hits, any order)
+    evs = []
+    for i, (e, (h, a)) in enumerate(zip(base, flags)):
+        if a:
+            p = np.random.default_rng(80 + i).permutation(e["module"].size)
+            e = {k: (v[p] if isinstance(v, np.ndarray) else v) for k, v in e.items()}
+        evs.append(e)
+    ctx = px.Context(1856, 2000)
+    cap = max(e["module"].size for e in evs)
+    slots = [px.Event(ctx, cap) for _ in evs]
+    b = px.Batch(ctx, len(evs))
+    digis = [px.Digis.from_numpy(e, "cuda", hits=h, any_order=a) for e, (h, a) in zip(evs, flags)]
+    f = px.Flag()
+    px.acquire_batch(b, slots, digis, torch.cuda.current_stream(), flag=f, graph=graph)
+    for s in slots:
+        px.wait(s)
+    for i, (slot, e, (h, a)) in enumerate(zip(slots, evs, flags)):
+        ref = oracle.hits(e, 2000, any_order=a)
+        compare(px.produce(slot).numpy(), ref, f"batch event {i}")
+        if h:
+            px.hits_enqueue(slot, torch.cuda.current_stream())
+            px.hits_wait(slot)
+            hn = px.hits_produce(slot).numpy()
+            assert np.array_equal(hn["x"], ref["x"]) and np.array_equal(hn["y"], ref["y"]), f"hits of event {i}"
+    for s in slots:
+        s.close()
+    b.close()
+    ctx.close()
