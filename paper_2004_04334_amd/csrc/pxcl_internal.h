@@ -74,7 +74,10 @@ constexpr u32 EF_UNSORTED = 1;   // the digis are in any order: the grouping ker
                                  // position (perm), where its per-digi output goes
 constexpr u32 EF_HITS = 2;       // hits fused into the clustering: every kept digi adds
                                  // adc*col and adc*row to its cluster's staging sums (hsum),
-                                 // the compaction writes x and y beside each record
+                                 // the compaction writes x and y beside each record and
+                                 // zeroes the sums it read: they are zero between launches
+                                 // (binding clears them, and so does the host after a
+                                 // launch that failed or reported an error)
 
 // One event as the kernels see it (144 bytes).
 struct EventDesc {

@@ -395,6 +395,7 @@ __device__ __forceinline__ void link_pair(u32* par, const ColPair& P, u32 lane) 
 // order); the clustering does not depend on it.
 // ---------------------------------------------------------------------------
 constexpr u32 G_WG = 256, G_PER = 16, G_CH = G_WG * G_PER, G_HMAX = 4096, G_TPM = 8;
+constexpr u32 G_SPER = 4, G_SCH = G_WG * G_SPER;   // scatter: smaller chunks, more workgroups
 
 struct GroupArrays {
     u16 *m, *r, *c, *a;
@@ -447,11 +448,21 @@ __global__ __launch_bounds__(G_WG) void k_group_count(LaunchArgs a) {
             }
         }
         lds_barrier();
-        if (lds)
-            for (u32 m = tid; m < M; m += G_WG) {
-                const u32 h = hist[m];
-                if (h) hist[m] = atomicAdd(&gcnt[m], h);
+        if (lds) {                                // the chunk's bases: independent atomics, all in flight
+            constexpr u32 FL = G_HMAX / G_WG;
+            u32 h[FL];
+#pragma unroll
+            for (u32 j = 0; j < FL; ++j) {
+                const u32 m = tid + j * G_WG;
+                h[j] = m < M ? hist[m] : 0u;
             }
+#pragma unroll
+            for (u32 j = 0; j < FL; ++j)
+                if (h[j]) h[j] = atomicAdd(&gcnt[tid + j * G_WG], h[j]);
+#pragma unroll
+            for (u32 j = 0; j < FL; ++j)
+                if (tid + j * G_WG < M) hist[tid + j * G_WG] = h[j];
+        }
         lds_barrier();
 #pragma unroll
         for (u32 q = 0; q < G_PER; ++q)
@@ -522,7 +533,7 @@ __global__ __launch_bounds__(G_WG) void k_group_scatter(LaunchArgs a) {
     __shared__ u32 s_pref[MAXB + 1];
     __shared__ u32 s_wsum[G_WG / 64];
     const u32 tid = threadIdx.x, k = num_events(a), M = a.n_modules;
-    const u32 total = event_prefix<G_WG>(a, k, s_pref, s_wsum, CNT_ANY, G_CH, 0);
+    const u32 total = event_prefix<G_WG>(a, k, s_pref, s_wsum, CNT_ANY, G_SCH, 0);
     for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
         const u32 e = find_slot(s_pref, k, t), c = t - s_pref[e];
         const EventDesc E = get_event(a, e);
@@ -530,25 +541,37 @@ __global__ __launch_bounds__(G_WG) void k_group_scatter(LaunchArgs a) {
         const ModRange* mt = ws_ptr<const ModRange>(E, L.mtab);
         const u32* rank = reinterpret_cast<const u32*>(E.o_digi);
         const GroupArrays G = group_arrays(E, L);
-        const u32 i0 = c * G_CH + tid;
-        u32 mm[G_PER];
+        // every load first (module ids, then table entries, ranks and the digis), then
+        // the stores: stores to the grouped copy could alias the input for the compiler,
+        // which would otherwise keep each digi's loads behind the previous digi's stores
+        const u32 i0 = c * G_SCH + tid;
+        u32 mm[G_SPER], pos[G_SPER], rr[G_SPER], cc[G_SPER], aa[G_SPER];
 #pragma unroll
-        for (u32 q = 0; q < G_PER; ++q) {
+        for (u32 q = 0; q < G_SPER; ++q) {
             const u32 i = i0 + q * G_WG;
             mm[q] = i < E.n ? u32(E.r_module[i]) : NOPIX;
         }
 #pragma unroll
-        for (u32 q = 0; q < G_PER; ++q) {
+        for (u32 q = 0; q < G_SPER; ++q) {
             const u32 i = i0 + q * G_WG;
-            if (mm[q] >= M) continue;            // past the end, or out of range (flagged by count)
-            const ModRange r = mt[mm[q]];
-            const u32 p = u32(r.first) + rank[i];
-            if (u32(r.first >> 32) != E.epoch || p >= u32(r.end)) continue;   // only after an internal error
+            const bool v = mm[q] < M;            // past the end, or out of range (flagged by count)
+            const u32 iv = v ? i : 0u;
+            const ModRange r = mt[v ? mm[q] : 0u];
+            pos[q] = (v && u32(r.first >> 32) == E.epoch) ? u32(r.first) + rank[iv] : NOPIX;
+            if (pos[q] != NOPIX && pos[q] >= u32(r.end)) pos[q] = NOPIX;   // only after an internal error
+            rr[q] = E.r_row[iv];
+            cc[q] = E.r_col[iv];
+            aa[q] = E.r_adc[iv];
+        }
+#pragma unroll
+        for (u32 q = 0; q < G_SPER; ++q) {
+            const u32 p = pos[q];
+            if (p == NOPIX) continue;
             G.m[p] = u16(mm[q]);
-            G.r[p] = E.r_row[i];
-            G.c[p] = E.r_col[i];
-            G.a[p] = E.r_adc[i];
-            G.perm[p] = i;
+            G.r[p] = u16(rr[q]);
+            G.c[p] = u16(cc[q]);
+            G.a[p] = u16(aa[q]);
+            G.perm[p] = i0 + q * G_WG;
         }
     }
 }
@@ -1020,15 +1043,10 @@ __device__ __forceinline__ void cluster_regs(const LaunchArgs& a, const EventDes
                     tid_[I.st + pos] = int32_t(id);
                     tch[I.st + pos] = int32_t(charge);
                     tsz[I.st + pos] = int32_t(size);
-                    if (hits) {
-                        hs[2 * (I.st + pos)] = 0ull;
-                        hs[2 * (I.st + pos) + 1] = 0ull;
-                    }
                 }
                 gp.acc[r] = u64(id) | (u64(pos) << 32);        // id (or -1) and record for P9
             }
         if (lt == 0) ws_ptr<u32>(E, L.kept)[I.it] = Kc;
-        if (hits) wait_all_mem();            // the zeroed sums reach memory before P9 adds to them
     }
     mid(3);
     gsync<G>();
@@ -1663,13 +1681,6 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
             if (w >= KW) continue;
             u32 pos = keep_pre[i];
             s.rootp[w] = u16(pos);                              // kept clusters before word w
-            if (hits)
-                for (u32 b = 0; b < 32 && w * 32 + b < ncl; ++b)
-                    if (s.rootb[w] & (1u << b)) {
-                        const u32 q = st + keep_pre[i] + __popc(s.rootb[w] & ((1u << b) - 1u));
-                        hs[2 * q] = 0ull;
-                        hs[2 * q + 1] = 0ull;
-                    }
             for (u32 b = 0; b < 32; ++b) {
                 const u32 c = w * 32 + b;
                 if (c >= ncl) break;
@@ -1866,7 +1877,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         int32_t* och = E.o_charge;
         int32_t* osz = E.o_size;
         const bool hits = (E.flags & EF_HITS) != 0;
-        const u64* hsm = ws_ptr<const u64>(E, L.hsum);
+        u64* hsm = ws_ptr<u64>(E, L.hsum);
         float* hx = ws_ptr<float>(E, L.hit_x);
         float* hy = ws_ptr<float>(E, L.hit_y);
         const u32 mod_src = src_ok ? src : NOPIX;          // a record of a bad module is skipped
@@ -1890,7 +1901,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
                 r1[q] = tch[fs];
                 r2[q] = tsz[fs];
                 sx[q] = sy[q] = 0ull;
-                if (hits) {
+                if (hits && from[q] != NOPIX) {
                     sx[q] = hsm[2 * fs];
                     sy[q] = hsm[2 * fs + 1];
                 }
@@ -1906,6 +1917,8 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
                         const u32 ch = u32(r1[q]);
                         hx[base + j] = ch ? float(double(sx[q]) / double(ch)) : __int_as_float(0x7FC00000);
                         hy[base + j] = ch ? float(double(sy[q]) / double(ch)) : __int_as_float(0x7FC00000);
+                        hsm[2 * from[q]] = 0ull;           // the sums are zero again for the next launch
+                        hsm[2 * from[q] + 1] = 0ull;
                     }
                 }
             }
@@ -2036,15 +2049,16 @@ int occupancy_group() {
                     occ(reinterpret_cast<const void*>(k_group_scatter), G_WG));
 }
 u32 group_chunk() { return G_CH; }
+u32 group_scatter_chunk() { return G_SCH; }
 // The grouping kernels of the events in any order: count over `grid` workgroups,
-// the table over `grid_events`, scatter over `grid`.
-hipError_t launch_group(const LaunchArgs& a, u32 grid, u32 grid_events, hipStream_t s) {
+// the table over `grid_events`, scatter over `grid_scatter`.
+hipError_t launch_group(const LaunchArgs& a, u32 grid, u32 grid_events, u32 grid_scatter, hipStream_t s) {
     hipLaunchKernelGGL(k_group_count, dim3(grid), dim3(G_WG), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_group_table, dim3(grid_events), dim3(G_WG), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_group_scatter, dim3(grid), dim3(G_WG), 0, s, a);
+    hipLaunchKernelGGL(k_group_scatter, dim3(grid_scatter), dim3(G_WG), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_segment(const LaunchArgs& a, u32 grid, hipStream_t s) {

@@ -45,7 +45,8 @@ hipError_t launch_hits(const LaunchArgs& a, u32 grid, hipStream_t s);
 hipError_t launch_fill(u32* p, u32 n, u32 v, hipStream_t s);
 int occupancy_group();
 u32 group_chunk();
-hipError_t launch_group(const LaunchArgs& a, u32 grid, u32 grid_events, hipStream_t s);
+u32 group_scatter_chunk();
+hipError_t launch_group(const LaunchArgs& a, u32 grid, u32 grid_events, u32 grid_scatter, hipStream_t s);
 }  // namespace pxcl
 
 using namespace pxcl;
@@ -137,11 +138,13 @@ struct pxcl_event {
     u32 timed_flags = 0;              // launch flags of the timed launch (kernels it ran)
     EventDesc desc{};                 // the event as the kernels saw it (for the hits)
     u32 slot = 0;                     // launch parity of the last launch
-    bool dirty = false;               // a launch failed to queue: clear the control words
+    bool dirty = false;               // a launch failed to queue or reported an error: clear
+                                      // the control words, grouping counts and hit sums first
     // hits of the last acquired event
     std::atomic<int> hstate{ST_IDLE};
     std::atomic<int> hits_pending{0};
     hipEvent_t hits_ev = nullptr;
+    hipEvent_t hits_done = nullptr;   // the event the last hits completion waits for
     hipEvent_t hits_tev[2] = {};      // around the hits kernel of a timed launch
     bool hits_timed = false;
     u32 hits_launches = 0;
@@ -193,7 +196,7 @@ namespace {
 
 struct Grids {
     u32 a, b, s, c, x;   // segment, big, small, compact, scratch
-    u32 g, ge;           // grouping of digis in any order: count/scatter, table
+    u32 g, ge, gs;       // grouping of digis in any order: count, table, scatter
 };
 
 // Wide segmentation chunks once a launch holds at least one of them per compute
@@ -221,11 +224,13 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
     const u64 fg = ncu * (u64)ctx->occ_g;
     if (full) {
         g.a = u32(fa); g.b = u32(fb); g.s = u32(fs); g.c = u32(fc); g.x = u32(fx);
-        g.g = u32(fg); g.ge = u32(std::min<u64>(ncu, MAXB));
+        g.g = u32(fg); g.ge = u32(std::min<u64>(ncu, MAXB)); g.gs = u32(fg);
         return g;
     }
     const u64 gch = group_chunk();
     g.g = u32(std::max<u64>(1, std::min<u64>(fg, (any_digis + gch - 1) / gch + any_events)));
+    const u64 gsc = group_scatter_chunk();
+    g.gs = u32(std::max<u64>(1, std::min<u64>(fg, (any_digis + gsc - 1) / gsc + any_events)));
     g.ge = std::max<u32>(1u, any_events);
     const u32 dcap = cluster_capacity(wg, mpw);
     const u64 ch = seg_chunk(flags);
@@ -244,7 +249,7 @@ Grids grids_for(const pxcl_ctx* ctx, u32 wg, u32 mpw, u64 digis, u64 present, u3
 hipError_t launch_all(const LaunchArgs& a, const Grids& g, u32 wg, u32 mpw, hipStream_t s, hipEvent_t* tev) {
     hipError_t e;
     if (tev && (e = hipEventRecord(tev[0], s)) != hipSuccess) return e;
-    if ((a.flags & LF_GROUP) && (e = launch_group(a, g.g, g.ge, s)) != hipSuccess) return e;
+    if ((a.flags & LF_GROUP) && (e = launch_group(a, g.g, g.ge, g.gs, s)) != hipSuccess) return e;
     if (!(a.flags & (LF_FUSED | LF_NO_SEG)) && (e = launch_segment(a, g.a, s)) != hipSuccess) return e;
     if (tev && (e = hipEventRecord(tev[1], s)) != hipSuccess) return e;
     if ((e = launch_small(wg, mpw, a, g.s, s)) != hipSuccess) return e;   // lists the big modules
@@ -273,6 +278,7 @@ hipError_t make_desc(pxcl_event* ev, const pxcl_digis* in, hipStream_t s, EventD
     if (ev->dirty) {
         hipError_t e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
         if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.gcnt, 0, size_t(4) * ev->ctx->n_modules, s);
+        if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.hsum, 0, size_t(16) * ev->cap, s);
         if (e != hipSuccess) return e;
         ev->dirty = false;
     }
@@ -326,6 +332,9 @@ void finish_event_from_host_status(pxcl_event* ev) {
     const u32 ncl = hs[HS_NCL];
     ev->ncl = ncl < ev->n ? ncl : ev->n;              // never more clusters than digis
     ev->status = status_from_bits(bits);
+    // after an error some staged sums of fused hits may not have been read back and
+    // zeroed by the compaction: the next launch clears the slot's scratch first
+    if (ev->status != PXCL_OK) ev->dirty = true;
 }
 
 // Set while a completion callback runs on this thread: a wait called from inside
@@ -579,6 +588,7 @@ extern "C" int pxcl_event_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void*
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.ctl, 0, CTL_WORDS * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.mtab, 0, size_t(16) * ctx->n_modules, s);
     if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.gcnt, 0, size_t(4) * ctx->n_modules, s);
+    if (e == hipSuccess) e = hipMemsetAsync(ev->ws + L.hsum, 0, size_t(16) * max_digis, s);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (ev->done_ev) hipEventDestroy(ev->done_ev);
@@ -885,10 +895,13 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
         if (e == hipSuccess) e = launch_hits(a, grid, s);
         if (e == hipSuccess && timed) e = hipEventRecord(ev->hits_tev[1], s);
     }
-    if (e == hipSuccess) e = hipEventRecord(ev->hits_ev, s);
+    // fused hits asked for on the event's own stream are complete with the event: its
+    // completion event serves, no event is recorded
+    ev->hits_done = (fused && s == ev->stream) ? (ev->batch ? ev->batch->done_ev : ev->done_ev) : ev->hits_ev;
+    if (e == hipSuccess && ev->hits_done == ev->hits_ev) e = hipEventRecord(ev->hits_ev, s);
     if (e == hipSuccess) {
         ev->hits_pending.fetch_add(1, std::memory_order_acq_rel);
-        completer_post(ctx, CK_HITS, ev, ev->hits_ev);
+        completer_post(ctx, CK_HITS, ev, ev->hits_done);
     }
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != hipSuccess) {
@@ -920,7 +933,7 @@ extern "C" int pxcl_hits_produce(pxcl_event* ev, pxcl_hits* out) {
     out->x = reinterpret_cast<const float*>(ev->ws + L.hit_x);
     out->y = reinterpret_cast<const float*>(ev->ws + L.hit_y);
     out->stream = ev->hits_stream;
-    out->done_event = ev->hits_ev;
+    out->done_event = ev->hits_done;
     out->device = ev->ctx->device;
     return ev->hits_status;
 }
@@ -1022,7 +1035,7 @@ extern "C" int pxcl_copy_to_host(pxcl_event* ev, void* stream, pxcl_host_cluster
     if (st == ST_INFLIGHT && s != ev->stream)
         e = hipStreamWaitEvent(s, ev->batch ? ev->batch->done_ev : ev->done_ev, 0);
     if (e == hipSuccess && want_hits && hst == ST_INFLIGHT && s != ev->hits_stream)
-        e = hipStreamWaitEvent(s, ev->hits_ev, 0);
+        e = hipStreamWaitEvent(s, ev->hits_done, 0);
     ev->copy_dst = dst;
     ev->copy_cb = cb;
     ev->copy_user = user;
@@ -1067,7 +1080,7 @@ extern "C" int pxcl_hits_wait(pxcl_event* ev) {
     const int st = ev->hstate.load(std::memory_order_acquire);
     if (st == ST_IDLE) return PXCL_E_INVAL;
     if (st == ST_INFLIGHT) {
-        if (hipEventSynchronize(ev->hits_ev) != hipSuccess) return PXCL_E_HIP;
+        if (hipEventSynchronize(ev->hits_done) != hipSuccess) return PXCL_E_HIP;
         while (ev->hstate.load(std::memory_order_acquire) != ST_DONE) std::this_thread::yield();
     }
     if (!t_in_callback)

@@ -59,6 +59,7 @@ int main(int argc, char** argv) {
         }
         if (!(h[10] & LF_FUSED)) reinterpret_cast<u32*>(ws[e] + L.ctl)[CTL_BIG] = 3;
         memset(ws[e] + L.gcnt, 0, size_t(4) * M);                          // what binding clears
+        memset(ws[e] + L.hsum, 0, size_t(16) * cap);
         hs[e] = static_cast<u32*>(aligned_alloc(64, HS_BYTES));
         memset(hs[e], 0, HS_BYTES);
         EventDesc& d = evs[e];
@@ -109,7 +110,7 @@ int main(int argc, char** argv) {
         memset(a.ctr, 0, 64);
     }
     if (stale_ticket) a.ctr[S_TICK] = 1000003u;
-    if (((a.flags & LF_GROUP) && launch_group(a, h[5], h[5], nullptr)) ||
+    if (((a.flags & LF_GROUP) && launch_group(a, h[5], h[5], h[5], nullptr)) ||
         (!(a.flags & (LF_FUSED | LF_NO_SEG)) && launch_segment(a, h[5], nullptr)) || launch_small(h[3], h[4], a, h[7], nullptr) ||
         (!(a.flags & LF_NO_BIG) && launch_big(a, h[6], h[6], nullptr)) || launch_compact(a, h[8], nullptr)) {
         fprintf(stderr, "launch failed\n");

@@ -265,3 +265,29 @@ def test_fused_hits_batch_mixed(px, graph):
         s.close()
     b.close()
     ctx.close()
+
+
+def test_fused_hits_repeated_on_one_slot(px):
+    """The hit sums are zero between launches (the compaction clears what it read, the
+    host clears the slot after an error): one slot runs several events with fused hits
+    in turn, one of them with an input error, and every event's hits are exact."""
+    import torch
+    evs = [synth.async_event(20), synth.batch_event(21), synth.async_event(22)]
+    bad = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in evs[1].items()}
+    bad["row"][3] = 170
+    seq = [evs[0], evs[1], bad, evs[0], evs[2], evs[1]]
+    ctx = px.Context(1856, 2000)
+    slot = px.Event(ctx, max(e["module"].size for e in evs))
+    s = torch.cuda.current_stream()
+    for i, ev in enumerate(seq):
+        px.acquire(slot, px.Digis.from_numpy(ev, "cuda", hits=True), s)
+        px.hits_enqueue(slot, s)
+        px.hits_wait(slot)
+        px.wait(slot)
+        ref = oracle.hits(ev, 2000)
+        compare(px.produce(slot).numpy(), ref, f"step {i}")
+        if ref["status"] == 0:
+            hn = px.hits_produce(slot).numpy()
+            assert np.array_equal(hn["x"], ref["x"]) and np.array_equal(hn["y"], ref["y"]), f"hits at step {i}"
+    slot.close()
+    ctx.close()
