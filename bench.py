@@ -85,8 +85,27 @@ def load_traffic(workload: str, kernel: str):
     return total if found else None
 
 
+def profile_kernel_us(workload: str):
+    """Mean kernel durations (us) from the committed rocprofv3 kernel-trace summary of
+    the workload, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"kernels_{workload}.txt")
+    if not os.path.exists(p):
+        return None
+    lines = open(p).read().splitlines()
+    if not any(l.startswith("kernel source sha256[:16]: ") and l.split(": ")[1].strip() == kernel_src_sha()
+               for l in lines):
+        return None
+    out = {}
+    for l in lines:
+        f = l.split()
+        if len(f) >= 6 and f[0] in ALL_SYMBOLS:
+            out[f[0]] = out.get(f[0], 0.0) + float(f[2])
+    return out
+
+
 def roofline(ctx, bytes_per_launch: float, workload: str):
-    """Roofline of the dominant kernel from the context's per-kernel hipEvent sums."""
+    """Roofline of the dominant kernel from the context's per-kernel hipEvent sums, and
+    the same figure from the committed kernel-trace summary of the same launches."""
     ms, cnt = ctx.timing(reset=True)
     avg = {k: (ms[i] / cnt[i] if cnt[i] else 0.0) for i, k in enumerate(KERNELS)}
     if not cnt[KERNELS.index("hits")]:
@@ -96,8 +115,11 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
     t = avg[dom] * 1e-3
     achieved = bytes_per_launch / t / 1e9 if t > 0 else 0.0
     pipe = sum(avg.values()) * 1e-3
+    parts = KERNEL_PARTS.get(dom, [KERNEL_SYMBOLS[dom]])
+    kt = profile_kernel_us(workload)
+    kt_us = sum(kt.get(x, 0.0) for x in parts) if kt else None
     return {
-        "bound": "hbm", "kernel": "+".join(KERNEL_PARTS.get(dom, [KERNEL_SYMBOLS[dom]])), "achieved": round(achieved, 2),
+        "bound": "hbm", "kernel": "+".join(parts), "achieved": round(achieved, 2),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": load_traffic(workload, dom),
         "algorithmic_bytes_per_launch": int(bytes_per_launch),
@@ -105,6 +127,8 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
         "timed_launches": int(max(cnt)),
         "pipeline_us": round(pipe * 1e6, 3),
         "pipeline_GBps": round(bytes_per_launch / pipe / 1e9, 2) if pipe > 0 else 0.0,
+        "kernel_trace_us": round(kt_us, 3) if kt_us else None,
+        "frac_kernel_trace": round(bytes_per_launch / (kt_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5) if kt_us else None,
     }
 
 
@@ -112,7 +136,7 @@ def profile_commands(workload: str) -> dict:
     """The rocprofv3 commands whose output --summarize-profiles reads (run from the
     repository root with the output directory DIR): the one-stream roofline launches
     of the workload with its kernel shape pinned."""
-    shape = {"stress": "512x1", "batch": "64x1", "async": "256x4", "hits": "256x4"}.get(workload, "256x1")
+    shape = {"stress": "512x1", "batch": "256x1", "async": "256x4", "hits": "256x4"}.get(workload, "256x1")
     b = f"python3 bench.py --workload {workload} --roofline-only --kernel-config {shape}"
     return {
         "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d DIR/kt_{workload} -o run -- {b}",
