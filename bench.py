@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the pixel-clustering path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|stress|batch|serve|async|plain|hits]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|stress|batch|serve|async|plain|hits|fusedhits]
 
 Default ("all"): one JSON line whose headline (``value``) is the high-pileup stress
 configuration, the largest one that runs on one GPU: batches of 16 events of ~320k
