@@ -576,23 +576,33 @@ def bench_serve(px, torch, args, evs):
                          seed=7, **common)
     sat = cal["events"] / cal["wall_s"]
     mean_b = float(np.mean([event_bytes(e["module"].size, 0) for e in evs]))
-    runs = []
-    for load in SERVE_LOADS:
-        torch.cuda.synchronize()
-        st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=load * sat,
-                                   n_requests=SERVE_REQUESTS, seed=11, **common)
-        rate = st["events"] / st["wall_s"]
-        runs.append({"load": load, "arrival_rate_hz": round(load * sat, 1), "value": round(rate, 2),
-                     "digis_per_s": round(st["digis"] / st["wall_s"], 1),
-                     "lat_p50_us": round(st["lat_p50_us"], 2), "lat_p99_us": round(st["lat_p99_us"], 2),
-                     "host_blocked_us_per_event": round(st["blocked_us_per_event"], 3),
-                     "cpu_tasks_per_s": round(st["cpu_tasks_per_s"], 1), "errors": st["errors"],
-                     "mean_events_per_launch": round(st["events"] / max(1, st["batches"]), 2),
-                     "stage_p50_us": [round(x, 1) for x in st["stage_p50_us"]],
-                     "stage_p99_us": [round(x, 1) for x in st["stage_p99_us"]],
-                     "cpu_tasks_per_s_idle": round(st["cpu_tasks_per_s_idle"], 1),
-                     "kept_up": bool(rate >= 0.95 * load * sat),
-                     "hbm_frac_whole_job": round(mean_b * rate / 1e9 / HBM_PEAK_GBS, 5)})
+
+    def sweep(**kw):
+        runs = []
+        for load in SERVE_LOADS:
+            torch.cuda.synchronize()
+            st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=load * sat,
+                                       n_requests=SERVE_REQUESTS, seed=11, **{**common, **kw})
+            rate = st["events"] / st["wall_s"]
+            runs.append({"load": load, "arrival_rate_hz": round(load * sat, 1), "value": round(rate, 2),
+                         "digis_per_s": round(st["digis"] / st["wall_s"], 1),
+                         "lat_p50_us": round(st["lat_p50_us"], 2), "lat_p99_us": round(st["lat_p99_us"], 2),
+                         "host_blocked_us_per_event": round(st["blocked_us_per_event"], 3),
+                         "cpu_tasks_per_s": round(st["cpu_tasks_per_s"], 1), "errors": st["errors"],
+                         "mean_events_per_launch": round(st["events"] / max(1, st["batches"]), 2),
+                         "stage_p50_us": [round(x, 1) for x in st["stage_p50_us"]],
+                         "stage_p99_us": [round(x, 1) for x in st["stage_p99_us"]],
+                         "cpu_tasks_per_s_idle": round(st["cpu_tasks_per_s_idle"], 1),
+                         "kept_up": bool(rate >= 0.95 * load * sat),
+                         "hbm_frac_whole_job": round(mean_b * rate / 1e9 / HBM_PEAK_GBS, 5)})
+        return runs
+
+    runs = sweep()
+    # The 16 busy CPU threads leave no core to the dispatcher, the completion thread and
+    # the runtime's own threads when the host has 16: the same sweep with as many CPU
+    # threads as leave four cores free shows the latency tails that this costs.
+    spare = cpu_threads() - 4
+    spare_runs = sweep(n_cpu_threads=spare) if 0 < spare < 16 else None
     for b in batches:
         b.close()
     shape = list(ctx.kernel_config())
@@ -602,6 +612,10 @@ def bench_serve(px, torch, args, evs):
         "value": mid["value"], "digis_per_s": mid["digis_per_s"], "lat_p50_us": mid["lat_p50_us"],
         "lat_p99_us": mid["lat_p99_us"], "host_blocked_us_per_event": mid["host_blocked_us_per_event"],
         "saturated_events_per_s": round(sat, 1), "runs": runs,
+        "with_four_cores_free": None if spare_runs is None else {
+            "cpu_threads": spare, "runs": spare_runs,
+            "note": "the same loads with fewer CPU threads, so that the dispatcher, completion and runtime "
+                    "threads have cores of their own (the host has %d)" % cpu_threads()},
         "config": {"workload": "serve: Poisson arrivals, 10k-200k digis/event, 16 GB admission budget, "
                                "continuous batching over 8 streams with at most 6 batches on the device, "
                                "16 CPU threads with 20 us synthetic tasks",

@@ -367,8 +367,11 @@ int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
  * [d_arena, d_arena + arena_bytes) is carved into at most n_slots event slots of
  * min(budget_bytes, arena_bytes) bytes in total, bound once, in size classes (powers
  * of two from 16,384 digis up to the largest request) shared out in proportion to the
- * requests that need each class; a request is admitted, in arrival order, when a slot
- * of its class is free, so admission neither allocates nor clears memory.  Every tick
+ * requests that need each class; requests are admitted in arrival order, each to a
+ * free slot of its class or else of the smallest larger class with one, and a request
+ * that finds none waits without holding back later requests that can be admitted
+ * (they can only take slots it cannot use); admission neither allocates nor clears
+ * memory.  Every tick
  * the admitted requests not yet launched go to the device as one batch on a free batch
  * object (continuous batching: batches on different streams overlap), at most
  * max_inflight of them on the device at once: while they run, arrivals accumulate, so

@@ -200,8 +200,8 @@ struct Request {
 // of up to cap[c] digis (powers of two from 16,384 up to the largest request).  The
 // slots of a class take a share of the slot count and of the memory budget in
 // proportion to how many requests need that class, at least one each.  Admission then
-// takes a free slot of the request's class: no allocation, binding or clearing happens
-// per request.
+// takes a free slot of the request's class (or of a larger one): no allocation, binding
+// or clearing happens per request.
 struct SlotPool {
     std::vector<u32> cap;                     // per class: capacity in digis
     std::vector<size_t> bytes;                // per class: workspace bytes
@@ -446,19 +446,33 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     while (S.done.load(std::memory_order_acquire) < o->n_requests && err_rc.load() == PXCL_OK) {
         const double now = us_since(t0, clk::now());
         while (next_arrival < o->n_requests && req[next_arrival].arrival_us <= now) arrived.push_back(next_arrival++);
-        {
+        if (!arrived.empty()) {
+            // In arrival order, a request takes a free slot of its class or else of the
+            // smallest larger class that has one.  One that finds none waits without
+            // holding back those behind it: every class it can use is empty, so a later
+            // request admitted now takes nothing it waits for, and a later one of its
+            // class or above waits too (blocked_from).
             std::lock_guard<std::mutex> g(amu);
-            while (!arrived.empty()) {                 // in arrival order
-                Request& q = req[arrived.front()];
-                auto& fr = P.free[q.cls];
-                if (fr.empty()) break;
-                q.slot = fr.back();
-                fr.pop_back();
-                q.admit_us = now;
-                P.in_use += P.bytes[q.cls];
-                P.peak = std::max(P.peak, P.in_use);
-                admitted.push_back(arrived.front());
+            const u32 ncls_ = u32(P.free.size());
+            u32 blocked_from = ncls_;
+            for (size_t i = 0, n = arrived.size(); i < n; ++i) {
+                const u32 ri = arrived.front();
                 arrived.pop_front();
+                Request& q = req[ri];
+                u32 c = q.cls;
+                if (c < blocked_from)
+                    while (c < ncls_ && P.free[c].empty()) ++c;
+                if (c >= blocked_from || c >= ncls_) {
+                    blocked_from = std::min(blocked_from, q.cls);
+                    arrived.push_back(ri);               // keeps its place among those waiting
+                    continue;
+                }
+                q.slot = P.free[c].back();
+                P.free[c].pop_back();
+                q.admit_us = now;
+                P.in_use += P.bytes[c];
+                P.peak = std::max(P.peak, P.in_use);
+                admitted.push_back(ri);
             }
         }
         u32 mask = S.batch_free_mask.load(std::memory_order_acquire);
