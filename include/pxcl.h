@@ -354,13 +354,19 @@ typedef struct {
  * t, t+n_threads, ... (mod pool_size), events_per_thread of them.  flags:
  * PXCL_RUN_BLOCKING: the thread instead waits with hipStreamSynchronize (the
  * contrast); PXCL_RUN_HITS: every event's hits are queued right behind it on the
- * same stream and produced with it. */
+ * same stream and produced with it.
+ * Verification mode: with d_results and result_offsets given (both NULL: off), event
+ * i of thread t (request r = t + i * n_threads, pool entry r mod pool_size) has its
+ * results copied to d_results + result_offsets[r] after its produce (int32 per-digi
+ * ids [n], then ids, charges, sizes [n_clusters each] at +4n, +8n, +12n bytes), and
+ * the thread waits for the copy before it reuses its event; that wait counts as
+ * blocked time.  result_offsets holds n_threads * events_per_thread entries. */
 #define PXCL_RUN_BLOCKING 1
 #define PXCL_RUN_HITS 2
 int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
                    uint32_t n_threads, const pxcl_digis* pool, uint32_t pool_size,
                    uint32_t events_per_thread, uint32_t cpu_task_ns, int flags,
-                   pxcl_run_stats* out);
+                   pxcl_run_stats* out, void* d_results, const uint64_t* result_offsets);
 
 /* Serving form: requests arrive as a Poisson process (rate_hz, seeded) and draw
  * their digis round-robin from `pool`.  At set-up the device arena

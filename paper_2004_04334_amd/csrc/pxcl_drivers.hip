@@ -87,7 +87,8 @@ void lower_priority() { (void)setpriority(PRIO_PROCESS, id_t(syscall(SYS_gettid)
 // ---------------------------------------------------------------------------
 extern "C" int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams, uint32_t n_threads,
                               const pxcl_digis* pool, uint32_t pool_size, uint32_t events_per_thread,
-                              uint32_t cpu_task_ns, int flags, pxcl_run_stats* out) {
+                              uint32_t cpu_task_ns, int flags, pxcl_run_stats* out, void* d_results,
+                              const uint64_t* result_offsets) {
     const bool blocking = (flags & PXCL_RUN_BLOCKING) != 0, with_hits = (flags & PXCL_RUN_HITS) != 0;
     if (!ctx || !evs || !streams || !pool || !out || n_threads == 0 || pool_size == 0) return PXCL_E_INVAL;
     std::vector<std::vector<double>> lat(n_threads);
@@ -148,6 +149,19 @@ extern "C" int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const
             }
             const auto p1 = clk::now();
             blocked[t] += us_since(p0, p1);
+            if (d_results && result_offsets && r == PXCL_OK) {   // verification mode: copy out, then reuse
+                u8* dst = static_cast<u8*>(d_results) + result_offsets[t + u64(i) * n_threads];
+                const size_t nb = size_t(res.n_digis) * 4, cb = size_t(res.n_clusters) * 4;
+                hipStream_t rs = static_cast<hipStream_t>(res.stream);
+                hipError_t ce = hipSuccess;
+                if (nb) ce = hipMemcpyAsync(dst, res.digi_cluster, nb, hipMemcpyDeviceToDevice, rs);
+                if (cb && ce == hipSuccess) ce = hipMemcpyAsync(dst + nb, res.id, cb, hipMemcpyDeviceToDevice, rs);
+                if (cb && ce == hipSuccess) ce = hipMemcpyAsync(dst + 2 * nb, res.charge, cb, hipMemcpyDeviceToDevice, rs);
+                if (cb && ce == hipSuccess) ce = hipMemcpyAsync(dst + 3 * nb, res.size, cb, hipMemcpyDeviceToDevice, rs);
+                if (ce == hipSuccess) ce = hipStreamSynchronize(rs);
+                if (ce != hipSuccess) { rc.store(PXCL_E_HIP); break; }
+                blocked[t] += us_since(p1, clk::now());
+            }
             if (r != PXCL_OK) ++errors[t];
             digis[t] += in.n;
             lat[t].push_back(us_since(t0, p1));

@@ -151,7 +151,7 @@ _SIGS = {
     "pxcl_run_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.POINTER(_Digis),
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
-                                      ctypes.POINTER(RunStats)]),
+                                      ctypes.POINTER(RunStats), ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "pxcl_serve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                   ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.c_uint32, ctypes.POINTER(_Digis), ctypes.c_uint32,
@@ -557,15 +557,24 @@ def autotune_load(ctx: Context, cache_path: str, mean_digis: int) -> bool:
 
 
 def run_async(ctx: Context, events: Sequence[Event], streams, pool: Sequence[Digis], events_per_thread: int,
-              cpu_task_ns: int = 0, blocking: bool = False, hits: bool = False) -> dict:
+              cpu_task_ns: int = 0, blocking: bool = False, hits: bool = False,
+              results: Optional[torch.Tensor] = None, result_offsets: Optional[Sequence[int]] = None) -> dict:
+    """Asynchronous form.  With ``results`` (a device uint8 tensor) and
+    ``result_offsets`` (one per event, request r = thread + i * threads) every event's
+    outputs are copied there (verification mode)."""
     n = len(events)
     evs = (ctypes.c_void_p * n)(*[e.handle.value for e in events])
     sts = (ctypes.c_void_p * n)(*[int(s.cuda_stream) for s in streams])
     ins = (_Digis * len(pool))(*[d.struct() for d in pool])
     st = RunStats()
+    n_req = n * int(events_per_thread)
+    if result_offsets is not None and len(result_offsets) != n_req:
+        raise ValueError(f"run_async: {len(result_offsets)} result offsets for {n_req} events")
     _check(lib().pxcl_run_async(ctx.handle, evs, sts, n, ins, len(pool), int(events_per_thread),
-                                int(cpu_task_ns), (1 if blocking else 0) | (2 if hits else 0), ctypes.byref(st)),
-           "run_async")
+                                int(cpu_task_ns), (1 if blocking else 0) | (2 if hits else 0), ctypes.byref(st),
+                                results.data_ptr() if results is not None else None,
+                                (ctypes.c_uint64 * n_req)(*result_offsets) if result_offsets is not None
+                                else None), "run_async")
     return st.as_dict()
 
 

@@ -235,6 +235,22 @@ def test_async_driver(px):
     assert st["events"] == 100 and st["errors"] == 0
     assert st["cpu_tasks"] > 0
     assert st["blocked_us_per_event"] < st["lat_p50_us"]
+    # every event of a run, copied out as it is produced (verification mode)
+    refs = [oracle.cluster_event(e, 2000) for e in pool_np]
+    sizes = [pool_np[r % len(pool_np)]["module"].size for r in range(100)]
+    offs = np.concatenate([[0], np.cumsum([16 * n for n in sizes])]).astype(np.int64)
+    results = torch.full((int(offs[-1]),), 0xFF, dtype=torch.uint8, device="cuda")
+    ver = px.run_async(ctx, slots, streams, pool, events_per_thread=25, cpu_task_ns=20000, results=results,
+                       result_offsets=offs[:-1].tolist())
+    assert ver["events"] == 100 and ver["errors"] == 0
+    host = results.cpu().numpy()
+    for r in range(100):
+        ref, n = refs[r % len(pool_np)], sizes[r]
+        k = ref["n_clusters"]
+        blob = host[offs[r]: offs[r] + 16 * n].view(np.int32)
+        got = {"status": 0, "n_clusters": k, "digi": blob[:n], "id": blob[n:n + k],
+               "charge": blob[2 * n:2 * n + k], "size": blob[3 * n:3 * n + k]}
+        compare(got, ref, f"async event {r} (thread {r % 4})")
     blk = px.run_async(ctx, slots, streams, pool, events_per_thread=10, blocking=True)
     assert blk["errors"] == 0 and blk["cpu_tasks"] == 0
     # each thread's last event is still readable and exact
