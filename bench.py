@@ -598,11 +598,6 @@ def bench_serve(px, torch, args, evs):
         return runs
 
     runs = sweep()
-    # The 16 busy CPU threads leave no core to the dispatcher, the completion thread and
-    # the runtime's own threads when the host has 16: the same sweep with as many CPU
-    # threads as leave four cores free shows the latency tails that this costs.
-    spare = cpu_threads() - 4
-    spare_runs = sweep(n_cpu_threads=spare) if 0 < spare < 16 else None
     for b in batches:
         b.close()
     shape = list(ctx.kernel_config())
@@ -612,17 +607,15 @@ def bench_serve(px, torch, args, evs):
         "value": mid["value"], "digis_per_s": mid["digis_per_s"], "lat_p50_us": mid["lat_p50_us"],
         "lat_p99_us": mid["lat_p99_us"], "host_blocked_us_per_event": mid["host_blocked_us_per_event"],
         "saturated_events_per_s": round(sat, 1), "runs": runs,
-        "with_four_cores_free": None if spare_runs is None else {
-            "cpu_threads": spare, "runs": spare_runs,
-            "note": "the same loads with fewer CPU threads, so that the dispatcher, completion and runtime "
-                    "threads have cores of their own (the host has %d)" % cpu_threads()},
         "config": {"workload": "serve: Poisson arrivals, 10k-200k digis/event, 16 GB admission budget, "
                                "continuous batching over 8 streams with at most 6 batches on the device, "
                                "16 CPU threads with 20 us synthetic tasks",
                    "requests_per_run": SERVE_REQUESTS, "kernel_config": shape,
                    "autotune_us": tuned, "value_is": "the run at 0.7 of the saturated rate",
                    "stages": "arrival->admission, admission->launch, launch->completion callback, "
-                             "callback->produce"},
+                             "callback->produce",
+                   "host_cpus": cpu_threads(),
+                   "placement": "dispatcher on the last core, CPU threads off the last two"},
     }
 
 

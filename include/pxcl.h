@@ -382,7 +382,11 @@ int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
  * object (continuous batching: batches on different streams overlap), at most
  * max_inflight of them on the device at once: while they run, arrivals accumulate, so
  * batches grow with the load instead of the latency.  n_cpu_threads
- * threads run synthetic CPU tasks (cpu_task_ns each) and the produce work.
+ * threads run synthetic CPU tasks (cpu_task_ns each) and the produce work, at a lower
+ * priority than the dispatcher; with at least four CPUs in the process's affinity set
+ * the dispatcher (the calling thread, its affinity restored on return) keeps the last
+ * CPU to itself and the CPU threads stay off the last two, which the completion
+ * thread and the runtime's threads then find free.
  * Latency = arrival -> produce returned.  h_pinned must hold n_slots event status
  * blocks (pxcl_event_pinned_bytes each).
  * Verification mode: with d_results and result_offsets given, the produce step also

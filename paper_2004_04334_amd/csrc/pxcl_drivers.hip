@@ -25,6 +25,8 @@
 #include <random>
 #include <sstream>
 #include <string>
+#include <pthread.h>
+#include <sched.h>
 #include <sys/prctl.h>
 #include <sys/resource.h>
 #include <sys/syscall.h>
@@ -79,6 +81,36 @@ std::atomic<u64> g_sink{0};   // keeps the CPU tasks' results alive
 // would otherwise wait for whole scheduler time slices (milliseconds).  Raising a
 // thread's niceness needs no privileges.
 void lower_priority() { (void)setpriority(PRIO_PROCESS, id_t(syscall(SYS_gettid)), 10); }
+
+// Cores of the serving form: with at least four CPUs in the process's affinity set,
+// the dispatcher (the calling thread) keeps the last one to itself and the CPU threads
+// stay off the last two, so that the dispatcher, the completion thread and the
+// runtime's own threads never wait behind busy CPU threads for a time slice; the CPU
+// threads share the other cores (with as many threads as cores the synthetic work is
+// bound by the cores anyway).
+struct CorePlan {
+    bool on = false;
+    cpu_set_t all, workers, dispatcher;
+};
+CorePlan plan_cores() {
+    CorePlan p;
+    CPU_ZERO(&p.all);
+    if (sched_getaffinity(0, sizeof(p.all), &p.all) != 0) return p;
+    std::vector<int> cpus;
+    for (int c = 0; c < CPU_SETSIZE; ++c)
+        if (CPU_ISSET(c, &p.all)) cpus.push_back(c);
+    if (cpus.size() < 4) return p;
+    CPU_ZERO(&p.workers);
+    CPU_ZERO(&p.dispatcher);
+    for (size_t i = 0; i + 2 < cpus.size(); ++i) CPU_SET(cpus[i], &p.workers);
+    CPU_SET(cpus.back(), &p.dispatcher);
+    p.on = true;
+    return p;
+}
+void place_worker(const CorePlan& p) {
+    if (p.on) (void)pthread_setaffinity_np(pthread_self(), sizeof(cpu_set_t), &p.workers);
+    lower_priority();
+}
 
 }  // namespace
 
@@ -353,6 +385,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         }
     }
 
+    const CorePlan cores = plan_cores();
     // the CPU threads' task rate with no requests (the reference for the rate while serving)
     double idle_rate = 0.0;
     if (o->cpu_task_ns) {
@@ -362,7 +395,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         const auto i0 = clk::now();
         for (u32 t = 0; t < nt; ++t)
             it.emplace_back([&, t] {
-                lower_priority();
+                place_worker(cores);
                 u64 k = 0;
                 while (us_since(i0, clk::now()) < 50000.0) {
                     g_sink.fetch_add(cpu_task(o->cpu_task_ns, k + t), std::memory_order_relaxed);
@@ -392,7 +425,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     // CPU threads: produce first, else a synthetic task
     auto cpu_worker = [&](u32 t) {
         hipSetDevice(dev);
-        lower_priority();
+        place_worker(cores);
         u64 local_tasks = 0;
         for (;;) {
             u32 r = 0xFFFFFFFFu;
@@ -453,6 +486,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     // granularity of every wait), and restored at the end.
     const int old_slack = prctl(PR_GET_TIMERSLACK, 0, 0, 0, 0);
     prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
+    if (cores.on) (void)sched_setaffinity(0, sizeof(cpu_set_t), &cores.dispatcher);
     std::deque<u32> arrived, admitted;
     u32 next_arrival = 0;
     std::vector<pxcl_event*> bev(MAXB);
@@ -537,6 +571,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         }
     }
     if (old_slack > 0) prctl(PR_SET_TIMERSLACK, u64(old_slack), 0, 0, 0);
+    if (cores.on) (void)sched_setaffinity(0, sizeof(cpu_set_t), &cores.all);
     stop.store(true);
     S.cv.notify_all();
     for (auto& x : th) x.join();
