@@ -31,6 +31,7 @@ ENTROPY = 2004_04334
 
 # configuration ids used in the seed's spawn key
 CFG_PLAIN, CFG_ASYNC, CFG_BATCH, CFG_SERVE, CFG_STRESS, CFG_TEST = 0, 1, 2, 3, 4, 9
+CFG_STRESS_ALL = 5   # the stress configuration with 10 % of all modules hot
 
 
 def rng_for(config_id: int, event_idx: int) -> np.random.Generator:
@@ -297,16 +298,17 @@ def serpentine(row_wise: bool):
     return np.concatenate(rr).astype(np.int64), np.concatenate(cc).astype(np.int64)
 
 
-def stress_event(event_idx: int, n_modules: int = N_MODULES_FULL):
+def stress_event(event_idx: int, n_modules: int = N_MODULES_FULL, n_hot: int = 16, config: int = CFG_STRESS):
     """Configuration 5: 160 active modules = 16 hot modules at 20 % occupancy with
     mean-40 clusters + 142 modules of the configuration-3 law + a module holding only
     a full-column track + a module holding only a serpentine (row-wise on even
-    events, column-wise on odd ones); about 310-330k digis."""
-    rng = rng_for(CFG_STRESS, event_idx)
-    chosen = rng.choice(n_modules, size=18, replace=False)
-    hot, adv = np.sort(chosen[:16]), chosen[16:]
+    events, column-wise on odd ones); about 310-330k digis.  With n_hot hot modules
+    instead of 16 (stress_all_event) the rest is drawn the same way."""
+    rng = rng_for(config, event_idx)
+    chosen = rng.choice(n_modules, size=n_hot + 2, replace=False)
+    hot, adv = np.sort(chosen[:n_hot]), chosen[n_hot:]
     hot_px = int(round(0.20 * PIXELS))
-    hcl, hnz = _split_10_to_1(np.full(16, hot_px))
+    hcl, hnz = _split_10_to_1(np.full(n_hot, hot_px))
     m1, r1, c1 = _fill_modules(rng, hot, hcl, hnz, 0.025)
     # 142 modules of the log-normal law (total drawn module by module)
     pool = np.setdiff1d(np.arange(n_modules), chosen)
@@ -324,6 +326,13 @@ def stress_event(event_idx: int, n_modules: int = N_MODULES_FULL):
     r = np.concatenate([r1, r2])
     c = np.concatenate([c1, c2])
     return _finish(rng, m, r, c, n_modules, extra=(m3, r3, c3))
+
+
+def stress_all_event(event_idx: int, n_modules: int = N_MODULES_FULL):
+    """The stress configuration read literally: 10 % of all modules (186 of 1,856) hot
+    at 20 % occupancy, plus the 142 sparse modules, the track and the serpentine; about
+    2.5 million digis (a maximum-size case)."""
+    return stress_event(event_idx, n_modules, n_hot=int(round(0.10 * n_modules)), config=CFG_STRESS_ALL)
 
 
 def from_pixels(module, row, col, adc=None, n_modules=None, seed=0, shuffle=True):

@@ -176,3 +176,21 @@ def test_slot_alternates_grouped_and_shuffled(px):
                 f"step {i}")
     slot.close()
     ctx.close()
+
+
+def test_all_modules_hot_stress_event(px):
+    """Maximum-size case: the stress configuration read literally (186 of 1,856 modules
+    hot at 20 % occupancy, ~2.5 million digis in one event) through the single-event
+    kernels, as a one-event batch replayed from a graph (segmentation kernel), and
+    shuffled (grouping kernels), bit-exact against the oracle."""
+    print("stress event with 10 % of all modules hot", flush=True)
+    ev = synth.stress_all_event(0)
+    assert ev["module"].size > 2_400_000
+    ref = oracle.cluster_event(ev, 2000)
+    assert ref["status"] == 0
+    ctx = px.Context(1856, 2000, 0)
+    compare(_run_alone(px, ctx, ev, any_order=False), ref, "alone")
+    compare(_run_batch(px, ctx, [ev], [False], True)[0], ref, "one-event batch, graph")
+    sh = _shuffled(ev, 90)
+    compare(_run_alone(px, ctx, sh), oracle.cluster_event(sh, 2000, any_order=True), "shuffled")
+    ctx.close()

@@ -58,6 +58,17 @@ def test_stress_shape():
     assert 33487 in np.bincount(ev["module"]).tolist()
 
 
+def test_stress_all_modules_hot_shape():
+    """The literal reading of the stress configuration: 10 % of the 1,856 modules hot."""
+    ev = synth.stress_all_event(0)
+    _valid(ev)
+    counts = np.bincount(ev["module"], minlength=1856)
+    assert (counts == 13312).sum() == 186
+    assert np.count_nonzero(counts) == 186 + 142 + 2
+    assert 33359 in counts.tolist() and 160 in counts.tolist()
+    assert 2_400_000 < ev["module"].size < 2_700_000
+
+
 def test_elongated_along_columns():
     # row steps are 3x likelier than column steps, so clusters extend more in rows
     ev = synth.plain_event(1, n_modules=4)
