@@ -121,9 +121,21 @@ typedef struct {
     uint32_t n;
     int32_t where;        /* PXCL_WHERE_HOST or PXCL_WHERE_DEVICE */
     uint32_t max_module_digis;
-    uint32_t flags;       /* PXCL_DIGIS_ANY_ORDER | PXCL_DIGIS_HITS, or 0 */
+    uint32_t flags;       /* PXCL_DIGIS_ANY_ORDER | PXCL_DIGIS_HITS | PXCL_DIGIS_DEFER_BIG, or 0 */
 } pxcl_digis;
 #define PXCL_DIGIS_ANY_ORDER 1u
+/* Deferred big-module kernels (single-event pxcl_acquire only; PXCL_E_INVAL in a
+ * batch): the launch holds no big-module kernels.  If the small-module kernel finds
+ * modules above its capacity it lists them and the compaction leaves the event
+ * unfinished; the completion thread then queues the big-module kernels and the
+ * compaction on the event's stream (a second launch, recording the completion event
+ * again) before the callback fires.  Events without such modules finish in the one
+ * launch, sparing the two big-module launches, which wait for whole compute units.
+ * The results are final only when the callback fires: work queued after the acquire
+ * on the same stream is not ordered after the second launch, and pxcl_hits_enqueue
+ * and pxcl_copy_to_host return PXCL_E_BUSY while the event is in flight.  With
+ * PXCL_DIGIS_HITS the hits are complete with the event, as without this flag. */
+#define PXCL_DIGIS_DEFER_BIG 4u
 /* Hits fused into the clustering (Figure 1's GPU chain goes from raw data to hits): the
  * clustering kernels add every kept digi's adc*col and adc*row to exact 64-bit sums of
  * its cluster, and the compaction writes each cluster's hit beside its record, so the

@@ -56,6 +56,10 @@ constexpr u32 HS_BYTES = HS_WORDS * 4;
 
 // Error bits (same values as PXCL_ERRBIT_*).
 constexpr u32 EB_RANGE = 1, EB_ORDER = 2, EB_DUP = 4, EB_INTERNAL = 8, EB_HINT = 16;
+// Not an error: a launch with LF_DEFER found modules above the small kernel's
+// capacity, listed them and left the compaction to a second launch (big-module
+// kernels, then the compaction), which the host queues.
+constexpr u32 EB_DEFER = 32;
 
 // Launch flags.
 constexpr u32 LF_NO_BIG = 1;     // the big-module kernel is not launched (size hint)
@@ -65,6 +69,9 @@ constexpr u32 LF_FUSED = 4;      // one event, no segmentation kernel: the small
 constexpr u32 LF_NO_SCRATCH = 8; // the scratch-mode kernel is not launched (size hint)
 constexpr u32 LF_GROUP = 16;     // some event is in any order: the grouping kernels run first
 constexpr u32 LF_NO_SEG = 32;    // no event is grouped by module: no segmentation kernel
+constexpr u32 LF_DEFER = 64;     // with LF_NO_BIG | LF_NO_SCRATCH: modules above the small
+                                 // kernel's capacity are listed as usual, and an event with
+                                 // any is not compacted but reported with EB_DEFER
 PXCL_HD constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
 // Event flags (EventDesc::flags).

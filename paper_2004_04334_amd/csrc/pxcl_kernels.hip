@@ -1295,14 +1295,16 @@ __global__ __launch_bounds__(WG) PXCL_WAVES_PER_EU(small_waves_per_simd<WG, MPW,
     };
     // A module larger than the group goes to the big-module list, or above BIG_RCAP
     // digis to the scratch-mode list (or, when that kernel is not launched, keeps
-    // nothing and flags the size hint).  Other units not clustered (absent modules,
+    // nothing and flags the size hint; with LF_DEFER it is listed all the same, for
+    // the second launch).  Other units not clustered (absent modules,
     // entries not of this launch) keep nothing: the segmentation kernel cleared the
     // kept counts, without it this kernel does.
     auto skip = [&](const EventDesc& Ev, const Item& Is) {
         const EvLayout L = ev_layout(Ev.cap, a.n_modules);
         u32* ctl = ws_ptr<u32>(Ev, L.ctl);
         const bool scr = Is.n > BIG_RCAP;
-        if (Is.n > G * K && !(a.flags & (scr ? (LF_NO_BIG | LF_NO_SCRATCH) : LF_NO_BIG))) {
+        const bool listed = (a.flags & LF_DEFER) || !(a.flags & (scr ? (LF_NO_BIG | LF_NO_SCRATCH) : LF_NO_BIG));
+        if (Is.n > G * K && listed) {
             const u32 r = atomicAdd(&ctl[scr ? CTL_SCR : CTL_BIG], 1u);
             if (r < a.n_modules) ws_ptr<u32>(Ev, scr ? L.scr : L.big)[r] = Is.mod;
             else atomicOr(&ctl[CTL_ERR], EB_INTERNAL);
@@ -1845,6 +1847,17 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
         const EvLayout L = ev_layout(E.cap, M);
         u32* ctl = ws_ptr<u32>(E, L.ctl);
         const u32* kept = ws_ptr<const u32>(E, L.kept);
+        if ((a.flags & LF_DEFER) && (ld_ag(ctl + CTL_BIG) | ld_ag(ctl + CTL_SCR)) != 0u) {
+            // modules wait for the big-module kernels of a second launch: nothing is
+            // compacted, the lists and error bits stay for it, the host learns why
+            if (b + 1 == nblk && part == 0 && lane == 0) {
+                u32* hs = E.hstat;
+                st_sys(&hs[HS_ERR], ctl[CTL_ERR] | EB_DEFER);
+                st_sys(&hs[HS_NCL], 0u);
+                st_sys(&hs[HS_EPOCH], E.epoch);
+            }
+            continue;
+        }
         const u32 m = b * C_BLK + lane;
         // an empty event's kept counts were never written: it has no clusters
         const bool live = E.n != 0 && m < M;

@@ -137,6 +137,12 @@ struct pxcl_event {
     u32 launches = 0;                 // for sampling launches to time
     u32 timed_flags = 0;              // launch flags of the timed launch (kernels it ran)
     EventDesc desc{};                 // the event as the kernels saw it (for the hits)
+    // a launch with the big-module kernels deferred (PXCL_DIGIS_DEFER_BIG): its
+    // arguments and grids for the second launch, and whether that is still possible
+    bool defer = false;
+    bool defer_first = false;         // the first launch's completion is pending
+    LaunchArgs defer_args{};
+    u32 defer_grid_b = 1, defer_grid_x = 1, defer_grid_c = 1;
     u32 slot = 0;                     // launch parity of the last launch
     bool dirty = false;               // a launch failed to queue or reported an error: clear
                                       // the control words, grouping counts and hit sums first
@@ -265,7 +271,7 @@ bool digis_ok(const pxcl_digis* in) {
     if (!in) return false;
     if (in->where != PXCL_WHERE_HOST && in->where != PXCL_WHERE_DEVICE) return false;
     if (in->n && (!in->module || !in->row || !in->col || !in->adc)) return false;
-    if (in->flags & ~(PXCL_DIGIS_ANY_ORDER | PXCL_DIGIS_HITS)) return false;
+    if (in->flags & ~(PXCL_DIGIS_ANY_ORDER | PXCL_DIGIS_HITS | PXCL_DIGIS_DEFER_BIG)) return false;
     return true;
 }
 
@@ -328,6 +334,7 @@ void finish_event_from_host_status(pxcl_event* ev) {
     const u32 tag = __atomic_load_n(&ev->hs[HS_EPOCH], __ATOMIC_ACQUIRE);
     u32 bits = hs[HS_ERR];
     if (tag != ev->epoch) bits |= EB_INTERNAL;       // status write-back missing
+    if (bits & EB_DEFER) bits = (bits & ~EB_DEFER) | (bits == EB_DEFER ? EB_INTERNAL : 0u);   // not finished
     ev->err_bits = bits;
     const u32 ncl = hs[HS_NCL];
     ev->ncl = ncl < ev->n ? ncl : ev->n;              // never more clusters than digis
@@ -341,8 +348,28 @@ void finish_event_from_host_status(pxcl_event* ev) {
 // the callback must not wait for the callback itself.
 thread_local int t_in_callback = 0;
 
-void event_complete(void* p) {
+// The second launch of an event whose big-module kernels were deferred: those
+// kernels and the compaction, on the event's stream, then its completion event again.
+bool relaunch_deferred(pxcl_event* ev) {
+    const LaunchArgs& a = ev->defer_args;
+    hipError_t e = launch_big(a, ev->defer_grid_b, ev->defer_grid_x, ev->stream);
+    if (e == hipSuccess) e = launch_compact(a, ev->defer_grid_c, ev->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev->done_ev, ev->stream);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e == hipSuccess;
+}
+
+// false: the event goes on (its deferred second launch is queued, its completion
+// event recorded again), true: it is complete and its callback has run.
+bool event_complete(void* p) {
     pxcl_event* ev = static_cast<pxcl_event*>(p);
+    if (ev->defer_first) {
+        ev->defer_first = false;
+        const u32 tag = __atomic_load_n(&ev->hs[HS_EPOCH], __ATOMIC_ACQUIRE);
+        const u32 bits = static_cast<volatile u32*>(ev->hs)[HS_ERR];
+        // modules above the small kernel's capacity and no input error: second launch
+        if (tag == ev->epoch && bits == EB_DEFER && relaunch_deferred(ev)) return false;
+    }
     finish_event_from_host_status(ev);
     pxcl_done_cb cb = ev->cb;
     void* user = ev->user;
@@ -354,6 +381,7 @@ void event_complete(void* p) {
         --t_in_callback;
     }
     ev->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
+    return true;
 }
 
 void batch_complete(void* p) {
@@ -666,10 +694,22 @@ extern "C" int pxcl_acquire(pxcl_event* ev, const pxcl_digis* in, void* stream, 
     // one event grouped by module: ranges by search, no segmentation kernel; in any
     // order: the grouping kernels build the module table instead
     a.flags |= any ? (LF_GROUP | LF_NO_SEG) : LF_FUSED;
+    // deferred big-module kernels: only if the small kernel lists a module for them
+    // does the completion thread queue them (and the compaction) in a second launch
+    ev->defer = (in->flags & PXCL_DIGIS_DEFER_BIG) != 0;
+    if (ev->defer) a.flags |= LF_NO_BIG | LF_NO_SCRATCH | LF_DEFER;
     hipError_t e = make_desc(ev, in, s, &a.single);
     ev->desc = a.single;
     const Grids g = grids_for(ctx, wg, mpw, in->n, in->n ? ctx->n_modules : 0u, 1, a.flags, false,
                               any ? in->n : 0u, any ? 1u : 0u);
+    ev->defer_first = ev->defer;
+    if (ev->defer) {
+        ev->defer_args = a;
+        ev->defer_args.flags &= ~(LF_NO_BIG | LF_NO_SCRATCH | LF_DEFER);
+        ev->defer_grid_b = g.b;
+        ev->defer_grid_x = g.x;
+        ev->defer_grid_c = g.c;
+    }
     if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? ev->tev : nullptr);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, s);
     if (e == hipSuccess) {
@@ -865,6 +905,7 @@ extern "C" int pxcl_hits_enqueue(pxcl_event* ev, void* stream, pxcl_done_cb cb, 
     if (!ev) return PXCL_E_INVAL;
     const int st = ev->state.load(std::memory_order_acquire);
     if (st == ST_IDLE) return PXCL_E_INVAL;                     // no event acquired
+    if (st == ST_INFLIGHT && ev->defer) return PXCL_E_BUSY;      // its results are final only at the callback
     if (!claim(ev->hstate)) return PXCL_E_BUSY;
     pxcl_ctx* ctx = ev->ctx;
     collect_hits_timing(ev);                                    // the previous hits are complete
@@ -1003,7 +1044,9 @@ static void completer_loop(pxcl_completer* c, int device) {
             mine[i] = mine.back();
             mine.pop_back();
             switch (p.kind) {
-                case CK_EVENT: event_complete(p.obj); break;
+                case CK_EVENT:
+                    if (!event_complete(p.obj)) mine.push_back(p);   // its second launch
+                    break;
                 case CK_BATCH: batch_complete(p.obj); break;
                 case CK_HITS: hits_complete(p.obj); break;
                 default: copy_complete(p.obj); break;
@@ -1019,6 +1062,7 @@ extern "C" int pxcl_copy_to_host(pxcl_event* ev, void* stream, pxcl_host_cluster
     if (!ev || !dst || !dst->id || !dst->charge || !dst->size) return PXCL_E_INVAL;
     const int st = ev->state.load(std::memory_order_acquire);
     if (st == ST_IDLE) return PXCL_E_INVAL;
+    if (st == ST_INFLIGHT && ev->defer) return PXCL_E_BUSY;     // its results are final only at the callback
     const bool want_hits = dst->x || dst->y;
     const int hst = ev->hstate.load(std::memory_order_acquire);
     if (want_hits && (!dst->x || !dst->y || hst == ST_IDLE)) return PXCL_E_INVAL;   // no hits queued
@@ -1211,6 +1255,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     if (k > b->max_events) return PXCL_E_CAPACITY;
     for (u32 i = 0; i < k; ++i) {
         if (!evs[i] || evs[i]->ctx != b->ctx || !digis_ok(&ins[i])) return PXCL_E_INVAL;
+        if (ins[i].flags & PXCL_DIGIS_DEFER_BIG) return PXCL_E_INVAL;   // single-event launches only
         if (ins[i].n > evs[i]->cap) return PXCL_E_CAPACITY;
         if (evs[i]->hstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
         if (evs[i]->cstate.load(std::memory_order_acquire) == ST_INFLIGHT) return PXCL_E_BUSY;
@@ -1260,6 +1305,7 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         ev->stream = s;
         ev->batch = b;
         ev->timed = false;
+        ev->defer = ev->defer_first = false;
         ev->status = PXCL_OK;
         __atomic_store_n(&ev->hs[HS_EPOCH], 0u, __ATOMIC_RELEASE);
         ev->hstate.store(ST_IDLE, std::memory_order_release);

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libpxcl.so")
 OK, E_INVAL, E_CAPACITY, E_BUSY, E_NOT_READY = 0, -1, -2, -3, -4
 E_DUP_PIXEL, E_RANGE, E_ORDER, E_HIP, E_INTERNAL, E_NOTFOUND, E_HINT = -5, -6, -7, -8, -10, -11, -12
 WHERE_HOST, WHERE_DEVICE = 0, 1
-DIGIS_ANY_ORDER, DIGIS_HITS = 1, 2
+DIGIS_ANY_ORDER, DIGIS_HITS, DIGIS_DEFER_BIG = 1, 2, 4
 BATCH_GRAPH = 1
 MAX_BATCH = 128
 ROWS, COLS, PIXELS_PER_MODULE = 160, 416, 66560
@@ -212,7 +212,9 @@ class Digis:
     non-decreasing module, or in any order with ``any_order`` (the library then
     groups them on the device).  Keep the object alive until the done callback.
     max_module_digis: an upper bound on the digis of any one module, or 0 (unknown);
-    a small bound lets the library skip its big-module kernel."""
+    a small bound lets the library skip its big-module kernel.  ``defer_big`` (single
+    acquire only): the big-module kernels run in a second launch, queued by the
+    library only if a module needs them; results are final at the callback."""
     module: torch.Tensor
     row: torch.Tensor
     col: torch.Tensor
@@ -220,6 +222,7 @@ class Digis:
     max_module_digis: int = 0
     any_order: bool = False
     hits: bool = False           # hits fused into the clustering
+    defer_big: bool = False      # big-module kernels only when needed, in a second launch
 
     @property
     def n(self) -> int:
@@ -238,11 +241,12 @@ class Digis:
                 raise ValueError("digis must all be on the device or all in pinned host memory")
         return _Digis(*(t.data_ptr() if self.n else None for t in ts), self.n, self.where,
                       int(self.max_module_digis),
-                      (DIGIS_ANY_ORDER if self.any_order else 0) | (DIGIS_HITS if self.hits else 0))
+                      (DIGIS_ANY_ORDER if self.any_order else 0) | (DIGIS_HITS if self.hits else 0) |
+                      (DIGIS_DEFER_BIG if self.defer_big else 0))
 
     @staticmethod
     def from_numpy(ev, device: str = "cuda", hint: bool = False, any_order: bool = False,
-                   hits: bool = False) -> "Digis":
+                   hits: bool = False, defer_big: bool = False) -> "Digis":
         """Copy a numpy event; with `hint`, the largest number of digis sharing a
         module id (a host-side count over the event) is passed as max_module_digis;
         with `any_order` the digis are flagged as being in any order."""
@@ -255,7 +259,7 @@ class Digis:
                 t = t.pin_memory()
             ts.append(t.contiguous())
         mx = int(np.bincount(ev["module"]).max()) if (hint and ev["module"].size) else 0
-        return Digis(*ts, max_module_digis=mx, any_order=any_order, hits=hits)
+        return Digis(*ts, max_module_digis=mx, any_order=any_order, hits=hits, defer_big=defer_big)
 
 
 @dataclass

@@ -36,7 +36,7 @@ def build(force: bool = False, sanitizer: str = "address") -> str:
 def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, grids=(2, 2, 2, 2), caps=None,
         header: bool = False, sanitizer: str = "address", no_big: bool = False, hits: bool = False,
         seg_wide: bool = False, fused: bool = False, stale_ticket: bool = False, any_order=None,
-        fused_hits: bool = False):
+        fused_hits: bool = False, defer: bool = False):
     """Cluster `events` (list of dicts of uint16 arrays) as one launch; returns a list
     of result dicts like the oracle's (status from the error bits).  With `header` the
     events are passed through a batch header even when there is only one; with
@@ -49,9 +49,14 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
     `any_order` (one bool per event) flags events whose digis are in any order: the
     grouping kernels run first, and segmentation only if some event is grouped.
     `fused_hits`: every event asks for hits fused into the clustering (no hits kernel;
-    the results carry "x" and "y")."""
+    the results carry "x" and "y").  `defer` (one event): the big-module kernels are
+    deferred, and run with a second compaction only when the first launch reports
+    modules for them; every result then carries "launches" (1 or 2)."""
     any_order = [False] * len(events) if any_order is None else list(any_order)
     lflags = int(no_big) | (int(seg_wide) << 1) | (int(fused) << 2) | (int(stale_ticket) << 31)
+    if defer:
+        assert len(events) == 1, "deferred big-module kernels: one event per launch"
+        lflags |= 1 | 8 | 64                                  # LF_NO_BIG, LF_NO_SCRATCH, LF_DEFER
     if any(any_order):
         lflags |= 16 | (32 if all(any_order) else 0)        # LF_GROUP, LF_NO_SEG
     exe = build(sanitizer=sanitizer)
@@ -74,7 +79,8 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
         if r.returncode != 0:
             raise RuntimeError(f"emulated kernels failed ({r.returncode}):\n{r.stderr[-4000:]}")
         raw = np.fromfile(fout, dtype=np.int32)
-    out, p = [], 0
+    launches = int(raw[0])
+    out, p = [], 1
     for ev in events:
         n = ev["module"].size
         err, ncl = int(np.uint32(raw[p])), int(raw[p + 1])
@@ -87,6 +93,8 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
         if hits or fused_hits:
             hx = raw[p:p + ncl].view(np.float32); p += ncl
             hy = raw[p:p + ncl].view(np.float32); p += ncl
+        if err & 32:                      # deferred and not finished: as the host reports it
+            err = (err & ~32) | (8 if err == 32 else 0)
         st = 0
         if err & 0x80000000:
             st = -10
@@ -101,7 +109,7 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
         elif err & 8:
             st = -10
         r = {"status": st, "err_bits": err, "n_clusters": ncl, "digi": digi.copy(), "id": cid.copy(),
-             "charge": chg.copy(), "size": siz.copy()}
+             "charge": chg.copy(), "size": siz.copy(), "launches": launches}
         if hits or fused_hits:
             r["x"], r["y"] = hx.copy(), hy.copy()
         out.append(r)

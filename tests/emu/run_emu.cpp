@@ -5,11 +5,14 @@
 // input:  u32 k, n_modules, cut, wg, mpw, grid_a, grid_b, grid_s, grid_c, header
 //         (1: the events go through a batch header even when k == 1), launch flags
 //         (LF_NO_BIG: the big-module kernel is not run; LF_SEG_WIDE: segmentation in
-//         wide chunks; LF_FUSED: no segmentation kernel; bit 31: the ticket counter
-//         starts non-zero), hits (1: run the hits kernel after the launch);
+//         wide chunks; LF_FUSED: no segmentation kernel; LF_DEFER with LF_NO_BIG |
+//         LF_NO_SCRATCH: big-module kernels deferred to a second launch, which is run
+//         when the first reports it (one event); bit 31: the ticket counter starts
+//         non-zero), hits (1: run the hits kernel after the launch);
 //         per event: u32 n, u32 cap, u32 flags (1: digis in any order), u16 module[n],
 //         row[n], col[n], adc[n]
-// output: per event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
+// output: u32 launches (2 when a deferred launch needed its second one), then per
+//         event: u32 err, u32 n_clusters, i32 digi[n], id[nc], charge[nc], size[nc]
 //         (with hits: then f32 x[nc], y[nc])
 #include "../../paper_2004_04334_amd/csrc/pxcl_kernels.hip"
 
@@ -116,11 +119,24 @@ int main(int argc, char** argv) {
         fprintf(stderr, "launch failed\n");
         return 3;
     }
+    // deferred big-module kernels (one event): the host's second launch when the first
+    // reported modules above the small kernel's capacity and no error
+    u32 passes = 1;
+    if ((a.flags & LF_DEFER) && hs[0][HS_EPOCH] == evs[0].epoch && hs[0][HS_ERR] == EB_DEFER) {
+        LaunchArgs a2 = a;
+        a2.flags &= ~(LF_NO_BIG | LF_NO_SCRATCH | LF_DEFER);
+        if (launch_big(a2, h[6], h[6], nullptr) || launch_compact(a2, h[8], nullptr)) {
+            fprintf(stderr, "second launch failed\n");
+            return 3;
+        }
+        passes = 2;
+    }
     if (h[11] == 1 && launch_hits(a, h[8], nullptr)) {
         fprintf(stderr, "hits launch failed\n");
         return 3;
     }
     FILE* o = fopen(argv[2], "wb");
+    fwrite(&passes, 4, 1, o);
     for (u32 e = 0; e < k; ++e) {
         const EvLayout L = ev_layout(evs[e].cap, M);
         const u32 err = hs[e][HS_ERR], ncl = std::min(hs[e][HS_NCL], evs[e].n);

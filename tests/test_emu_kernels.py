@@ -387,3 +387,37 @@ def test_fused_hits(emulator, sanitizer):
             ref = emulator.hits(ev, 2000, any_order=any_o)
             compare(r, ref, "fused hits")
             assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])
+
+
+@pytest.mark.parametrize("sanitizer", ["address", "thread"])
+def test_deferred_big_module_kernels(emulator, sanitizer):
+    """Big-module kernels deferred (one event): an event whose modules all fit the small
+    kernel finishes in one launch; one with register-mode and scratch-mode modules is
+    listed by the first launch, reported unfinished, and finished by the second (big
+    kernels, compaction), also in any order and with fused hits; an input error with a
+    big module present ends after the first launch with the error."""
+    small = synth.plain_event(3, n_modules=8)              # modules of ~733 digis: 256-thread groups hold them
+    r = emu.run([small], 8, wg=256, mpw=1, grids=(2, 2, 2, 2), fused=True, defer=True, sanitizer=sanitizer)
+    assert r[0]["launches"] == 1
+    compare(r[0], emulator.cluster_event(small, 2000), "no big module")
+    sr, sc = synth.serpentine(row_wise=False)
+    rng = np.random.default_rng(5)
+    d = rng.choice(160 * 416, size=6000, replace=False)
+    parts = [(sr, sc), (d % 160, d // 160), (np.arange(7), np.full(7, 9))]
+    m = np.concatenate([np.full(p[0].size, i) for i, p in enumerate(parts)])
+    big = synth.from_pixels(m, np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]),
+                            n_modules=3, seed=17)
+    r = emu.run([big], 3, wg=64, mpw=1, grids=(2, 2, 2, 2), fused=True, defer=True, sanitizer=sanitizer)
+    assert r[0]["launches"] == 2
+    compare(r[0], emulator.cluster_event(big, 2000), "big modules")
+    if sanitizer == "address":
+        sh = _shuffled(big, 8)
+        r = emu.run([sh], 3, wg=64, mpw=1, grids=(2, 2, 2, 2), any_order=[True], defer=True, fused_hits=True)
+        ref = emulator.hits(sh, 2000, any_order=True)
+        assert r[0]["launches"] == 2
+        compare(r[0], ref, "any order, fused hits")
+        assert np.array_equal(r[0]["x"], ref["x"]) and np.array_equal(r[0]["y"], ref["y"])
+        bad = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in big.items()}
+        bad["row"][-1] = 170
+        r = emu.run([bad], 3, wg=64, mpw=1, grids=(2, 2, 2, 2), fused=True, defer=True)
+        assert r[0]["launches"] == 1 and r[0]["status"] == emulator.cluster_event(bad, 2000)["status"] != 0
