@@ -314,6 +314,12 @@ int pxcl_batch_bind(pxcl_ctx* ctx, void* d_ws, size_t ws_bytes, void* h_pinned,
 int pxcl_batch_unbind(pxcl_batch* b);
 
 #define PXCL_BATCH_GRAPH 1u   /* replay a captured hipGraph of the per-batch pipeline */
+/* Deferred big-module kernels for a whole batch: as PXCL_DIGIS_DEFER_BIG for one event
+ * (the second launch, big-module kernels and the compaction of the events the first
+ * launch left unfinished, is queued by the completion thread before the callback, only
+ * if some event lists a module for them).  The events' results are final at the
+ * callback; their hits and copy calls return PXCL_E_BUSY until then. */
+#define PXCL_BATCH_DEFER_BIG 2u
 
 /* Enqueue k events (each bound to its own slot, none in flight) as one batch: one
  * set of persistent kernels processes every module of every event.  ins[i] are
@@ -396,9 +402,9 @@ int pxcl_run_async(pxcl_ctx* ctx, pxcl_event* const* evs, void* const* streams,
  * batches grow with the load instead of the latency.  n_cpu_threads
  * threads run synthetic CPU tasks (cpu_task_ns each) and the produce work, at a lower
  * priority than the dispatcher; with at least four CPUs in the process's affinity set
- * the dispatcher (the calling thread, its affinity restored on return) keeps the last
- * CPU to itself and the CPU threads stay off the last two, which the completion
- * thread and the runtime's threads then find free.
+ * the dispatcher (the calling thread) keeps the last CPU to itself, the context's
+ * completion thread the one before, and the CPU threads stay off both (both
+ * affinities are restored on return).
  * Latency = arrival -> produce returned.  h_pinned must hold n_slots event status
  * blocks (pxcl_event_pinned_bytes each).
  * Verification mode: with d_results and result_offsets given, the produce step also
@@ -413,7 +419,7 @@ typedef struct {
     uint32_t max_batch;          /* events per launch (<= each batch's capacity) */
     uint32_t n_cpu_threads;
     uint32_t cpu_task_ns;
-    uint32_t flags;              /* PXCL_BATCH_GRAPH */
+    uint32_t flags;              /* PXCL_BATCH_GRAPH | PXCL_BATCH_DEFER_BIG */
     uint64_t seed;
     uint32_t max_inflight;       /* batches on the device at once (0 = n_batches) */
     uint32_t batch_delay_us;     /* 0: a batch starts as soon as fewer than max_inflight are on

@@ -41,6 +41,7 @@ namespace pxcl {
 bool cluster_config_valid(u32 wg, u32 mpw);
 const std::string& ctx_arch(const pxcl_ctx* c);
 int ctx_device(const pxcl_ctx* c);
+void ctx_place_completer(pxcl_ctx* c, const void* cpus);
 }  // namespace pxcl
 
 using namespace pxcl;
@@ -83,14 +84,14 @@ std::atomic<u64> g_sink{0};   // keeps the CPU tasks' results alive
 void lower_priority() { (void)setpriority(PRIO_PROCESS, id_t(syscall(SYS_gettid)), 10); }
 
 // Cores of the serving form: with at least four CPUs in the process's affinity set,
-// the dispatcher (the calling thread) keeps the last one to itself and the CPU threads
-// stay off the last two, so that the dispatcher, the completion thread and the
-// runtime's own threads never wait behind busy CPU threads for a time slice; the CPU
-// threads share the other cores (with as many threads as cores the synthetic work is
-// bound by the cores anyway).
+// the dispatcher (the calling thread) keeps the last one to itself, the context's
+// completion thread the one before, and the CPU threads stay off both, so that the
+// dispatcher, the completion thread and the runtime's own threads never wait behind
+// busy CPU threads for a time slice; the CPU threads share the other cores (with as
+// many threads as cores the synthetic work is bound by the cores anyway).
 struct CorePlan {
     bool on = false;
-    cpu_set_t all, workers, dispatcher;
+    cpu_set_t all, workers, dispatcher, completer;
 };
 CorePlan plan_cores() {
     CorePlan p;
@@ -102,8 +103,10 @@ CorePlan plan_cores() {
     if (cpus.size() < 4) return p;
     CPU_ZERO(&p.workers);
     CPU_ZERO(&p.dispatcher);
+    CPU_ZERO(&p.completer);
     for (size_t i = 0; i + 2 < cpus.size(); ++i) CPU_SET(cpus[i], &p.workers);
     CPU_SET(cpus.back(), &p.dispatcher);
+    CPU_SET(cpus[cpus.size() - 2], &p.completer);
     p.on = true;
     return p;
 }
@@ -486,7 +489,10 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     // granularity of every wait), and restored at the end.
     const int old_slack = prctl(PR_GET_TIMERSLACK, 0, 0, 0, 0);
     prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
-    if (cores.on) (void)sched_setaffinity(0, sizeof(cpu_set_t), &cores.dispatcher);
+    if (cores.on) {
+        (void)sched_setaffinity(0, sizeof(cpu_set_t), &cores.dispatcher);
+        ctx_place_completer(ctx, &cores.completer);
+    }
     std::deque<u32> arrived, admitted;
     u32 next_arrival = 0;
     std::vector<pxcl_event*> bev(MAXB);
@@ -571,7 +577,10 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         }
     }
     if (old_slack > 0) prctl(PR_SET_TIMERSLACK, u64(old_slack), 0, 0, 0);
-    if (cores.on) (void)sched_setaffinity(0, sizeof(cpu_set_t), &cores.all);
+    if (cores.on) {
+        (void)sched_setaffinity(0, sizeof(cpu_set_t), &cores.all);
+        ctx_place_completer(ctx, nullptr);
+    }
     stop.store(true);
     S.cv.notify_all();
     for (auto& x : th) x.join();

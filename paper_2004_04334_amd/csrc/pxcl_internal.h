@@ -45,6 +45,8 @@ enum : u32 {
     CTL_SCR = 3,      // modules on the scratch-mode list
     CTL_PRESENT = 5,  // words 5-6: modules on the present-module list, one count per
                       // launch parity (EventDesc::slot); a launch clears the other one
+    CTL_DEFERRED = 7, // 1: a batch launch with LF_DEFER left this event to its second
+                      // launch (set by the compaction, cleared by segmentation or grouping)
     CTL_CTR = 8,      // launch counters when the event is launched on its own
     CTL_WORDS = 64
 };
@@ -72,6 +74,8 @@ constexpr u32 LF_NO_SEG = 32;    // no event is grouped by module: no segmentati
 constexpr u32 LF_DEFER = 64;     // with LF_NO_BIG | LF_NO_SCRATCH: modules above the small
                                  // kernel's capacity are listed as usual, and an event with
                                  // any is not compacted but reported with EB_DEFER
+constexpr u32 LF_SECOND = 128;   // the second launch of a deferred batch: the compaction
+                                 // takes only the events the first one left (CTL_DEFERRED)
 PXCL_HD constexpr u32 seg_chunk(u32 flags) { return A_WG * ((flags & LF_SEG_WIDE) ? A_PER_W : A_PER_N); }
 
 // Event flags (EventDesc::flags).

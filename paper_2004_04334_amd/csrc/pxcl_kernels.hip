@@ -523,6 +523,7 @@ __global__ __launch_bounds__(G_WG) void k_group_table(LaunchArgs a) {
             const u32 slot = E.slot & 1u;
             ctl[CTL_BIG] = 0u;
             ctl[CTL_SCR] = 0u;
+            ctl[CTL_DEFERRED] = 0u;
             ctl[CTL_PRESENT + slot] = pcarry;
             ctl[CTL_PRESENT + (slot ^ 1u)] = 0u;
         }
@@ -630,6 +631,7 @@ __global__ __launch_bounds__(A_WG) void k_segment(LaunchArgs a) {
             if (tid == 0) {
                 ctl[CTL_BIG] = 0u;
                 ctl[CTL_SCR] = 0u;
+                ctl[CTL_DEFERRED] = 0u;
                 ctl[CTL_PRESENT + (slot ^ 1u)] = 0u;   // for the next launch (the last one's is done)
             }
             u32* kept = ws_ptr<u32>(E, L.kept);
@@ -1851,6 +1853,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             // modules wait for the big-module kernels of a second launch: nothing is
             // compacted, the lists and error bits stay for it, the host learns why
             if (b + 1 == nblk && part == 0 && lane == 0) {
+                ctl[CTL_DEFERRED] = 1u;
                 u32* hs = E.hstat;
                 st_sys(&hs[HS_ERR], ctl[CTL_ERR] | EB_DEFER);
                 st_sys(&hs[HS_NCL], 0u);
@@ -1858,6 +1861,7 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             }
             continue;
         }
+        if ((a.flags & LF_SECOND) && ld_ag(ctl + CTL_DEFERRED) == 0u) continue;   // finished by the first launch
         const u32 m = b * C_BLK + lane;
         // an empty event's kept counts were never written: it has no clusters
         const bool live = E.n != 0 && m < M;

@@ -10,6 +10,8 @@
 // microseconds after the work ends, while a query of an event is a read of its
 // signal.  No device or pinned allocation happens after bind.
 #include <hip/hip_runtime.h>
+#include <pthread.h>
+#include <sched.h>
 
 #include <algorithm>
 #include <atomic>
@@ -183,9 +185,9 @@ struct pxcl_batch {
     hipEvent_t done_ev = nullptr;
     hipStream_t cap_stream = nullptr;
     // captured pipelines, one per combination of the launch flags that change it
-    // (LF_NO_BIG, LF_SEG_WIDE, LF_NO_SCRATCH, LF_GROUP, LF_NO_SEG), all for the kernel
-    // shape g_wg x g_mpw
-    static constexpr int N_GRAPHS = 32;
+    // (LF_NO_BIG, LF_SEG_WIDE, LF_NO_SCRATCH, LF_GROUP, LF_NO_SEG, LF_DEFER), all for
+    // the kernel shape g_wg x g_mpw
+    static constexpr int N_GRAPHS = 64;
     hipGraphExec_t gexec[N_GRAPHS] = {};
     hipGraph_t graph[N_GRAPHS] = {};
     u32 g_wg = 0, g_mpw = 0;
@@ -193,6 +195,12 @@ struct pxcl_batch {
     u32 timed_flags = 0;
     hipEvent_t tev[5] = {};
     bool timed = false;       // the launch in flight records per-kernel events
+    // deferred big-module kernels (PXCL_BATCH_DEFER_BIG): the second launch's
+    // arguments and grids, and whether the first launch's completion is pending
+    hipStream_t stream = nullptr;
+    bool defer_first = false;
+    LaunchArgs defer_args{};
+    u32 defer_grid_b = 1, defer_grid_x = 1, defer_grid_c = 1;
 };
 
 // ---------------------------------------------------------------------------
@@ -384,8 +392,29 @@ bool event_complete(void* p) {
     return true;
 }
 
-void batch_complete(void* p) {
+// The second launch of a batch whose big-module kernels were deferred.
+bool relaunch_deferred(pxcl_batch* b) {
+    const LaunchArgs& a = b->defer_args;
+    hipError_t e = launch_big(a, b->defer_grid_b, b->defer_grid_x, b->stream);
+    if (e == hipSuccess) e = launch_compact(a, b->defer_grid_c, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->done_ev, b->stream);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e == hipSuccess;
+}
+
+// false: the batch goes on (its deferred second launch is queued), true: complete.
+bool batch_complete(void* p) {
     pxcl_batch* b = static_cast<pxcl_batch*>(p);
+    if (b->defer_first) {
+        b->defer_first = false;
+        bool any = false;
+        for (u32 i = 0; i < b->k && !any; ++i) {
+            const pxcl_event* ev = b->evs[i];
+            any = __atomic_load_n(&ev->hs[HS_EPOCH], __ATOMIC_ACQUIRE) == ev->epoch &&
+                  (static_cast<volatile u32*>(ev->hs)[HS_ERR] & EB_DEFER) != 0;
+        }
+        if (any && relaunch_deferred(b)) return false;
+    }
     int32_t bst = PXCL_OK;
     for (u32 i = 0; i < b->k; ++i) {
         pxcl_event* ev = b->evs[i];
@@ -406,6 +435,7 @@ void batch_complete(void* p) {
         --t_in_callback;
     }
     for (u32 i = 0; i < k; ++i) evs[i]->cb_pending.fetch_sub(1, std::memory_order_acq_rel);
+    return true;
 }
 
 bool claim(std::atomic<int>& st) {
@@ -1047,7 +1077,9 @@ static void completer_loop(pxcl_completer* c, int device) {
                 case CK_EVENT:
                     if (!event_complete(p.obj)) mine.push_back(p);   // its second launch
                     break;
-                case CK_BATCH: batch_complete(p.obj); break;
+                case CK_BATCH:
+                    if (!batch_complete(p.obj)) mine.push_back(p);   // its second launch
+                    break;
                 case CK_HITS: hits_complete(p.obj); break;
                 default: copy_complete(p.obj); break;
             }
@@ -1189,7 +1221,7 @@ static void drop_graphs(pxcl_batch* b) {
 
 static u32 graph_slot(u32 flags) {
     return ((flags & LF_NO_BIG) ? 1u : 0u) | ((flags & LF_SEG_WIDE) ? 2u : 0u) | ((flags & LF_NO_SCRATCH) ? 4u : 0u) |
-           ((flags & LF_GROUP) ? 8u : 0u) | ((flags & LF_NO_SEG) ? 16u : 0u);
+           ((flags & LF_GROUP) ? 8u : 0u) | ((flags & LF_NO_SEG) ? 16u : 0u) | ((flags & LF_DEFER) ? 32u : 0u);
 }
 
 extern "C" int pxcl_batch_unbind(pxcl_batch* b) {
@@ -1305,7 +1337,8 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
         ev->stream = s;
         ev->batch = b;
         ev->timed = false;
-        ev->defer = ev->defer_first = false;
+        ev->defer = (flags & PXCL_BATCH_DEFER_BIG) != 0;       // results final at the callback
+        ev->defer_first = false;
         ev->status = PXCL_OK;
         __atomic_store_n(&ev->hs[HS_EPOCH], 0u, __ATOMIC_RELEASE);
         ev->hstate.store(ST_IDLE, std::memory_order_release);
@@ -1325,8 +1358,23 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
     // a captured graph replays with any input: its segmentation always takes wide
     // chunks (correct for any size), so batches of varying size share one graph
     lflags |= (flags & PXCL_BATCH_GRAPH) ? LF_SEG_WIDE : seg_flag(ctx, sorted_digis);
+    // deferred big-module kernels: a second launch (big-module kernels, compaction of
+    // the events the first one left) only if some event lists a module for them
+    b->defer_first = (flags & PXCL_BATCH_DEFER_BIG) != 0;
+    if (b->defer_first) lflags |= LF_NO_BIG | LF_NO_SCRATCH | LF_DEFER;
+    b->stream = s;
     if (e == hipSuccess) {
-        if (flags & PXCL_BATCH_GRAPH) {
+        const bool graph = (flags & PXCL_BATCH_GRAPH) != 0;
+        const Grids g = graph ? grids_for(ctx, wg, mpw, 0, 0, 0, lflags, true)
+                              : grids_for(ctx, wg, mpw, digis, present, k, lflags, false, any_digis, any_events);
+        if (b->defer_first) {
+            b->defer_args = batch_args(b, wg, mpw);
+            b->defer_args.flags = (lflags & ~(LF_NO_BIG | LF_NO_SCRATCH | LF_DEFER)) | LF_SECOND;
+            b->defer_grid_b = g.b;
+            b->defer_grid_x = g.x;
+            b->defer_grid_c = g.c;
+        }
+        if (graph) {
             hipGraphExec_t exec = nullptr;
             e = ensure_graph(b, wg, mpw, lflags, &exec);
             if (e == hipSuccess) e = hipGraphLaunch(exec, s);
@@ -1334,7 +1382,6 @@ extern "C" int pxcl_acquire_batch(pxcl_batch* b, pxcl_event* const* evs, const p
             LaunchArgs a = batch_args(b, wg, mpw);
             a.flags = lflags;
             e = hipMemcpyAsync(b->ws + BW_HDR, b->hp, header_bytes(k), hipMemcpyHostToDevice, s);
-            const Grids g = grids_for(ctx, wg, mpw, digis, present, k, lflags, false, any_digis, any_events);
             if (e == hipSuccess) e = launch_all(a, g, wg, mpw, s, timed ? b->tev : nullptr);
         }
     }
@@ -1401,6 +1448,18 @@ u32 event_n(const pxcl_event* ev) { return ev->n; }
 hipEvent_t batch_done_event(const pxcl_batch* b) { return b->done_ev; }
 const std::string& ctx_arch(const pxcl_ctx* c) { return c->arch; }
 int ctx_device(const pxcl_ctx* c) { return c->device; }
+// Restrict the context's completion thread to `cpus` (a cpu_set_t), or to every CPU of
+// the process's affinity set with nullptr.
+void ctx_place_completer(pxcl_ctx* c, const void* cpus) {
+    cpu_set_t all;
+    if (!cpus) {
+        CPU_ZERO(&all);
+        if (sched_getaffinity(0, sizeof(all), &all) != 0) return;
+        cpus = &all;
+    }
+    if (c->comp.th.joinable())
+        (void)pthread_setaffinity_np(c->comp.th.native_handle(), sizeof(cpu_set_t), static_cast<const cpu_set_t*>(cpus));
+}
 }  // namespace pxcl
 
 

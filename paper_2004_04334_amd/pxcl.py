@@ -27,6 +27,7 @@ E_DUP_PIXEL, E_RANGE, E_ORDER, E_HIP, E_INTERNAL, E_NOTFOUND, E_HINT = -5, -6, -
 WHERE_HOST, WHERE_DEVICE = 0, 1
 DIGIS_ANY_ORDER, DIGIS_HITS, DIGIS_DEFER_BIG = 1, 2, 4
 BATCH_GRAPH = 1
+BATCH_DEFER_BIG = 2
 MAX_BATCH = 128
 ROWS, COLS, PIXELS_PER_MODULE = 160, 416, 66560
 
@@ -521,15 +522,17 @@ class BatchInputs:
 
 
 def acquire_batch(batch: Batch, events, digis: Optional[Sequence[Digis]] = None, stream=None,
-                  flag: Optional[Flag] = None, graph: bool = False) -> None:
+                  flag: Optional[Flag] = None, graph: bool = False, defer_big: bool = False) -> None:
     """Launch a batch: `events` and `digis` are sequences of equal length, or `events`
-    is a BatchInputs (and `digis` None)."""
+    is a BatchInputs (and `digis` None); ``defer_big``: big-module kernels only in a
+    second launch, when some event needs them (results final at the callback)."""
     prepared = events if isinstance(events, BatchInputs) else BatchInputs(events, digis)
     k, evs, ins = prepared.k, prepared.evs, prepared.ins
     cb_ptr, user = (flag_cb_ptr(), ctypes.addressof(flag)) if flag is not None else (None, None)
     batch._keep = (prepared, flag)
     _check(lib().pxcl_acquire_batch(batch.handle, evs, ins, k, _stream_ptr(stream), cb_ptr, user,
-                                    BATCH_GRAPH if graph else 0), "acquire_batch")
+                                    (BATCH_GRAPH if graph else 0) | (BATCH_DEFER_BIG if defer_big else 0)),
+           "acquire_batch")
 
 
 def batch_query(batch: Batch) -> int:
@@ -586,7 +589,7 @@ def serve(ctx: Context, arena: torch.Tensor, pinned: torch.Tensor, batches: Sequ
           pool: Sequence[Digis], rate_hz: float, n_requests: int, budget_bytes: int, n_slots: int,
           max_batch: int, n_cpu_threads: int = 16, cpu_task_ns: int = 20000, graph: bool = True,
           seed: int = 1, results: Optional[torch.Tensor] = None, result_offsets: Optional[Sequence[int]] = None,
-          max_inflight: int = 0, batch_delay_us: int = 0):
+          max_inflight: int = 0, batch_delay_us: int = 0, defer_big: bool = False):
     """Serving form; returns (stats dict, per-request status, per-request n_clusters).
     With ``results`` (a device uint8 tensor) and ``result_offsets`` every request's
     outputs are copied there (verification mode)."""
@@ -595,7 +598,8 @@ def serve(ctx: Context, arena: torch.Tensor, pinned: torch.Tensor, batches: Sequ
     sts = (ctypes.c_void_p * nb)(*[int(s.cuda_stream) for s in streams])
     ins = (_Digis * len(pool))(*[d.struct() for d in pool])
     o = ServeOpts(float(rate_hz), int(n_requests), int(budget_bytes), int(n_slots), int(max_batch),
-                  int(n_cpu_threads), int(cpu_task_ns), BATCH_GRAPH if graph else 0, int(seed), int(max_inflight),
+                  int(n_cpu_threads), int(cpu_task_ns),
+                  (BATCH_GRAPH if graph else 0) | (BATCH_DEFER_BIG if defer_big else 0), int(seed), int(max_inflight),
                   int(batch_delay_us))
     st = RunStats()
     rs = (ctypes.c_int32 * n_requests)()

@@ -51,11 +51,12 @@ def run(events, n_modules: int, cut: int = 2000, wg: int = 256, mpw: int = 1, gr
     `fused_hits`: every event asks for hits fused into the clustering (no hits kernel;
     the results carry "x" and "y").  `defer` (one event): the big-module kernels are
     deferred, and run with a second compaction only when the first launch reports
-    modules for them; every result then carries "launches" (1 or 2)."""
+    modules for them (through a header: a batch, whose second compaction takes only
+    the events left unfinished); every result carries "launches" (1 or 2)."""
     any_order = [False] * len(events) if any_order is None else list(any_order)
     lflags = int(no_big) | (int(seg_wide) << 1) | (int(fused) << 2) | (int(stale_ticket) << 31)
     if defer:
-        assert len(events) == 1, "deferred big-module kernels: one event per launch"
+        assert len(events) == 1 or header, "deferred big-module kernels: one event, or a batch header"
         lflags |= 1 | 8 | 64                                  # LF_NO_BIG, LF_NO_SCRATCH, LF_DEFER
     if any(any_order):
         lflags |= 16 | (32 if all(any_order) else 0)        # LF_GROUP, LF_NO_SEG

@@ -119,12 +119,22 @@ int main(int argc, char** argv) {
         fprintf(stderr, "launch failed\n");
         return 3;
     }
-    // deferred big-module kernels (one event): the host's second launch when the first
-    // reported modules above the small kernel's capacity and no error
+    // deferred big-module kernels: the host's second launch when the first reported
+    // modules above the small kernel's capacity (one event: with no error; a batch: in
+    // any event, and then the compaction takes only the events left unfinished)
     u32 passes = 1;
-    if ((a.flags & LF_DEFER) && hs[0][HS_EPOCH] == evs[0].epoch && hs[0][HS_ERR] == EB_DEFER) {
+    bool second = false;
+    if (a.flags & LF_DEFER) {
+        if (a.hdr) {
+            for (u32 e = 0; e < k; ++e)
+                second |= hs[e][HS_EPOCH] == evs[e].epoch && (hs[e][HS_ERR] & EB_DEFER) != 0;
+        } else {
+            second = hs[0][HS_EPOCH] == evs[0].epoch && hs[0][HS_ERR] == EB_DEFER;
+        }
+    }
+    if (second) {
         LaunchArgs a2 = a;
-        a2.flags &= ~(LF_NO_BIG | LF_NO_SCRATCH | LF_DEFER);
+        a2.flags = (a.flags & ~(LF_NO_BIG | LF_NO_SCRATCH | LF_DEFER)) | (a.hdr ? LF_SECOND : 0u);
         if (launch_big(a2, h[6], h[6], nullptr) || launch_compact(a2, h[8], nullptr)) {
             fprintf(stderr, "second launch failed\n");
             return 3;

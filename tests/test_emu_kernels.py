@@ -421,3 +421,34 @@ def test_deferred_big_module_kernels(emulator, sanitizer):
         bad["row"][-1] = 170
         r = emu.run([bad], 3, wg=64, mpw=1, grids=(2, 2, 2, 2), fused=True, defer=True)
         assert r[0]["launches"] == 1 and r[0]["status"] == emulator.cluster_event(bad, 2000)["status"] != 0
+
+
+@pytest.mark.parametrize("sanitizer", ["address", "thread"])
+def test_deferred_big_module_kernels_in_a_batch(emulator, sanitizer):
+    """A batch with its big-module kernels deferred: events with and without modules
+    for them in one launch, fused hits on both kinds (an event finished by the first
+    launch must not be compacted again: its hit sums were consumed), an empty event;
+    the second launch compacts only the events the first left."""
+    sr, sc = synth.serpentine(row_wise=True)
+    rng = np.random.default_rng(9)
+    d = rng.choice(160 * 416, size=5000, replace=False)
+    parts = [(d % 160, d // 160), (sr, sc), (np.arange(9), np.full(9, 20))]
+    m = np.concatenate([np.full(p[0].size, i + 1) for i, p in enumerate(parts)])
+    big = dict(synth.from_pixels(m, np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]),
+                                 n_modules=6, seed=19), n_modules=6)
+    empty = {k: np.zeros(0, np.uint16) for k in ("module", "row", "col", "adc")}
+    evs = [dict(synth.plain_event(6, n_modules=6), n_modules=6), big, dict(empty, n_modules=6),
+           dict(synth.plain_event(7, n_modules=5), n_modules=6)]
+    caps = [max(1, e["module"].size) for e in evs]
+    res = emu.run(evs, 6, wg=256, mpw=1, grids=(2, 2, 2, 2), header=True, defer=True, fused_hits=True, caps=caps,
+                  sanitizer=sanitizer)
+    assert res[0]["launches"] == 2
+    for i, (r, e) in enumerate(zip(res, evs)):
+        ref = emulator.hits(e, 2000)
+        compare(r, ref, f"event {i}")
+        assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"]), f"hits of event {i}"
+    res = emu.run([evs[0], evs[3]], 6, wg=256, mpw=1, grids=(2, 2, 2, 2), header=True, defer=True,
+                  sanitizer=sanitizer)
+    assert res[0]["launches"] == 1
+    for i, (r, e) in enumerate(zip(res, [evs[0], evs[3]])):
+        compare(r, emulator.cluster_event(e, 2000), f"no big module, event {i}")

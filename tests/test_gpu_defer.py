@@ -146,3 +146,74 @@ def test_deferred_async_driver(px):
     for s in slots:
         s.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_deferred_batches(px, graph):
+    """Batches with their big-module kernels deferred: one whose events need none
+    (finished in one launch) and one mixing stress events (register and scratch mode)
+    with sparse ones, some in any order, some with fused hits."""
+    import torch
+    print(f"deferred batch, graph={graph}", flush=True)
+    ctx = px.Context(1856, 2000, 0)
+    mixes = [[synth.async_event(50 + i) for i in range(4)],
+             [synth.stress_event(5), synth.async_event(55), _shuffled(synth.batch_event(56), 3), synth.stress_event(6),
+              synth.batch_event(57)]]
+    for j, evs in enumerate(mixes):
+        anyo = [i == 2 for i in range(len(evs))]
+        hits = [i % 2 == 1 for i in range(len(evs))]
+        slots = [px.Event(ctx, e["module"].size) for e in evs]
+        digis = [px.Digis.from_numpy(e, "cuda", any_order=a, hits=h) for e, a, h in zip(evs, anyo, hits)]
+        b = px.Batch(ctx, len(evs))
+        for rep in range(2):                           # the second replays the captured graph
+            f = px.Flag()
+            px.acquire_batch(b, slots, digis, torch.cuda.current_stream(), flag=f, graph=graph, defer_big=True)
+            for s in slots:
+                px.wait(s)
+            while f.fired == 0:
+                pass
+            for i, (s, e, a, h) in enumerate(zip(slots, evs, anyo, hits)):
+                ref = oracle.hits(e, 2000, any_order=a) if h else oracle.cluster_event(e, 2000, any_order=a)
+                compare(px.produce(s).numpy(), ref, f"mix {j}, event {i}, launch {rep}")
+                if h:
+                    px.hits_enqueue(s, torch.cuda.current_stream())
+                    px.hits_wait(s)
+                    hh = px.hits_produce(s).numpy()
+                    assert np.array_equal(hh["x"], ref["x"]) and np.array_equal(hh["y"], ref["y"]), f"hits {j} {i}"
+        b.close()
+        for s in slots:
+            s.close()
+    ctx.close()
+
+
+def test_deferred_serving(px):
+    import torch
+    pool_np = [synth.serve_event(i) for i in range(8)] + [synth.stress_event(7)]
+    refs = [oracle.cluster_event(e, 2000) for e in pool_np]
+    ctx = px.Context(1856)
+    pool = [px.Digis.from_numpy(e, "cuda") for e in pool_np]
+    n_req = 90
+    arena = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    pinned = torch.empty(64 * 64, dtype=torch.uint8, pin_memory=True)
+    batches = [px.Batch(ctx, 16) for _ in range(3)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    sizes = [pool_np[r % len(pool_np)]["module"].size for r in range(n_req)]
+    offs = np.concatenate([[0], np.cumsum([16 * n for n in sizes])]).astype(np.int64)
+    results = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+    st, status, ncl = px.serve(ctx, arena, pinned, batches, streams, pool, rate_hz=20000.0, n_requests=n_req,
+                               budget_bytes=400 << 20, n_slots=64, max_batch=16, n_cpu_threads=4,
+                               cpu_task_ns=10000, graph=True, seed=4, results=results,
+                               result_offsets=offs[:-1].tolist(), max_inflight=2, defer_big=True)
+    assert st["errors"] == 0 and st["events"] == n_req
+    host = results.cpu().numpy()
+    for r in range(n_req):
+        ref = refs[r % len(pool_np)]
+        n, k = sizes[r], int(ncl[r])
+        assert status[r] == 0 and k == ref["n_clusters"]
+        blob = host[offs[r]: offs[r] + 16 * n].view(np.int32)
+        got = {"status": 0, "n_clusters": k, "digi": blob[:n], "id": blob[n:n + k],
+               "charge": blob[2 * n:2 * n + k], "size": blob[3 * n:3 * n + k]}
+        compare(got, ref, f"served request {r}")
+    for b in batches:
+        b.close()
+    ctx.close()
