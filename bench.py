@@ -597,7 +597,8 @@ def bench_serve(px, torch, args, evs):
                          "stage_p50_us": [round(x, 1) for x in st["stage_p50_us"]],
                          "stage_p99_us": [round(x, 1) for x in st["stage_p99_us"]],
                          "cpu_tasks_per_s_idle": round(st["cpu_tasks_per_s_idle"], 1),
-                         "kept_up": bool(rate >= 0.95 * load * sat),
+                         "offered_per_s": round(st["offered_per_s"], 1),
+                         "kept_up": bool(rate >= 0.95 * st["offered_per_s"]),
                          "hbm_frac_whole_job": round(mean_b * rate / 1e9 / HBM_PEAK_GBS, 5)})
         return runs
 

@@ -363,6 +363,7 @@ typedef struct {
     double stage_p50_us[4];
     double stage_p99_us[4];
     double cpu_tasks_per_s_idle; /* serving form: the same CPU threads' task rate with no requests */
+    double offered_per_s;        /* serving form: requests / time of the last arrival (the rate drawn) */
 } pxcl_run_stats;
 
 /* Asynchronous form: n_threads host threads, each owning evs[t] and stream

@@ -616,6 +616,8 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         out->stage_p99_us[k] = percentile(st, 0.99);
     }
     out->cpu_tasks_per_s_idle = idle_rate;
+    const double last_arrival_us = o->n_requests ? req[o->n_requests - 1].arrival_us : 0.0;
+    out->offered_per_s = last_arrival_us > 0 ? double(o->n_requests) / (last_arrival_us * 1e-6) : 0.0;
     return err_rc.load();
 }
 

@@ -84,7 +84,7 @@ class RunStats(ctypes.Structure):
                 ("cpu_tasks", ctypes.c_uint64), ("errors", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
                 ("peak_resident_bytes", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("stage_p50_us", ctypes.c_double * 4), ("stage_p99_us", ctypes.c_double * 4),
-                ("cpu_tasks_per_s_idle", ctypes.c_double)]
+                ("cpu_tasks_per_s_idle", ctypes.c_double), ("offered_per_s", ctypes.c_double)]
 
     def as_dict(self):
         out = {}
