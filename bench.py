@@ -51,6 +51,7 @@ SERVE_LOADS = (0.5, 0.7, 0.9)   # serving: offered load as fractions of the satu
 SERVE_REQUESTS = 10000          # requests per serving run (p99 over 10,000)
 SERVE_SLOTS = 1024              # serving: event slots at most (within the 16 GB budget)
 SERVE_INFLIGHT = 6              # serving: batches on the device at once (no batching delay)
+LLC_BYTES = 256 << 20           # last-level (Infinity) cache: one-event forms rotate more input than this
 N_STREAMS = 4                   # streams the batched workloads spread their launches over
 SUB_STEPS = {"batch": 200, "async": 2000, "plain": 2000}   # fixed step counts of the sub-records
 ROOFLINE_LAUNCHES = 32          # one-stream graph-free launches timed for the roofline
@@ -456,14 +457,22 @@ def bench_batch(px, torch, args, evs, steps, warmup, timed=True):
     return r
 
 
+def device_copies(evs) -> int:
+    """Copies of the events' inputs that together exceed the last-level cache, so that
+    a rotation over them reads its inputs from HBM."""
+    b = sum(8 * e["module"].size for e in evs)
+    return max(1, -(-int(1.25 * LLC_BYTES) // max(1, b)))
+
+
 def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda", hint=False, shape=None,
                 any_order=False, fused_hits=False, defer=False):
     """4 host threads, one event in flight each, synthetic 20 us CPU tasks while waiting;
     the rate is over the driver's own timed window (after its threads are ready)."""
     n_threads = 4
     ctx = px.Context(1856, 2000)
+    reps = device_copies(evs) if where == "cuda" else 1
     pool = [px.Digis.from_numpy(e, where, hint=hint, any_order=any_order, hits=fused_hits, defer_big=defer)
-            for e in evs]
+            for _ in range(reps) for e in evs]
     hits = hits or fused_hits
     cap = max(e["module"].size for e in evs)
     slots = [px.Event(ctx, cap) for _ in range(n_threads)]
@@ -487,7 +496,7 @@ def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda
                     best, best_rate = sh, rate
             ctx.set_kernel_config(*map(int, best.split("x")))
     kept = []
-    for d in pool:                       # one pass for the kept-cluster counts (bytes per event)
+    for d in pool[:len(evs)]:            # one pass for the kept-cluster counts (bytes per event)
         px.acquire(slots[0], d)
         px.wait(slots[0])
         kept.append(px.produce(slots[0]).n_clusters)
@@ -516,7 +525,8 @@ def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda
                                 ", hits queued behind every event" if hits else "") +
                                (", input in pinned host memory (PCIe copy per event)" if where == "pinned" else ""),
                    "mean_digis": int(np.mean([e["module"].size for e in evs])), "input": where,
-                   "size_hint": bool(hint), "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
+                   "device_copies": reps, "size_hint": bool(hint), "kernel_config": list(ctx.kernel_config()),
+                   "autotune_us": tuned},
         "roofline": rl,
     }
     for s in slots:
@@ -527,7 +537,8 @@ def bench_async(px, torch, args, evs, events_per_thread, hits=False, where="cuda
 
 def bench_plain(px, torch, args, evs, steps, defer=False, shape=None):
     ctx = px.Context(64, 2000)
-    pool = [px.Digis.from_numpy(e, "cuda", defer_big=defer) for e in evs]
+    reps = device_copies(evs)
+    pool = [px.Digis.from_numpy(e, "cuda", defer_big=defer) for _ in range(reps) for e in evs]
     slot = px.Event(ctx, max(e["module"].size for e in evs))
     stream = torch.cuda.Stream()
     tuned = None
@@ -536,7 +547,7 @@ def bench_plain(px, torch, args, evs, steps, defer=False, shape=None):
     else:
         tuned = tune(px, ctx, args, evs[:1], [px.Digis.from_numpy(evs[0], "cuda")])
     kept = []
-    for d in pool:
+    for d in pool[:len(evs)]:
         px.acquire(slot, d)
         px.wait(slot)
         kept.append(px.produce(slot).n_clusters)
@@ -557,7 +568,7 @@ def bench_plain(px, torch, args, evs, steps, defer=False, shape=None):
         "host_blocked_us_per_event": st["blocked_us_per_event"], "errors": st["errors"],
         "hbm_frac_whole_job": round(b_mean * rate / 1e9 / HBM_PEAK_GBS, 5),
         "config": {"workload": "plain: 64 modules x 160x416, 46,912 digis/event, one event per synchronous launch",
-                   "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
+                   "device_copies": reps, "kernel_config": list(ctx.kernel_config()), "autotune_us": tuned},
         "roofline": roofline(ctx, b_mean, "plain"),
     }
     slot.close()
