@@ -576,6 +576,9 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
                 std::this_thread::sleep_for(std::chrono::nanoseconds(u64(wait * 1000.0)));
         }
     }
+    // the requests are served: the run ends here, not when the CPU threads (which may be
+    // waiting for a time slice) have noticed the stop
+    const auto t1 = clk::now();
     if (old_slack > 0) prctl(PR_SET_TIMERSLACK, u64(old_slack), 0, 0, 0);
     if (cores.on) {
         (void)sched_setaffinity(0, sizeof(cpu_set_t), &cores.all);
@@ -584,7 +587,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     stop.store(true);
     S.cv.notify_all();
     for (auto& x : th) x.join();
-    const auto t1 = clk::now();
+    const auto t_join = clk::now();
     for (u32 b = 0; b < n_batches; ++b) hipStreamSynchronize(static_cast<hipStream_t>(streams[b]));
     for (auto* e : slot_ev) pxcl_event_unbind(e);
 
@@ -600,7 +603,8 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     out->lat_max_us = l.empty() ? 0 : l.back();
     out->blocked_us_per_event = double(blocked_ns.load()) * 1e-3 / double(o->n_requests);
     out->cpu_tasks = tasks.load();
-    out->cpu_tasks_per_s = out->wall_s > 0 ? double(out->cpu_tasks) / out->wall_s : 0;
+    const double cpu_s = us_since(t0, t_join) * 1e-6;      // the CPU threads ran until they stopped
+    out->cpu_tasks_per_s = cpu_s > 0 ? double(out->cpu_tasks) / cpu_s : 0;
     out->errors = errors.load();
     out->max_inflight = max_inflight.load();
     out->peak_resident_bytes = P.peak;
