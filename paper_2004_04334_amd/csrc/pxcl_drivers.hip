@@ -275,10 +275,15 @@ struct BatchCtx {
     u32 req[MAXB];
 };
 
+// Hand-overs between the serving threads take no lock: a CPU thread (lower priority,
+// more threads than its cores) preempted while holding a lock would stall the
+// dispatcher or the completion thread for a time slice (milliseconds).  Every request
+// passes each queue once, so each is an array of n_requests places filled in order.
 struct ServeState {
-    std::mutex mu;
-    std::condition_variable cv;
-    std::deque<u32> produce_q;          // requests whose batch completed
+    u32* produce_q = nullptr;           // requests whose batch completed (one producer:
+    u32 produce_fill = 0;               // the completion thread, which alone uses fill)
+    std::atomic<u32> produce_tail{0};   // places published
+    std::atomic<u32> produce_head{0};   // places taken by the CPU threads
     std::atomic<u32> done{0};
     std::atomic<u32> batch_free_mask{0};
     Request* req = nullptr;
@@ -291,15 +296,12 @@ void serve_batch_done(void* user, int32_t) {
     ServeState* S = bc->S;
     S->dispatch_wake.store(1, std::memory_order_release);
     const double now = us_since(S->t0, clk::now());
-    {
-        std::lock_guard<std::mutex> g(S->mu);
-        for (u32 i = 0; i < bc->k; ++i) {
-            S->req[bc->req[i]].done_us = now;
-            S->produce_q.push_back(bc->req[i]);
-        }
+    for (u32 i = 0; i < bc->k; ++i) {
+        S->req[bc->req[i]].done_us = now;
+        S->produce_q[S->produce_fill++] = bc->req[i];
     }
+    S->produce_tail.store(S->produce_fill, std::memory_order_release);
     S->batch_free_mask.fetch_or(1u << bc->bi, std::memory_order_acq_rel);
-    S->cv.notify_one();
 }
 
 }  // namespace
@@ -410,9 +412,16 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         idle_rate = double(n_idle.load()) / (us_since(i0, clk::now()) * 1e-6);
     }
 
-    std::mutex amu;                       // free slots
     ServeState S;
+    std::vector<u32> produce_q(o->n_requests);
+    S.produce_q = produce_q.data();
     S.req = req.data();
+    // slots released by the CPU threads: a thread claims a place, then writes slot + 1
+    // there; the dispatcher, which alone owns the free lists, takes them in order
+    std::vector<std::atomic<u32>> released(o->n_requests);
+    for (auto& x : released) x.store(0u, std::memory_order_relaxed);
+    std::atomic<u32> released_tail{0};
+    u32 released_head = 0;
     S.batch_free_mask.store((n_batches >= 32 ? 0xFFFFFFFFu : ((1u << n_batches) - 1u)));
     std::vector<BatchCtx> bctx(n_batches);
     for (u32 b = 0; b < n_batches; ++b) { bctx[b].S = &S; bctx[b].bi = b; bctx[b].k = 0; }
@@ -422,7 +431,7 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     std::atomic<bool> stop{false};
     std::atomic<int> err_rc{PXCL_OK};
     // the arrival clock starts once the CPU threads exist (they read it only for
-    // requests, which come after it starts; the hand-over goes through S.mu)
+    // requests, which come after it starts, through the completion thread's hand-over)
     clk::time_point t0;
 
     // CPU threads: produce first, else a synthetic task
@@ -432,11 +441,16 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         u64 local_tasks = 0;
         for (;;) {
             u32 r = 0xFFFFFFFFu;
-            {
-                std::unique_lock<std::mutex> g(S.mu);
-                if (!S.produce_q.empty()) { r = S.produce_q.front(); S.produce_q.pop_front(); }
-                else if (stop.load()) break;
-                else if (!o->cpu_task_ns) S.cv.wait_for(g, std::chrono::microseconds(50));
+            for (u32 h = S.produce_head.load(std::memory_order_acquire);
+                 h < S.produce_tail.load(std::memory_order_acquire);) {
+                if (S.produce_head.compare_exchange_weak(h, h + 1, std::memory_order_acq_rel)) {
+                    r = S.produce_q[h];
+                    break;
+                }
+            }
+            if (r == 0xFFFFFFFFu) {
+                if (stop.load()) break;
+                if (!o->cpu_task_ns) std::this_thread::sleep_for(std::chrono::microseconds(20));
             }
             if (r != 0xFFFFFFFFu) {
                 Request& q = req[r];
@@ -464,11 +478,8 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
                 if (st != PXCL_OK) errors.fetch_add(1);
                 if (request_status) request_status[r] = st;
                 if (request_nclusters) request_nclusters[r] = res.n_clusters;
-                {
-                    std::lock_guard<std::mutex> g(amu);
-                    P.free[P.slot_cls[q.slot]].push_back(q.slot);
-                    P.in_use -= P.bytes[P.slot_cls[q.slot]];
-                }
+                released[released_tail.fetch_add(1, std::memory_order_acq_rel)].store(q.slot + 1u,
+                                                                                   std::memory_order_release);
                 inflight.fetch_sub(1);
                 S.done.fetch_add(1, std::memory_order_acq_rel);
             } else if (o->cpu_task_ns) {
@@ -500,13 +511,17 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
     while (S.done.load(std::memory_order_acquire) < o->n_requests && err_rc.load() == PXCL_OK) {
         const double now = us_since(t0, clk::now());
         while (next_arrival < o->n_requests && req[next_arrival].arrival_us <= now) arrived.push_back(next_arrival++);
+        for (u32 v; released_head < o->n_requests &&
+                    (v = released[released_head].load(std::memory_order_acquire)) != 0u; ++released_head) {
+            P.free[P.slot_cls[v - 1u]].push_back(v - 1u);      // a slot free again
+            P.in_use -= P.bytes[P.slot_cls[v - 1u]];
+        }
         if (!arrived.empty()) {
             // In arrival order, a request takes a free slot of its class or else of the
             // smallest larger class that has one.  One that finds none waits without
             // holding back those behind it: every class it can use is empty, so a later
             // request admitted now takes nothing it waits for, and a later one of its
             // class or above waits too (blocked_from).
-            std::lock_guard<std::mutex> g(amu);
             const u32 ncls_ = u32(P.free.size());
             u32 blocked_from = ncls_;
             for (size_t i = 0, n = arrived.size(); i < n; ++i) {
@@ -585,7 +600,6 @@ extern "C" int pxcl_serve(pxcl_ctx* ctx, void* d_arena, size_t arena_bytes, void
         ctx_place_completer(ctx, nullptr);
     }
     stop.store(true);
-    S.cv.notify_all();
     for (auto& x : th) x.join();
     const auto t_join = clk::now();
     for (u32 b = 0; b < n_batches; ++b) hipStreamSynchronize(static_cast<hipStream_t>(streams[b]));
