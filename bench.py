@@ -70,39 +70,36 @@ def kernel_src_sha() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(workload: str, kernel: str, shape=None):
+def load_traffic(workload: str, kernel: str, shape):
     """HBM traffic per launch from the committed rocprofv3 counter summaries of the
-    kernels behind a timing slot, if they were taken on the current kernel source (and,
-    given `shape`, with that small-kernel shape; a kernel without a summary did not run
-    in that workload)."""
+    kernels behind a timing slot at the run's small-kernel shape, if they were taken on
+    the current kernel source (a kernel without a summary did not run in that
+    workload; no summary at all: None)."""
     total, found = 0, False
+    if not os.path.exists(os.path.join(ROOT, "profiles", f"kernels_{profile_tag(workload, shape)}.txt")):
+        return None
     for sym in KERNEL_PARTS.get(kernel, [KERNEL_SYMBOLS[kernel]]):
-        p = os.path.join(ROOT, "profiles", f"pmc_{sym}_{workload}.json")
+        p = os.path.join(ROOT, "profiles", f"pmc_{sym}_{profile_tag(workload, shape)}.json")
         if not os.path.exists(p):
             continue
         d = json.load(open(p))
         if d.get("kernel_src_sha") != kernel_src_sha():
-            return None
-        if shape is not None and f"--kernel-config {shape[0]}x{shape[1]}" not in d.get("commands", {}).get("fetch", ""):
             return None
         total += d.get("traffic_bytes_per_launch", 0)
         found = True
     return total if found else None
 
 
-def profile_kernel_us(workload: str, shape=None):
+def profile_kernel_us(workload: str, shape):
     """Mean kernel durations (us) from the committed rocprofv3 kernel-trace summary of
-    the workload, if it was taken on the current kernel source (and, given `shape`,
-    with that small-kernel shape)."""
-    p = os.path.join(ROOT, "profiles", f"kernels_{workload}.txt")
+    the workload at the run's small-kernel shape, if it was taken on the current kernel
+    source."""
+    p = os.path.join(ROOT, "profiles", f"kernels_{profile_tag(workload, shape)}.txt")
     if not os.path.exists(p):
         return None
     lines = open(p).read().splitlines()
     if not any(l.startswith("kernel source sha256[:16]: ") and l.split(": ")[1].strip() == kernel_src_sha()
                for l in lines):
-        return None
-    if shape is not None and not any(l.startswith("command: ") and f"--kernel-config {shape[0]}x{shape[1]}" in l
-                                     for l in lines):
         return None
     out = {}
     for l in lines:
@@ -141,16 +138,20 @@ def roofline(ctx, bytes_per_launch: float, workload: str):
     }
 
 
-def profile_commands(workload: str) -> dict:
+def profile_tag(workload: str, shape) -> str:
+    return f"{workload}_{shape[0]}x{shape[1]}"
+
+
+def profile_commands(workload: str, shape) -> dict:
     """The rocprofv3 commands whose output --summarize-profiles reads (run from the
     repository root with the output directory DIR): the one-stream roofline launches
-    of the workload with its kernel shape pinned."""
-    shape = {"stress": "256x1", "batch": "256x1", "async": "64x1", "hits": "64x1"}.get(workload, "256x1")
-    b = f"python3 bench.py --workload {workload} --roofline-only --kernel-config {shape}"
+    of the workload with the small kernel's shape pinned."""
+    tag = profile_tag(workload, shape)
+    b = f"python3 bench.py --workload {workload} --roofline-only --kernel-config {shape[0]}x{shape[1]}"
     return {
-        "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d DIR/kt_{workload} -o run -- {b}",
-        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_{workload} -o run -- {b}",
-        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_{workload} -o run -- {b}",
+        "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d DIR/kt_{tag} -o run -- {b}",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_{tag} -o run -- {b}",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_{tag} -o run -- {b}",
         "copy_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch_copy -o run -- "
                       "python3 bench.py --copy-calibration 5",
         "copy_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write_copy -o run -- "
@@ -258,25 +259,27 @@ def _short(name: str) -> str:
     return name
 
 
-def summarize_profiles(prof: str, workload: str, command: dict):
-    """Turn rocprofv3 output of one workload into the committed summaries:
-    profiles/kernels_<workload>.txt (kernel-trace statistics) and
-    profiles/pmc_<kernel>_<workload>.json per kernel (FETCH_SIZE and WRITE_SIZE per
-    dispatch, in KiB, scaled to bytes by the same counters on a device copy of
-    COPY_BYTES, whose true traffic is COPY_BYTES read and COPY_BYTES written)."""
+def summarize_profiles(prof: str, workload: str, shape, command: dict):
+    """Turn rocprofv3 output of one workload at one small-kernel shape into the
+    committed summaries: profiles/kernels_<workload>_<shape>.txt (kernel-trace
+    statistics) and profiles/pmc_<kernel>_<workload>_<shape>.json per kernel
+    (FETCH_SIZE and WRITE_SIZE per dispatch, in KiB, scaled to bytes by the same
+    counters on a device copy of COPY_BYTES, whose true traffic is COPY_BYTES read and
+    COPY_BYTES written)."""
     out_dir = os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
-    stats = _read_csv(os.path.join(prof, f"kt_{workload}", "run_kernel_stats.csv"))
+    tag = profile_tag(workload, shape)
+    stats = _read_csv(os.path.join(prof, f"kt_{tag}", "run_kernel_stats.csv"))
     lines = [f"rocprofv3 kernel-trace statistics, workload {workload} (one-stream roofline launches)",
              f"command: {command['kt']}", f"kernel source sha256[:16]: {kernel_src_sha()}", "",
              f"{'kernel':<40}{'calls':>8}{'avg_us':>10}{'min_us':>10}{'max_us':>10}{'pct':>8}"]
     for r in stats:
         lines.append(f"{_short(r['Name'])[:39]:<40}{int(r['Calls']):>8}{float(r['AverageNs']) / 1e3:>10.2f}"
                      f"{float(r['MinNs']) / 1e3:>10.2f}{float(r['MaxNs']) / 1e3:>10.2f}{float(r['Percentage']):>8.2f}")
-    open(os.path.join(out_dir, f"kernels_{workload}.txt"), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(out_dir, f"kernels_{tag}.txt"), "w").write("\n".join(lines) + "\n")
 
     def per_kernel(kind):
-        rows = _read_csv(os.path.join(prof, f"{kind}_{workload}", "run_counter_collection.csv"))
+        rows = _read_csv(os.path.join(prof, f"{kind}_{tag}", "run_counter_collection.csv"))
         acc = {}
         for r in rows:
             acc.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
@@ -301,7 +304,7 @@ def summarize_profiles(prof: str, workload: str, command: dict):
              "traffic_bytes_per_launch": int(fk * 1024 * ff + wk * 1024 * fw),
              "commands": {"fetch": command["fetch"], "write": command["write"],
                           "copy_fetch": command["copy_fetch"], "copy_write": command["copy_write"]}}
-        json.dump(d, open(os.path.join(out_dir, f"pmc_{k}_{workload}.json"), "w"), indent=1)
+        json.dump(d, open(os.path.join(out_dir, f"pmc_{k}_{tag}.json"), "w"), indent=1)
     print(json.dumps({"workload": workload, "fetch_scale": ff, "write_scale": fw,
                       "kernels": {k: [fetch.get(k), write.get(k)] for k in ALL_SYMBOLS}}))
 
@@ -711,11 +714,14 @@ def main():
                     help="write profiles/ summaries of the workload from rocprofv3 output in DIR and exit")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, args.workload, profile_commands(args.workload))
+        if not args.kernel_config:
+            sys.exit("--summarize-profiles needs the profiled shape (--kernel-config WGxMPW)")
+        shape = tuple(map(int, args.kernel_config.split("x")))
+        summarize_profiles(args.summarize_profiles, args.workload, shape, profile_commands(args.workload, shape))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(events shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the work is per event, and events shard across GPUs "
+              "with no exchange between them", file=sys.stderr)
         sys.exit(2)
 
     wl = args.workload
