@@ -52,7 +52,7 @@ SERVE_REQUESTS = 10000          # requests per serving run (p99 over 10,000)
 SERVE_SLOTS = 1024              # serving: event slots at most (within the 16 GB budget)
 SERVE_INFLIGHT = 6              # serving: batches on the device at once (no batching delay)
 LLC_BYTES = 256 << 20           # last-level (Infinity) cache: one-event forms rotate more input than this
-SHAPE_TRIAL_LAUNCHES = 64       # batched forms: launches per shape in the throughput trial
+SHAPE_TRIAL_LAUNCHES = 160      # batched forms: launches per shape in the throughput trial
 N_STREAMS = 4                   # streams the batched workloads spread their launches over
 SUB_STEPS = {"batch": 200, "async": 2000, "plain": 2000}   # fixed step counts of the sub-records
 ROOFLINE_LAUNCHES = 32          # one-stream graph-free launches timed for the roofline

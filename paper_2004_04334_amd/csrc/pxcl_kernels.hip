@@ -1647,12 +1647,32 @@ __device__ __forceinline__ void cluster_scratch(const LaunchArgs& a, const Event
         u32 c[UNR];
 #pragma unroll
         for (u32 u = 0; u < UNR; ++u) c[u] = lin[u] != NOPIX ? u32(cl[run_of(s.bm, s.rpre, lin[u])]) : 0u;
+        // when each thread's digis here belong to one cluster (a cluster spanning the
+        // module, as in a serpentine), the thread adds them up first: one wave sum
+        // instead of one per slot
+        u32 c0 = NOPIX;
+        u64 tot = 0;
+        bool one = true;
 #pragma unroll
-        for (u32 u = 0; u < UNR; ++u) {
-            const bool v = lin[u] != NOPIX;
-            wave_add_lds64(acc, c[u], (1ull << 44) | adc[u], v && c[u] < LCAP);
-            wave_add(cch, c[u], adc[u], v && c[u] >= LCAP);
-            wave_add(csz, c[u], 1u, v && c[u] >= LCAP);
+        for (u32 u = 0; u < UNR; ++u)
+            if (lin[u] != NOPIX) {
+                one = one && (c0 == NOPIX || c[u] == c0);
+                c0 = c[u];
+                tot += (1ull << 44) | adc[u];
+            }
+        if (__ballot(!one) == 0ull) {
+            const bool v = c0 != NOPIX;
+            wave_add_lds64(acc, c0, tot, v && c0 < LCAP);
+            wave_add(cch, c0, u32(tot & 0xFFFFFFFFFFFull), v && c0 >= LCAP);
+            wave_add(csz, c0, u32(tot >> 44), v && c0 >= LCAP);
+        } else {
+#pragma unroll
+            for (u32 u = 0; u < UNR; ++u) {
+                const bool v = lin[u] != NOPIX;
+                wave_add_lds64(acc, c[u], (1ull << 44) | adc[u], v && c[u] < LCAP);
+                wave_add(cch, c[u], adc[u], v && c[u] >= LCAP);
+                wave_add(csz, c[u], 1u, v && c[u] >= LCAP);
+            }
         }
     }
     wait_all_mem();
