@@ -363,7 +363,13 @@ bool relaunch_deferred(pxcl_event* ev) {
     hipError_t e = launch_big(a, ev->defer_grid_b, ev->defer_grid_x, ev->stream);
     if (e == hipSuccess) e = launch_compact(a, ev->defer_grid_c, ev->stream);
     if (e == hipSuccess) e = hipEventRecord(ev->done_ev, ev->stream);
-    if (e != hipSuccess) (void)hipGetLastError();
+    if (e != hipSuccess) {
+        // part of the second launch may be queued: let it drain before the event is
+        // finished (with an error) and its slot can be launched again
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(ev->stream);
+        (void)hipGetLastError();
+    }
     return e == hipSuccess;
 }
 
@@ -398,7 +404,11 @@ bool relaunch_deferred(pxcl_batch* b) {
     hipError_t e = launch_big(a, b->defer_grid_b, b->defer_grid_x, b->stream);
     if (e == hipSuccess) e = launch_compact(a, b->defer_grid_c, b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->done_ev, b->stream);
-    if (e != hipSuccess) (void)hipGetLastError();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();            // as for one event: drain what was queued
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipGetLastError();
+    }
     return e == hipSuccess;
 }
 
