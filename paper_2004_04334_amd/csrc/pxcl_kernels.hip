@@ -1896,8 +1896,8 @@ __global__ __launch_bounds__(C_WG) void k_compact(LaunchArgs a) {
             const u32 ncl = fits ? base + T : E.n;
             const u32 err = ctl[CTL_ERR];
             ctl[CTL_ERR] = 0u;
-            ctl[CTL_BIG] = 0u;                             // the big kernels have run
-            ctl[CTL_SCR] = 0u;
+            st_ag(ctl + CTL_BIG, 0u);                      // the big kernels have run (other waves
+            st_ag(ctl + CTL_SCR, 0u);                      // of the event may read them atomically)
             ctl[CTL_NCL] = ncl;
             u32* hs = E.hstat;
             st_sys(&hs[HS_ERR], err);
