@@ -134,7 +134,9 @@ typedef struct {
  * The results are final only when the callback fires: work queued after the acquire
  * on the same stream is not ordered after the second launch, and pxcl_hits_enqueue
  * and pxcl_copy_to_host return PXCL_E_BUSY while the event is in flight.  With
- * PXCL_DIGIS_HITS the hits are complete with the event, as without this flag. */
+ * PXCL_DIGIS_HITS the hits are complete with the event, as without this flag.  If the
+ * second launch cannot be queued, what was queued of it drains first and the callback
+ * then fires with PXCL_E_INTERNAL (the event's results are not valid). */
 #define PXCL_DIGIS_DEFER_BIG 4u
 /* Hits fused into the clustering (Figure 1's GPU chain goes from raw data to hits): the
  * clustering kernels add every kept digi's adc*col and adc*row to exact 64-bit sums of
