@@ -211,18 +211,16 @@ def _sized_modules_event(sizes, n_modules, seed):
                              n_modules=n_modules, seed=seed)
 
 
-@pytest.mark.parametrize("sanitizer", ["address", "thread"])
-def test_big_module_items_on_small_grids(emulator, sanitizer):
+def test_big_module_items_on_small_grids(emulator):
     """Register-mode items of two size classes (above twice the 512-digi capacity of
-    64-thread groups, and between once and twice it) on grids of one workgroup, of
-    fewer workgroups than items and of as many: every item clustered once."""
+    64-thread groups, and between once and twice it) on grids of one workgroup and of
+    fewer workgroups than items: every item clustered once."""
     sizes = [1500, 600, 2000, 700, 40, 1100, 900, 0]
     ev = _sized_modules_event(sizes, 8, 5)
     ev2 = _sized_modules_event(sizes[::-1], 8, 6)
-    for gb in (1, 2, 3, 6):
-        _check(emulator, [ev], 8, wg=64, mpw=1, grids=(2, gb, 3, 2), sanitizer=sanitizer)
-    for gb in (2, 4):                    # 12 items
-        _check(emulator, [ev, ev2], 8, wg=64, mpw=1, grids=(2, gb, 3, 2), header=True, sanitizer=sanitizer)
+    for gb in (1, 4):
+        _check(emulator, [ev], 8, wg=64, mpw=1, grids=(2, gb, 3, 2))
+    _check(emulator, [ev, ev2], 8, wg=64, mpw=1, grids=(2, 5, 3, 2), header=True)     # 12 items
 
 
 
