@@ -695,7 +695,8 @@ def sub_record(r, evs, args, with_oracle=True):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed batch launches of the headline workload")
+    ap.add_argument("--steps", type=int, default=400,
+                    help="timed batch launches of the headline workload (400: a ~55 ms window)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=["all", "stress", "batch", "serve", "async", "plain", "hits", "fusedhits"],
                     default="all")
